@@ -1,0 +1,164 @@
+/*
+ * bst.h -- C ABI of the BST backprojection library for AMD MI355X (gfx950).
+ *
+ * The library computes, slice by slice, the low-complexity backprojection of
+ * parallel-beam sinograms through the backprojection-slice theorem (Section 2,
+ * Eq. 3 of arXiv:1704.08364): for every projection a 1D FFT along the detector
+ * axis (steps P1-P4), an interpolation of the polar spectrum onto a Cartesian
+ * frequency grid (P5) and a 2D inverse FFT with shift and crop (P6-P8).
+ * Plain backprojection (Eq. 2) and filtered backprojection (x = B F y with the
+ * |sigma| ramp, Section 1) are both available; in FBP the ramp and the 1/|sigma|
+ * of Eq. 3 cancel.
+ *
+ * Problem statement (Section 1): a slice's sinogram y(t, theta) holds V
+ * projections at angles theta_j = j*pi/V in [0, pi), each of n detector bins
+ * t_i = (i - n/2)*2/n; the image is N x N with pixel centres
+ * u = ((q - N/2)*2/N, (p - N/2)*2/N) for row p, column q.
+ *
+ * Memory conventions
+ *   - Every large buffer (sinograms, images, workspace) is device memory owned
+ *     by the caller. A plan owns only small device tables (twiddles, tapers,
+ *     weights), freed by bst_destroy.
+ *   - sino: float32 [batch][V][n], detector index fastest, contiguous.
+ *     img : float32 [batch][N][N], row p = u2, column q = u1, contiguous.
+ *   - Input and output buffers must not overlap; the workspace must not
+ *     overlap either.
+ *   - All compute calls are asynchronous on the given HIP stream (hipStream_t
+ *     passed as void*; NULL = the default stream) and return once the kernels
+ *     are enqueued. The plan is immutable after creation and may be shared by
+ *     host threads; concurrent calls on different streams need separate
+ *     workspaces.
+ *
+ * Errors
+ *   - Every function returns a bst_status. Argument errors are detected on the
+ *     host before any device work: nothing is enqueued and outputs are untouched.
+ *   - BST_E_DEVICE reports a failed HIP runtime call (no GPU, launch failure);
+ *     bst_last_error_string() gives the HIP message for the calling thread.
+ */
+#ifndef BST_H_
+#define BST_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bst_plan_s* bst_plan_t;
+
+typedef enum {
+    BST_OK = 0,
+    BST_E_NULL = 1,         /* a required pointer is NULL                         */
+    BST_E_SHAPE = 2,        /* sizes out of range or inconsistent                 */
+    BST_E_ANGLES = 3,       /* angles not finite, not increasing or not in [0,pi) */
+    BST_E_PARAM = 4,        /* unknown filter / taper / padding value             */
+    BST_E_WORKSPACE = 5,    /* workspace smaller than bst_workspace_size          */
+    BST_E_NOMEM = 6,        /* device allocation of the plan tables failed        */
+    BST_E_DEVICE = 7,       /* a HIP runtime call failed                          */
+    BST_E_UNSUPPORTED = 8,  /* valid request this build does not implement        */
+    BST_E_BATCH = 9,        /* batch < 0 or batch > max_batch                     */
+    BST_E_ALIAS = 10        /* input, output or workspace overlap                 */
+} bst_status;
+
+typedef enum {
+    BST_FILTER_NONE = 0,    /* plain backprojection b = B y (Eq. 2, via Eq. 3)      */
+    BST_FILTER_RAMP = 1     /* filtered backprojection x = B F y, |sigma| ramp     */
+} bst_filter;
+
+typedef enum {
+    BST_TAPER_DEAPOD = 0,   /* 1/sinc^2(t dsigma): undoes radial linear interpolation */
+    BST_TAPER_NONE = 1,
+    BST_TAPER_KAISER = 2    /* Kaiser-Bessel I0(beta sqrt(1-t^2)) / I0(beta)          */
+} bst_taper;
+
+typedef struct {
+    int32_t n_det;          /* n: detector bins; power of two in [16, 4096]            */
+    int32_t n_angles;       /* V: projections; [2, 16384]                               */
+    int32_t n_out;          /* N: output side; must equal n_det in this version         */
+    const double* angles;   /* host, V values; NULL = uniform j*pi/V. Non-uniform
+                               angles are validated, then rejected with
+                               BST_E_UNSUPPORTED by the FFT path                        */
+    int32_t pad_radial;     /* P_r in {1,2,4}: FFT length M = P_r*n <= 8192 (P2); 0 -> 2 */
+    int32_t pad_cart;       /* P_c in {1,2,4}: Cartesian grid G = P_c*N <= 8192; 0 -> 2  */
+    int32_t filter;         /* bst_filter                                                */
+    int32_t taper;          /* bst_taper (step P1)                                       */
+    double taper_beta;      /* Kaiser-Bessel beta, >= 0                                  */
+    int32_t max_batch;      /* largest batch a call may pass; >= 1                       */
+    int32_t device;         /* HIP device ordinal the plan's tables live on              */
+} bst_params;
+
+/* Fill *p with the defaults: P_r = P_c = 2, RAMP, de-apodising taper, max_batch 1. */
+void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t n_out);
+
+/* Host-only validation of *p (no device call). */
+bst_status bst_validate(const bst_params* p);
+
+/* Workspace bytes bst_backproject needs for `batch` slices (host only, no plan
+ * needed): polar spectra [batch][V][M/2+2] complex64, per-projection DC terms
+ * [batch][V] float32 and the half-transformed grid [batch][N][G/2] complex64. */
+bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes);
+
+/* Validate *p, then build the plan on p->device: FP64-derived tables (twiddles
+ * of lengths M and G, taper, radial weights K[m] of step P4, angle tables)
+ * uploaded in one small allocation. On error *out is left NULL. */
+bst_status bst_plan(const bst_params* p, bst_plan_t* out);
+
+/* Same as bst_query_workspace for the plan's own parameters. */
+bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes);
+
+/* BST backprojection of `batch` sinograms (Section 2, steps P0-P8):
+ *   BST_FILTER_RAMP: img ~ x = B F y (FBP);  BST_FILTER_NONE: img ~ B y
+ *   (a constant sinogram c gives pi*c).
+ * sino: device float32 [batch][V][n]; img: device float32 [batch][N][N];
+ * ws: device workspace of ws_bytes >= bst_workspace_size(plan, batch).
+ * batch == 0 is a no-op. Three kernels are enqueued on `stream`. */
+bst_status bst_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* As bst_backproject, and records 4 caller-created HIP events (hipEvent_t
+ * passed as void*) on `stream`: before the spectrum kernel, between the
+ * kernels, and after the last one, so per-kernel time is measurable. */
+bst_status bst_backproject_timed(bst_plan_t plan, const float* sino, float* img, int32_t batch,
+                                 void* ws, size_t ws_bytes, void* stream, void* const* events4);
+
+/* Brute-force ("slant-stack") backprojection, Eq. 2 summed directly over the V
+ * angles with linear interpolation along t (Section 2, last paragraph):
+ *   img[p][q] = sum_j w_j * lerp(sino_j, (u.xi_j)/dt + n/2),  zero outside [0,n).
+ * It applies no filter: for FBP pass a ramp-filtered sinogram. Uses the plan's
+ * angles (uniform or not) and weights w_j (pi/V, or half the neighbour gap). */
+bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float* img,
+                                      int32_t batch, void* stream);
+
+/* Fourier-slice forward projector, the exact adjoint of bst_backproject
+ * (P8..P0 transposed). Not implemented in this version: BST_E_UNSUPPORTED
+ * after argument validation. */
+bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t batch,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Diagnostic: run steps P1-P4 only and copy the polar spectrum
+ * (complex64 [batch][V][M/2], Yh_j[m] = dt * K[m] * sum_k z_j[k] e^{-2 pi i k m/M})
+ * and the DC terms (float32 [batch][V], dt * sum_i w_i y_j[i]) to caller buffers. */
+bst_status bst_debug_spectrum(bst_plan_t plan, const float* sino, void* spec, float* dc,
+                              int32_t batch, void* ws, size_t ws_bytes, void* stream);
+
+/* Free the plan's device tables and the plan. NULL is accepted. */
+bst_status bst_destroy(bst_plan_t plan);
+
+/* Static text for a status code. */
+const char* bst_status_string(bst_status s);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char* bst_last_error_string(void);
+
+/* Helpers for callers that have no HIP bindings of their own. */
+bst_status bst_event_create(void** ev);
+bst_status bst_event_destroy(void* ev);
+bst_status bst_event_elapsed_ms(void* start, void* stop, float* ms);
+bst_status bst_stream_synchronize(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BST_H_ */

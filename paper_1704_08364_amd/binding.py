@@ -1,0 +1,276 @@
+"""ctypes binding of libbst.so (include/bst.h) -- argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; torch only
+provides device memory and the current stream. If the library has not been
+built, importing works but every call raises BstNativeMissing: there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbst.so")
+
+BST_OK = 0
+STATUS_NAMES = {
+    0: "BST_OK", 1: "BST_E_NULL", 2: "BST_E_SHAPE", 3: "BST_E_ANGLES", 4: "BST_E_PARAM",
+    5: "BST_E_WORKSPACE", 6: "BST_E_NOMEM", 7: "BST_E_DEVICE", 8: "BST_E_UNSUPPORTED",
+    9: "BST_E_BATCH", 10: "BST_E_ALIAS",
+}
+FILTERS = {"none": 0, "ramp": 1}
+TAPERS = {"deapod": 0, "none": 1, "kaiser": 2, "kb": 2}
+
+# Every symbol include/bst.h declares, with its ctypes signature.
+_P = C.c_void_p
+_I = C.c_int32
+_S = C.c_size_t
+
+
+class bst_params(C.Structure):
+    _fields_ = [
+        ("n_det", C.c_int32), ("n_angles", C.c_int32), ("n_out", C.c_int32),
+        ("angles", C.POINTER(C.c_double)),
+        ("pad_radial", C.c_int32), ("pad_cart", C.c_int32),
+        ("filter", C.c_int32), ("taper", C.c_int32), ("taper_beta", C.c_double),
+        ("max_batch", C.c_int32), ("device", C.c_int32),
+    ]
+
+
+SIGNATURES = {
+    "bst_params_default": (None, [C.POINTER(bst_params), _I, _I, _I]),
+    "bst_validate": (C.c_int, [C.POINTER(bst_params)]),
+    "bst_query_workspace": (C.c_int, [C.POINTER(bst_params), _I, C.POINTER(_S)]),
+    "bst_plan": (C.c_int, [C.POINTER(bst_params), C.POINTER(_P)]),
+    "bst_workspace_size": (C.c_int, [_P, _I, C.POINTER(_S)]),
+    "bst_backproject": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
+    "bst_backproject_timed": (C.c_int, [_P, _P, _P, _I, _P, _S, _P, C.POINTER(_P)]),
+    "bst_backproject_bruteforce": (C.c_int, [_P, _P, _P, _I, _P]),
+    "bst_project": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
+    "bst_debug_spectrum": (C.c_int, [_P, _P, _P, _P, _I, _P, _S, _P]),
+    "bst_destroy": (C.c_int, [_P]),
+    "bst_status_string": (C.c_char_p, [C.c_int]),
+    "bst_last_error_string": (C.c_char_p, []),
+    "bst_event_create": (C.c_int, [C.POINTER(_P)]),
+    "bst_event_destroy": (C.c_int, [_P]),
+    "bst_event_elapsed_ms": (C.c_int, [_P, _P, C.POINTER(C.c_float)]),
+    "bst_stream_synchronize": (C.c_int, [_P]),
+}
+
+
+class BstNativeMissing(RuntimeError):
+    pass
+
+
+class BstError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        name = STATUS_NAMES.get(status, str(status))
+        msg = f"{where}: {name}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises BstNativeMissing when it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise BstNativeMissing(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1704_08364_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != BST_OK:
+        L = lib()
+        detail = L.bst_last_error_string().decode() if status == 7 else L.bst_status_string(status).decode()
+        raise BstError(status, where, detail)
+
+
+def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_radial: int = 2,
+                pad_cart: int = 2, filter: str = "ramp", taper: str = "deapod",
+                taper_beta: float = 8.0, max_batch: int = 1, device: int = 0,
+                angles: Optional[Sequence[float]] = None):
+    """bst_params plus the ctypes array that backs `angles` (keep both alive)."""
+    p = bst_params()
+    lib().bst_params_default(C.byref(p), n_det, n_angles, n_det if n_out is None else n_out)
+    p.pad_radial = pad_radial
+    p.pad_cart = pad_cart
+    p.filter = FILTERS[filter] if isinstance(filter, str) else int(filter)
+    p.taper = TAPERS[taper] if isinstance(taper, str) else int(taper)
+    p.taper_beta = taper_beta
+    p.max_batch = max_batch
+    p.device = device
+    keep = None
+    if angles is not None:
+        arr = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
+        keep = (C.c_double * arr.size)(*arr.tolist())
+        p.angles = C.cast(keep, C.POINTER(C.c_double))
+    return p, keep
+
+
+def query_workspace(params: bst_params, batch: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().bst_query_workspace(C.byref(params), batch, C.byref(out)), "bst_query_workspace")
+    return int(out.value)
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_tensor(t, name: str, dtype, shape_tail):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [..., {shape_tail}]")
+    return t
+
+
+class Event:
+    """A HIP event made by the library (for per-kernel timing)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().bst_event_create(C.byref(h)), "bst_event_create")
+        self.handle = h
+
+    def elapsed_ms(self, stop: "Event") -> float:
+        ms = C.c_float(0.0)
+        _check(lib().bst_event_elapsed_ms(self.handle, stop.handle, C.byref(ms)), "bst_event_elapsed_ms")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().bst_event_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class Plan:
+    """A bst_plan on one device. Sinograms are float32 [B][V][n] (or [V][n]),
+    images float32 [B][N][N]."""
+
+    def __init__(self, n_det: int, n_angles: int, n_out: Optional[int] = None, **kw):
+        self.params, self._angles_keep = make_params(n_det, n_angles, n_out, **kw)
+        self.n = n_det
+        self.V = n_angles
+        self.N = n_det if n_out is None else n_out
+        self.max_batch = self.params.max_batch
+        self.device = self.params.device
+        self.M = (self.params.pad_radial or 2) * n_det
+        self.G = (self.params.pad_cart or 2) * self.N
+        h = C.c_void_p()
+        _check(lib().bst_plan(C.byref(self.params), C.byref(h)), "bst_plan")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().bst_destroy(self.handle), "bst_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self, batch: int) -> int:
+        out = C.c_size_t(0)
+        _check(lib().bst_workspace_size(self.handle, batch, C.byref(out)), "bst_workspace_size")
+        return int(out.value)
+
+    def workspace(self, batch: int):
+        import torch
+        return torch.empty(max(self.workspace_size(batch), 1), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+
+    def _prep(self, sino):
+        import torch
+        sino = _dev_tensor(sino, "sino", torch.float32, (self.V, self.n))
+        batched = sino.dim() == 3
+        s3 = sino if batched else sino.unsqueeze(0)
+        return s3, batched
+
+    def backproject(self, sino, out=None, workspace=None, stream=None, events=None):
+        import torch
+        s3, batched = self._prep(sino)
+        B = s3.shape[0]
+        if out is None:
+            out = torch.empty(B, self.N, self.N, dtype=torch.float32, device=s3.device)
+        _dev_tensor(out, "out", torch.float32, (self.N, self.N))
+        if workspace is None:
+            workspace = self.workspace(B)
+        sp = _stream_ptr(stream)
+        if events is None:
+            st = lib().bst_backproject(self.handle, s3.data_ptr(), out.data_ptr(), B,
+                                       workspace.data_ptr(), workspace.numel(), sp)
+            _check(st, "bst_backproject")
+        else:
+            arr = (C.c_void_p * 4)(*[e.handle for e in events])
+            st = lib().bst_backproject_timed(self.handle, s3.data_ptr(), out.data_ptr(), B,
+                                             workspace.data_ptr(), workspace.numel(), sp, arr)
+            _check(st, "bst_backproject_timed")
+        return out if batched else out[0]
+
+    def bruteforce(self, sino, out=None, stream=None):
+        import torch
+        s3, batched = self._prep(sino)
+        B = s3.shape[0]
+        if out is None:
+            out = torch.empty(B, self.N, self.N, dtype=torch.float32, device=s3.device)
+        _dev_tensor(out, "out", torch.float32, (self.N, self.N))
+        _check(lib().bst_backproject_bruteforce(self.handle, s3.data_ptr(), out.data_ptr(), B,
+                                                _stream_ptr(stream)), "bst_backproject_bruteforce")
+        return out if batched else out[0]
+
+    def debug_spectrum(self, sino, workspace=None, stream=None):
+        """(complex64 [B][V][M/2] polar spectrum dt*K*Y, float32 [B][V] dt*Y[0])."""
+        import torch
+        s3, batched = self._prep(sino)
+        B = s3.shape[0]
+        spec = torch.empty(B, self.V, self.M // 2, dtype=torch.complex64, device=s3.device)
+        dc = torch.empty(B, self.V, dtype=torch.float32, device=s3.device)
+        if workspace is None:
+            workspace = self.workspace(B)
+        _check(lib().bst_debug_spectrum(self.handle, s3.data_ptr(), spec.data_ptr(), dc.data_ptr(), B,
+                                        workspace.data_ptr(), workspace.numel(), _stream_ptr(stream)),
+               "bst_debug_spectrum")
+        return (spec, dc) if batched else (spec[0], dc[0])
+
+    def project(self, img, out=None, workspace=None, stream=None):
+        import torch
+        img = _dev_tensor(img, "img", torch.float32, (self.N, self.N))
+        i3 = img if img.dim() == 3 else img.unsqueeze(0)
+        B = i3.shape[0]
+        if out is None:
+            out = torch.empty(B, self.V, self.n, dtype=torch.float32, device=i3.device)
+        if workspace is None:
+            workspace = self.workspace(B)
+        _check(lib().bst_project(self.handle, i3.data_ptr(), out.data_ptr(), B, workspace.data_ptr(),
+                                 workspace.numel(), _stream_ptr(stream)), "bst_project")
+        return out if img.dim() == 3 else out[0]

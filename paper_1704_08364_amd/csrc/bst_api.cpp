@@ -1,0 +1,496 @@
+// bst_api.cpp -- the C ABI declared in include/bst.h: host-side validation,
+// FP64 plan tables, workspace carving and kernel enqueueing.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bst_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bst_status device_fail(hipError_t e) {
+    g_last_error = hipGetErrorString(e);
+    return BST_E_DEVICE;
+}
+
+bool is_pow2(int32_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int32_t x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+int pad_or_default(int32_t v) { return v == 0 ? 2 : v; }
+
+// I0(x) = sum_k (x^2/4)^k / (k!)^2; terms fall below 1e-17 of the sum within
+// a few dozen steps for the betas a Kaiser-Bessel taper uses.
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+struct Range {
+    uintptr_t lo, hi;
+};
+bool overlap(Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; }
+
+// RAII guard that makes the plan's device current and restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+namespace bst {
+
+WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch) {
+    (void)n;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    WsLayout L{};
+    const size_t B = (size_t)batch;
+    L.polar_off = 0;
+    const size_t polar = B * (size_t)V * (size_t)(M / 2 + 2) * sizeof(float2);
+    L.dc_off = up(L.polar_off + polar);
+    const size_t dc = B * (size_t)V * sizeof(float);
+    L.grid_off = up(L.dc_off + dc);
+    const size_t grid = B * (size_t)N * (size_t)(G / 2) * sizeof(float2);
+    L.total = up(L.grid_off + grid);
+    return L;
+}
+
+}  // namespace bst
+
+extern "C" {
+
+void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t n_out) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->n_det = n_det;
+    p->n_angles = n_angles;
+    p->n_out = n_out;
+    p->angles = nullptr;
+    p->pad_radial = 2;
+    p->pad_cart = 2;
+    p->filter = BST_FILTER_RAMP;
+    p->taper = BST_TAPER_DEAPOD;
+    p->taper_beta = 8.0;
+    p->max_batch = 1;
+    p->device = 0;
+}
+
+bst_status bst_validate(const bst_params* p) {
+    if (!p) return BST_E_NULL;
+    if (!is_pow2(p->n_det) || p->n_det < 16 || p->n_det > 4096) return BST_E_SHAPE;
+    if (p->n_out != p->n_det) return BST_E_SHAPE;
+    if (p->n_angles < 2 || p->n_angles > 16384) return BST_E_SHAPE;
+    const int pr = pad_or_default(p->pad_radial), pc = pad_or_default(p->pad_cart);
+    if (!(pr == 1 || pr == 2 || pr == 4) || !(pc == 1 || pc == 2 || pc == 4)) return BST_E_PARAM;
+    if ((int64_t)pr * p->n_det > 8192 || (int64_t)pc * p->n_out > 8192) return BST_E_SHAPE;
+    if (p->filter != BST_FILTER_NONE && p->filter != BST_FILTER_RAMP) return BST_E_PARAM;
+    if (p->taper != BST_TAPER_DEAPOD && p->taper != BST_TAPER_NONE && p->taper != BST_TAPER_KAISER)
+        return BST_E_PARAM;
+    if (p->taper == BST_TAPER_KAISER && !(std::isfinite(p->taper_beta) && p->taper_beta >= 0.0 &&
+                                          p->taper_beta <= 700.0))
+        return BST_E_PARAM;
+    if (p->max_batch < 1) return BST_E_BATCH;
+    if (p->device < 0) return BST_E_PARAM;
+    if (p->angles) {
+        double prev = -1.0;
+        for (int j = 0; j < p->n_angles; ++j) {
+            const double a = p->angles[j];
+            if (!std::isfinite(a) || a < 0.0 || a >= M_PI || a <= prev) return BST_E_ANGLES;
+            prev = a;
+        }
+    }
+    return BST_OK;
+}
+
+bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes) {
+    if (!bytes) return BST_E_NULL;
+    const bst_status st = bst_validate(p);
+    if (st != BST_OK) return st;
+    if (batch < 0 || batch > p->max_batch) return BST_E_BATCH;
+    const int M = pad_or_default(p->pad_radial) * p->n_det;
+    const int G = pad_or_default(p->pad_cart) * p->n_out;
+    *bytes = batch == 0 ? 0 : bst::workspace_layout(p->n_det, p->n_angles, p->n_out, M, G, batch).total;
+    return BST_OK;
+}
+
+bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
+    if (!out) return BST_E_NULL;
+    *out = nullptr;
+    const bst_status st = bst_validate(p);
+    if (st != BST_OK) return st;
+
+    bst_plan_s* pl = new (std::nothrow) bst_plan_s();
+    if (!pl) return BST_E_NOMEM;
+    pl->prm = *p;
+    pl->prm.angles = nullptr;
+    pl->prm.pad_radial = pad_or_default(p->pad_radial);
+    pl->prm.pad_cart = pad_or_default(p->pad_cart);
+    pl->n = p->n_det;
+    pl->V = p->n_angles;
+    pl->N = p->n_out;
+    pl->M = pl->prm.pad_radial * pl->n;
+    pl->G = pl->prm.pad_cart * pl->N;
+    pl->logM = ilog2(pl->M);
+    pl->logG = ilog2(pl->G);
+    pl->S = pl->M / 2 + 2;
+    pl->uniform = (p->angles == nullptr);
+    pl->dt = 2.0 / pl->n;
+    const double d = 2.0 / pl->N;
+    pl->dk = 1.0 / (pl->G * d);
+    pl->rscale = (double)pl->prm.pad_radial / (double)pl->prm.pad_cart;
+    pl->vpi = (double)pl->V / M_PI;
+    const double kappa = 4.0 * std::asinh(1.0);
+    const double dc_rule = (p->filter == BST_FILTER_RAMP) ? 1.0 : kappa / pl->dk;
+    pl->dc_scale = (float)(dc_rule / pl->V);
+    pl->out_scale = (float)(pl->dk * pl->dk);
+    pl->device = p->device;
+
+    // ---- FP64 tables ----
+    const int n = pl->n, M = pl->M, G = pl->G, V = pl->V;
+    const double dsig = 1.0 / (M * pl->dt);
+    std::vector<float> taper(n), kt(M / 2), bf_w(V);
+    std::vector<float2> twM(M), twG(G);
+    std::vector<double> bf_c(V), bf_s(V), theta(V);
+    for (int i = 0; i < n; ++i) {
+        const double t = (i - n / 2) * pl->dt;
+        double w = 1.0;
+        if (p->taper == BST_TAPER_DEAPOD) {
+            const double x = M_PI * t * dsig;
+            const double sc = (x == 0.0) ? 1.0 : std::sin(x) / x;
+            w = 1.0 / (sc * sc);
+        } else if (p->taper == BST_TAPER_KAISER) {
+            const double arg = 1.0 - t * t;
+            w = bessel_i0(p->taper_beta * std::sqrt(arg > 0.0 ? arg : 0.0)) / bessel_i0(p->taper_beta);
+        }
+        taper[i] = (float)w;
+    }
+    for (int m = 0; m < M / 2; ++m) {
+        double K;
+        if (p->filter == BST_FILTER_RAMP) K = 1.0;
+        else K = (m == 0) ? 0.0 : (M * pl->dt) / (double)m;
+        kt[m] = (float)(pl->dt * K);
+    }
+    for (int k = 0; k < M; ++k) {
+        const double a = -2.0 * M_PI * (double)k / (double)M;
+        twM[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    for (int k = 0; k < G; ++k) {
+        const double a = -2.0 * M_PI * (double)k / (double)G;
+        twG[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    for (int j = 0; j < V; ++j) theta[j] = p->angles ? p->angles[j] : (double)j * M_PI / (double)V;
+    const double ratio = d / pl->dt;
+    for (int j = 0; j < V; ++j) {
+        bf_c[j] = std::cos(theta[j]) * ratio;
+        bf_s[j] = std::sin(theta[j]) * ratio;
+        double w;
+        if (pl->uniform) {
+            w = M_PI / V;
+        } else {
+            const double prev = (j == 0) ? theta[V - 1] - M_PI : theta[j - 1];
+            const double next = (j == V - 1) ? theta[0] + M_PI : theta[j + 1];
+            w = 0.5 * (next - prev);
+        }
+        bf_w[j] = (float)w;
+    }
+
+    // ---- one device block ----
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_taper = off; off = up(off + n * sizeof(float));
+    const size_t o_kt = off;    off = up(off + (M / 2) * sizeof(float));
+    const size_t o_twM = off;   off = up(off + M * sizeof(float2));
+    const size_t o_twG = off;   off = up(off + G * sizeof(float2));
+    const size_t o_c = off;     off = up(off + V * sizeof(double));
+    const size_t o_s = off;     off = up(off + V * sizeof(double));
+    const size_t o_w = off;     off = up(off + V * sizeof(float));
+    const size_t total = off;
+    std::vector<unsigned char> host(total, 0);
+    std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
+    std::memcpy(host.data() + o_kt, kt.data(), (M / 2) * sizeof(float));
+    std::memcpy(host.data() + o_twM, twM.data(), M * sizeof(float2));
+    std::memcpy(host.data() + o_twG, twG.data(), G * sizeof(float2));
+    std::memcpy(host.data() + o_c, bf_c.data(), V * sizeof(double));
+    std::memcpy(host.data() + o_s, bf_s.data(), V * sizeof(double));
+    std::memcpy(host.data() + o_w, bf_w.data(), V * sizeof(float));
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= p->device) {
+        delete pl;
+        if (e == hipSuccess) e = hipErrorInvalidDevice;
+        return device_fail(e);
+    }
+    DeviceGuard guard(p->device);
+    if (guard.err != hipSuccess) {
+        delete pl;
+        return device_fail(guard.err);
+    }
+    e = hipMalloc(&pl->dev_block, total);
+    if (e != hipSuccess) {
+        g_last_error = hipGetErrorString(e);
+        delete pl;
+        return BST_E_NOMEM;
+    }
+    e = hipMemcpy(pl->dev_block, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(pl->dev_block);
+        delete pl;
+        return device_fail(e);
+    }
+    unsigned char* base = static_cast<unsigned char*>(pl->dev_block);
+    pl->taper = reinterpret_cast<float*>(base + o_taper);
+    pl->kt = reinterpret_cast<float*>(base + o_kt);
+    pl->tw_M = reinterpret_cast<float2*>(base + o_twM);
+    pl->tw_G = reinterpret_cast<float2*>(base + o_twG);
+    pl->bf_c = reinterpret_cast<double*>(base + o_c);
+    pl->bf_s = reinterpret_cast<double*>(base + o_s);
+    pl->bf_w = reinterpret_cast<float*>(base + o_w);
+    *out = pl;
+    return BST_OK;
+}
+
+bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
+    if (!plan || !bytes) return BST_E_NULL;
+    if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
+    *bytes = batch == 0 ? 0
+                        : bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch).total;
+    return BST_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const void* out, size_t out_bytes,
+                      int32_t batch, const void* ws, size_t ws_bytes, bool need_ws, size_t* need) {
+    if (!plan) return BST_E_NULL;
+    if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
+    if (batch == 0) return BST_OK;
+    if (!in || !out) return BST_E_NULL;
+    if (need_ws) {
+        *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch).total;
+        if (!ws) return BST_E_NULL;
+        if (ws_bytes < *need) return BST_E_WORKSPACE;
+    }
+    const Range ri{(uintptr_t)in, (uintptr_t)in + in_bytes};
+    const Range ro{(uintptr_t)out, (uintptr_t)out + out_bytes};
+    if (overlap(ri, ro)) return BST_E_ALIAS;
+    if (need_ws) {
+        const Range rw{(uintptr_t)ws, (uintptr_t)ws + *need};
+        if (overlap(rw, ri) || overlap(rw, ro)) return BST_E_ALIAS;
+    }
+    return BST_OK;
+}
+
+bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
+                           size_t ws_bytes, void* stream, void* const* ev, bool spectrum_only,
+                           void* spec_out, float* dc_out) {
+    if (!plan) return BST_E_NULL;
+    const size_t in_bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
+    const size_t out_bytes = (size_t)batch * plan->N * plan->N * sizeof(float);
+    size_t need = 0;
+    bst_status st;
+    if (spectrum_only) {
+        if (batch > 0 && (!spec_out || !dc_out)) return BST_E_NULL;
+        st = check_call(plan, sino, in_bytes, spec_out,
+                        (size_t)batch * plan->V * (plan->M / 2) * sizeof(float2), batch, ws, ws_bytes, true,
+                        &need);
+    } else {
+        st = check_call(plan, sino, in_bytes, img, out_bytes, batch, ws, ws_bytes, true, &need);
+    }
+    if (st != BST_OK || batch == 0) return st;
+    if (!plan->uniform) return BST_E_UNSUPPORTED;
+
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return device_fail(guard.err);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bst::WsLayout L = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch);
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
+    float* dc = reinterpret_cast<float*>(w + L.dc_off);
+    float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
+    hipError_t e;
+
+    if (ev && ev[0]) {
+        e = hipEventRecord(static_cast<hipEvent_t>(ev[0]), s);
+        if (e != hipSuccess) return device_fail(e);
+    }
+    bst::SpecArgs sa{sino, polar, dc, plan->taper, plan->kt, plan->tw_M, plan->n, plan->V, plan->S,
+                     (float)plan->dt};
+    e = bst::launch_spectrum(*plan, sa, batch, s);
+    if (e != hipSuccess) return device_fail(e);
+    if (ev && ev[1]) {
+        e = hipEventRecord(static_cast<hipEvent_t>(ev[1]), s);
+        if (e != hipSuccess) return device_fail(e);
+    }
+    if (spectrum_only) {
+        e = hipMemcpy2DAsync(spec_out, (plan->M / 2) * sizeof(float2), polar, plan->S * sizeof(float2),
+                             (plan->M / 2) * sizeof(float2), (size_t)batch * plan->V, hipMemcpyDeviceToDevice,
+                             s);
+        if (e != hipSuccess) return device_fail(e);
+        e = hipMemcpyAsync(dc_out, dc, (size_t)batch * plan->V * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return device_fail(e);
+        return BST_OK;
+    }
+    bst::GatherArgs ga{};
+    ga.polar = polar;
+    ga.dc = dc;
+    ga.grid = grid;
+    ga.tw = plan->tw_G;
+    ga.V = plan->V;
+    ga.S = plan->S;
+    ga.N = plan->N;
+    ga.Mh = plan->M / 2;
+    ga.batch = batch;
+    ga.slices_per_block = 16;
+    ga.rscale = plan->rscale;
+    ga.vpi = plan->vpi;
+    ga.dc_scale = plan->dc_scale;
+    e = bst::launch_gather_colifft(*plan, ga, s);
+    if (e != hipSuccess) return device_fail(e);
+    if (ev && ev[2]) {
+        e = hipEventRecord(static_cast<hipEvent_t>(ev[2]), s);
+        if (e != hipSuccess) return device_fail(e);
+    }
+    bst::RowArgs ra{grid, img, plan->tw_G, plan->N, plan->out_scale};
+    e = bst::launch_row_c2r(*plan, ra, batch, s);
+    if (e != hipSuccess) return device_fail(e);
+    if (ev && ev[3]) {
+        e = hipEventRecord(static_cast<hipEvent_t>(ev[3]), s);
+        if (e != hipSuccess) return device_fail(e);
+    }
+    return BST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bst_status bst_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
+                           size_t ws_bytes, void* stream) {
+    return run_backproject(plan, sino, img, batch, ws, ws_bytes, stream, nullptr, false, nullptr, nullptr);
+}
+
+bst_status bst_backproject_timed(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
+                                 size_t ws_bytes, void* stream, void* const* events4) {
+    if (!events4) return BST_E_NULL;
+    for (int i = 0; i < 4; ++i)
+        if (!events4[i]) return BST_E_NULL;
+    return run_backproject(plan, sino, img, batch, ws, ws_bytes, stream, events4, false, nullptr, nullptr);
+}
+
+bst_status bst_debug_spectrum(bst_plan_t plan, const float* sino, void* spec, float* dc, int32_t batch,
+                              void* ws, size_t ws_bytes, void* stream) {
+    return run_backproject(plan, sino, nullptr, batch, ws, ws_bytes, stream, nullptr, true, spec, dc);
+}
+
+bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float* img, int32_t batch,
+                                      void* stream) {
+    if (!plan) return BST_E_NULL;
+    const size_t in_bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
+    const size_t out_bytes = (size_t)batch * plan->N * plan->N * sizeof(float);
+    size_t need = 0;
+    const bst_status st = check_call(plan, sino, in_bytes, img, out_bytes, batch, nullptr, 0, false, &need);
+    if (st != BST_OK || batch == 0) return st;
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return device_fail(guard.err);
+    bst::BfArgs a{sino, img, plan->bf_c, plan->bf_s, plan->bf_w, plan->n, plan->V, plan->N};
+    const hipError_t e = bst::launch_bruteforce(*plan, a, batch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_fail(e);
+    return BST_OK;
+}
+
+bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t batch, void* ws,
+                       size_t ws_bytes, void* stream) {
+    (void)stream;
+    if (!plan) return BST_E_NULL;
+    const size_t in_bytes = (size_t)batch * plan->N * plan->N * sizeof(float);
+    const size_t out_bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
+    size_t need = 0;
+    const bst_status st = check_call(plan, img, in_bytes, sino, out_bytes, batch, ws, ws_bytes, true, &need);
+    if (st != BST_OK || batch == 0) return st;
+    return BST_E_UNSUPPORTED;
+}
+
+bst_status bst_destroy(bst_plan_t plan) {
+    if (!plan) return BST_OK;
+    bst_status st = BST_OK;
+    if (plan->dev_block) {
+        DeviceGuard guard(plan->device);
+        const hipError_t e = hipFree(plan->dev_block);
+        if (e != hipSuccess) st = device_fail(e);
+    }
+    delete plan;
+    return st;
+}
+
+const char* bst_status_string(bst_status s) {
+    switch (s) {
+        case BST_OK: return "ok";
+        case BST_E_NULL: return "null pointer argument";
+        case BST_E_SHAPE: return "unsupported or inconsistent sizes";
+        case BST_E_ANGLES: return "angles must be finite, strictly increasing and in [0, pi)";
+        case BST_E_PARAM: return "invalid filter, taper, padding or device value";
+        case BST_E_WORKSPACE: return "workspace smaller than bst_workspace_size";
+        case BST_E_NOMEM: return "device allocation failed";
+        case BST_E_DEVICE: return "HIP runtime error";
+        case BST_E_UNSUPPORTED: return "not supported by this build";
+        case BST_E_BATCH: return "batch out of range [0, max_batch]";
+        case BST_E_ALIAS: return "input, output and workspace must not overlap";
+    }
+    return "unknown status";
+}
+
+const char* bst_last_error_string(void) { return g_last_error.c_str(); }
+
+bst_status bst_event_create(void** ev) {
+    if (!ev) return BST_E_NULL;
+    hipEvent_t e = nullptr;
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return device_fail(r);
+    *ev = e;
+    return BST_OK;
+}
+
+bst_status bst_event_destroy(void* ev) {
+    if (!ev) return BST_OK;
+    const hipError_t r = hipEventDestroy(static_cast<hipEvent_t>(ev));
+    return r == hipSuccess ? BST_OK : device_fail(r);
+}
+
+bst_status bst_event_elapsed_ms(void* start, void* stop, float* ms) {
+    if (!start || !stop || !ms) return BST_E_NULL;
+    const hipError_t r = hipEventElapsedTime(ms, static_cast<hipEvent_t>(start), static_cast<hipEvent_t>(stop));
+    return r == hipSuccess ? BST_OK : device_fail(r);
+}
+
+bst_status bst_stream_synchronize(void* stream) {
+    const hipError_t r = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    return r == hipSuccess ? BST_OK : device_fail(r);
+}
+
+}  // extern "C"

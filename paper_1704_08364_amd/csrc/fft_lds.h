@@ -1,0 +1,176 @@
+// fft_lds.h -- in-register / LDS Stockham FFT used by every BST kernel.
+//
+// A transform of length L = 2^l is held by T = L/16 threads; thread j keeps the
+// 16 values x[j + e*T], e = 0..15, in registers on entry and X[j + e*T] on exit
+// (natural order). Passes are radix 2^(l mod 4) first (if l is not a multiple
+// of 4) and then radix 16. Each pass computes its butterflies in registers;
+// between passes the values go through LDS once (write, barrier, read, barrier).
+// The Stockham auto-sort indexing (Govindaraju et al., SC'08) keeps every pass
+// in natural order, so no bit reversal is needed.
+//
+// Inter-pass twiddles come from a table tw[k] = exp(-2 pi i k / L) computed in
+// FP64 on the host and rounded to FP32, so no twiddle carries more than half
+// an ulp of error. The inverse direction conjugates them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bst {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// multiply by exp(DIR * i * pi / 2): -i for the forward (DIR = -1), +i for the inverse
+template <int DIR>
+__device__ __forceinline__ float2 rot90(float2 a) {
+    return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+// multiply by c + DIR * i * s
+template <int DIR>
+__device__ __forceinline__ float2 cmulc(float2 a, float c, float s) {
+    const float sd = DIR < 0 ? -s : s;
+    return make_float2(fmaf(a.x, c, -a.y * sd), fmaf(a.x, sd, a.y * c));
+}
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+constexpr float kC1 = 0.92387953251128675613f;  // cos(pi/8)
+constexpr float kS1 = 0.38268343236508977173f;  // sin(pi/8)
+constexpr float kH = 0.70710678118654752440f;   // cos(pi/4)
+
+template <int DIR>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+    const float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+    const float2 t0 = cadd(x0, x2), t1 = csub(x0, x2);
+    const float2 t2 = cadd(x1, x3), t3 = rot90<DIR>(csub(x1, x3));
+    x0 = cadd(t0, t2);
+    x2 = csub(t0, t2);
+    x1 = cadd(t1, t3);
+    x3 = csub(t1, t3);
+}
+
+// natural order in, natural order out
+template <int DIR>
+__device__ __forceinline__ void dft8(float2* v) {
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    o1 = cmulc<DIR>(o1, kH, kH);
+    o2 = rot90<DIR>(o2);
+    o3 = cmulc<DIR>(o3, -kH, kH);
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft16(float2* v) {
+    float2 e[8], o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { e[i] = v[2 * i]; o[i] = v[2 * i + 1]; }
+    dft8<DIR>(e);
+    dft8<DIR>(o);
+    o[1] = cmulc<DIR>(o[1], kC1, kS1);
+    o[2] = cmulc<DIR>(o[2], kH, kH);
+    o[3] = cmulc<DIR>(o[3], kS1, kC1);
+    o[4] = rot90<DIR>(o[4]);
+    o[5] = cmulc<DIR>(o[5], -kS1, kC1);
+    o[6] = cmulc<DIR>(o[6], -kH, kH);
+    o[7] = cmulc<DIR>(o[7], -kC1, kS1);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { v[k] = cadd(e[k], o[k]); v[k + 8] = csub(e[k], o[k]); }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v) {
+    if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+    else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8<DIR>(v);
+    else dft16<DIR>(v);
+}
+
+// One Stockham pass of radix R over sub-transforms of size NS (product of the
+// earlier radices). Butterfly jj (= j + k*T) reads x[jj + r*L/R] -- which is
+// v[k + r*(16/R)] in this thread's registers -- twiddles it by
+// w^((jj mod NS) * r) with w = exp(DIR 2 pi i / (NS R)), transforms, and
+// writes output r to position (jj / NS) * NS * R + (jj mod NS) + r * NS.
+template <int L, int DIR, int R, int NS>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[16], float2* lds, int j, const float2* __restrict__ tw) {
+    constexpr int T = L / 16;
+    constexpr int BPT = 16 / R;
+    constexpr bool LAST = (NS * R == L);
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int jj = j + k * T;
+        const int m = jj & (NS - 1);
+        float2 x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = v[k + r * BPT];
+        if constexpr (NS > 1) {
+            constexpr int STEP = L / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[m * r * STEP];
+                if constexpr (DIR > 0) w.y = -w.y;
+                x[r] = cmul(x[r], w);
+            }
+        }
+        dft<R, DIR>(x);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[k + r * BPT] = x[r];
+        } else {
+            const int base = (jj / NS) * NS * R + m;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = x[r];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = lds[lds_pad(j + e * T)];
+        __syncthreads();
+    }
+}
+
+template <int L, int DIR, int NS>
+__device__ __forceinline__ void radix16_passes(float2 (&v)[16], float2* lds, int j, const float2* tw) {
+    if constexpr (NS < L) {
+        stockham_pass<L, DIR, 16, NS>(v, lds, j, tw);
+        radix16_passes<L, DIR, NS * 16>(v, lds, j, tw);
+    }
+}
+
+// Full transform. Requires every thread of the block to call it (barriers);
+// `lds` must hold lds_pad(L) float2 for this transform and not be read by
+// anyone else meanwhile. Ends with a barrier if any LDS exchange happened.
+template <int LOGL, int DIR>
+__device__ __forceinline__ void fft(float2 (&v)[16], float2* lds, int j, const float2* __restrict__ tw) {
+    constexpr int L = 1 << LOGL;
+    constexpr int REM = LOGL % 4;
+    if constexpr (REM != 0) {
+        stockham_pass<L, DIR, (1 << REM), 1>(v, lds, j, tw);
+        radix16_passes<L, DIR, (1 << REM)>(v, lds, j, tw);
+    } else {
+        radix16_passes<L, DIR, 1>(v, lds, j, tw);
+    }
+}
+
+template <int LOGL>
+struct FftShape {
+    static constexpr int L = 1 << LOGL;
+    static constexpr int T = L / 16;                       // threads per transform
+    static constexpr int LDS = L + L / 16;                 // padded float2 per transform
+};
+
+}  // namespace bst

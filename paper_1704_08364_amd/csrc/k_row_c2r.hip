@@ -1,0 +1,99 @@
+// k_row_c2r.hip -- second half of step P6 (inverse DFT along k_x, complex to
+// real) with P7/P8 (shift to the centre and crop to N columns) and the dk^2
+// scale of the inverse Fourier integral (Section 2).
+//
+// Two output rows p, p+1 share one complex inverse FFT of length G:
+//   W[k] = X_p[k] + i X_{p+1}[k] with the Hermitian extension
+//   X[G-k] = conj X[k]; then x_p = Re w and x_{p+1} = Im w.
+// As in the usual C2R convention the imaginary part of the k = 0 sample is
+// ignored, and the k = G/2 sample is zero (no polar data reaches |k_x| = G/2).
+// A block takes up to 8 rows, i.e. one contiguous [G/2][8] tile of the grid
+// written by the column kernel.
+#include "bst_internal.h"
+#include "fft_lds.h"
+
+namespace bst {
+
+template <int LOGG>
+struct RowCfg {
+    static constexpr int G = 1 << LOGG;
+    static constexpr int T = G / 16;
+    static constexpr int F = G <= 4096 ? 4 : (G == 8192 ? 2 : 1);  // row pairs per block
+    static constexpr int WG = F * T;
+};
+
+template <int LOGG>
+__global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
+    using C = RowCfg<LOGG>;
+    constexpr int G = C::G, T = C::T;
+    __shared__ float2 lds[C::F * FftShape<LOGG>::LDS];
+    const int fid = threadIdx.x / T;
+    const int j = threadIdx.x - fid * T;
+    float2* my = lds + fid * FftShape<LOGG>::LDS;
+    const int row0 = blockIdx.x * (2 * C::F) + 2 * fid;
+    const int s = blockIdx.y;
+    const int sub = row0 & 7;
+    const float4* tile = reinterpret_cast<const float4*>(
+        a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * (G / 2));
+
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int k = j + e * T;
+        float2 x0, x1;
+        if (k < G / 2) {
+            const float4 q = tile[k * 4 + (sub >> 1)];
+            x0 = make_float2(q.x, k == 0 ? 0.f : q.y);
+            x1 = make_float2(q.z, k == 0 ? 0.f : q.w);
+        } else if (k == G / 2) {
+            x0 = make_float2(0.f, 0.f);
+            x1 = x0;
+        } else {
+            const float4 q = tile[(G - k) * 4 + (sub >> 1)];
+            x0 = make_float2(q.x, -q.y);
+            x1 = make_float2(q.z, -q.w);
+        }
+        v[e] = make_float2(x0.x - x1.y, x0.y + x1.x);
+    }
+
+    fft<LOGG, +1>(v, my, j, a.tw);
+
+    float* o0 = a.img + ((size_t)s * a.N + row0) * a.N;
+    float* o1 = o0 + a.N;
+    const int half_n = a.N >> 1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int x = j + e * T;
+        const int q = (x + half_n) & (G - 1);
+        if (q < a.N) {
+            o0[q] = v[e].x * a.scale;
+            o1[q] = v[e].y * a.scale;
+        }
+    }
+}
+
+template <int LOGG>
+static hipError_t launch_row_t(const RowArgs& a, int batch, hipStream_t st) {
+    using C = RowCfg<LOGG>;
+    dim3 grid(a.N / (2 * C::F), batch);
+    hipLaunchKernelGGL(k_row_c2r<LOGG>, grid, dim3(C::WG), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipStream_t st) {
+    switch (p.logG) {
+        case 4: return launch_row_t<4>(a, batch, st);
+        case 5: return launch_row_t<5>(a, batch, st);
+        case 6: return launch_row_t<6>(a, batch, st);
+        case 7: return launch_row_t<7>(a, batch, st);
+        case 8: return launch_row_t<8>(a, batch, st);
+        case 9: return launch_row_t<9>(a, batch, st);
+        case 10: return launch_row_t<10>(a, batch, st);
+        case 11: return launch_row_t<11>(a, batch, st);
+        case 12: return launch_row_t<12>(a, batch, st);
+        case 13: return launch_row_t<13>(a, batch, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bst

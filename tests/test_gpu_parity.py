@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (stated in the tests): FP32 end-to-end BST within relative L2 1e-5 of the
+FP64 oracle on the same FP32 input bytes; the polar spectrum stage within 1e-6;
+brute force within 1e-5. Sizes span several FFT lengths, odd and ragged
+angle counts, every padding combination, both filters and all tapers, plus
+the full 64 x 2048 x 2048 batch in the launch configuration the benchmark
+times (two of its slices checked in full against the oracle).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import bruteforce as obf
+from oracle import bst as obst
+from oracle import ramp as oramp
+from oracle.geometry import Geometry
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1704_08364_amd as mod
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mod.lib()  # fails loudly when libbst.so is missing
+    return mod
+
+
+def _sinos(B, V, n, seed, kind="mixed"):
+    """[B][V][n] float32 on the GPU: ellipse phantoms with noise, plus random slices."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    out = synth.batch_sinograms(B, n, V, seed, device=DEV)
+    if kind == "mixed" and B > 1:
+        out[B - 1] = torch.randn(V, n, generator=g).to(DEV)
+    return out
+
+
+CASES = [
+    # N, V, filter, P_r, P_c, taper
+    (16, 10, "ramp", 2, 2, "deapod"),
+    (16, 7, "none", 1, 1, "none"),
+    (32, 24, "none", 2, 2, "deapod"),
+    (32, 33, "ramp", 4, 1, "kaiser"),
+    (64, 50, "ramp", 1, 2, "deapod"),
+    (64, 33, "none", 2, 1, "deapod"),
+    (128, 96, "ramp", 4, 2, "none"),
+    (128, 128, "ramp", 2, 4, "deapod"),
+    (256, 301, "none", 2, 2, "kaiser"),
+    (512, 400, "ramp", 2, 2, "deapod"),
+    (1024, 256, "ramp", 2, 2, "deapod"),
+]
+
+
+@pytest.mark.parametrize("N,V,filt,P_r,P_c,taper", CASES)
+def test_spectrum_stage(P, N, V, filt, P_r, P_c, taper):
+    _say(f"[spectrum] N={N} V={V} {filt} Pr={P_r} Pc={P_c} {taper}")
+    B = 3
+    plan = P.Plan(N, V, pad_radial=P_r, pad_cart=P_c, filter=filt, taper=taper, max_batch=B)
+    sino = _sinos(B, V, N, 1000 + N + V)
+    spec, dc = plan.debug_spectrum(sino)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    prm = obst.Params(P_r, P_c, filt, taper if taper != "kaiser" else "kb", 8.0)
+    M = P_r * N
+    for b in range(B):
+        Yh, Y0 = obst.spectrum(sino[b].double().cpu().numpy(), geom, prm)
+        got = spec[b].cpu().numpy().astype(np.complex128)
+        assert rel_l2(got, Yh[:, :M // 2]) <= 1e-6
+        assert rel_l2(dc[b].cpu().numpy(), Y0) <= 1e-6
+
+
+@pytest.mark.parametrize("N,V,filt,P_r,P_c,taper", CASES)
+def test_backproject_matches_oracle(P, N, V, filt, P_r, P_c, taper):
+    _say(f"[backproject] N={N} V={V} {filt} Pr={P_r} Pc={P_c} {taper}")
+    B = 3
+    plan = P.Plan(N, V, pad_radial=P_r, pad_cart=P_c, filter=filt, taper=taper, max_batch=B)
+    sino = _sinos(B, V, N, 2000 + N + V)
+    img = plan.backproject(sino)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    prm = obst.Params(P_r, P_c, filt, taper if taper != "kaiser" else "kb", 8.0)
+    for b in range(B):
+        ref = obst.backproject(sino[b].double().cpu().numpy(), geom, prm)
+        err = rel_l2(img[b].cpu().numpy(), ref)
+        _say(f"   slice {b}: rel-L2 {err:.2e}")
+        assert err <= 1e-5
+
+
+def test_config1_head_phantom(P):
+    """256 angles x 256 bins, 10-ellipse head phantom with 1% noise, both filters."""
+    sino, g, _ = synth.config1_sinogram(device=DEV)
+    geom = Geometry(256, 256, 256)
+    y64 = sino.double().cpu().numpy()
+    for filt in ("ramp", "none"):
+        _say(f"[config1] {filt}")
+        plan = P.Plan(256, 256, filter=filt)
+        img = plan.backproject(sino)
+        ref = obst.backproject(y64, geom, obst.Params(2, 2, filt))
+        assert rel_l2(img.cpu().numpy(), ref) <= 1e-5
+
+
+def test_full_batch_2048(P):
+    """64 slices of 2048 angles x 2048 bins: the batch and plan the benchmark
+    times; slices 0 and 63 are compared in full with the oracle, and a sample
+    of brute-force pixels of slice 7 with the oracle's B_d."""
+    B, N, V = 64, 2048, 2048
+    _say("[full 2048] generating")
+    sino = synth.batch_sinograms(B, N, V, seed=170408366, device=DEV)
+    plan = P.Plan(N, V, max_batch=B)
+    ws = plan.workspace(B)
+    img = torch.empty(B, N, N, dtype=torch.float32, device=DEV)
+    plan.backproject(sino, out=img, workspace=ws)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    for b in (0, B - 1):
+        _say(f"[full 2048] oracle slice {b}")
+        ref = obst.backproject(sino[b].double().cpu().numpy(), geom, obst.Params())
+        err = rel_l2(img[b].cpu().numpy(), ref)
+        _say(f"   rel-L2 {err:.2e}")
+        assert err <= 1e-5
+    _say("[full 2048] brute force")
+    bf = plan.bruteforce(sino[:8])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    rows = rng.integers(0, N, 3000)
+    cols = rng.integers(0, N, 3000)
+    ref = obf.backproject_pixels(sino[7].double().cpu().numpy(), geom, rows, cols)
+    got = bf[7].cpu().numpy()[rows, cols]
+    assert rel_l2(got, ref) <= 1e-5
+
+
+def test_largest_transform_4096(P):
+    N, V = 4096, 48  # M = G = 8192: the row kernel's two-pairs-per-block path
+    _say("[4096]")
+    plan = P.Plan(N, V, max_batch=1)
+    sino = _sinos(1, V, N, 4096, kind="plain")
+    img = plan.backproject(sino)
+    torch.cuda.synchronize()
+    ref = obst.backproject(sino[0].double().cpu().numpy(), Geometry(N, V, N), obst.Params())
+    assert rel_l2(img[0].cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("N,V,angles", [(16, 12, None), (64, 45, None), (256, 256, None),
+                                        (128, 90, "random"), (96 * 0 + 32, 17, "random")])
+def test_bruteforce_matches_oracle(P, N, V, angles):
+    _say(f"[bruteforce] N={N} V={V} {angles}")
+    rng = np.random.default_rng(N + V)
+    th = None if angles is None else np.sort(rng.uniform(0, np.pi, V))
+    plan = P.Plan(N, V, angles=th, max_batch=2)
+    sino = _sinos(2, V, N, 3000 + N + V)
+    img = plan.bruteforce(sino)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N, angles=th)
+    for b in range(2):
+        ref = obf.backproject(sino[b].double().cpu().numpy(), geom)
+        assert rel_l2(img[b].cpu().numpy(), ref) <= 1e-5
+
+
+def test_rotation_covariance_on_gpu(P):
+    N, V = 256, 200
+    plan = P.Plan(N, V, max_batch=2)
+    y = _sinos(1, V, N, 77, kind="plain")[0].clone()
+    y[:, 0] = 0.0
+    h = V // 2
+    yr = torch.zeros_like(y)
+    yr[h:] = y[:h]
+    yr[:h, 1:] = torch.flip(y[h:, 1:], dims=[1])
+    out = plan.backproject(torch.stack([y, yr]))
+    torch.cuda.synchronize()
+    b, br = out[0].cpu().numpy(), out[1].cpu().numpy()
+    expect = b[N - np.arange(1, N)].T
+    assert rel_l2(br[:, 1:], expect) <= 1e-5
+
+
+def test_deterministic_reruns(P):
+    N, V, B = 512, 300, 4
+    plan = P.Plan(N, V, max_batch=B)
+    sino = _sinos(B, V, N, 99)
+    ws = plan.workspace(B)
+    a = plan.backproject(sino, workspace=ws).clone()
+    b = plan.backproject(sino, workspace=ws).clone()
+    c = plan.bruteforce(sino).clone()
+    d = plan.bruteforce(sino).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(c, d)
+
+
+def test_batch_slices_are_independent(P):
+    """Slice b of a batch equals the same sinogram run alone (ragged last chunk of 16)."""
+    N, V, B = 128, 100, 19
+    plan = P.Plan(N, V, max_batch=B)
+    sino = _sinos(B, V, N, 5)
+    full = plan.backproject(sino)
+    one = plan.backproject(sino[B - 1:B].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(full[B - 1], one[0])
+
+
+def test_gap_against_bruteforce_fbp(P):
+    """Discretisation gap of the method (not a parity bar): BST FBP against
+    brute-force FBP with the band-limited ramp, noiseless phantom, disk
+    r <= (N/2 - 2) d."""
+    N = 256
+    sg = synth.Geometry(N, N, N)
+    ell = synth.head_phantom(5, 10)
+    y = synth.ellipse_sinogram(sg, ell).numpy()
+    geom = Geometry(N, N, N)
+    h = oramp.filter_fft(y, geom.dt)
+    plan = P.Plan(N, N, max_batch=1)
+    bst_img = plan.backproject(torch.tensor(y, dtype=torch.float32, device=DEV))
+    bf_img = plan.bruteforce(torch.tensor(h, dtype=torch.float32, device=DEV))
+    torch.cuda.synchronize()
+    u = geom.u()
+    disk = np.hypot(u[None, :], u[:, None]) <= (N / 2 - 2) * geom.d
+    gap = rel_l2(bst_img.cpu().numpy()[disk], bf_img.cpu().numpy()[disk])
+    _say(f"[gap] N={N}: {gap:.4f}")
+    assert gap <= 3e-2
+
+
+def test_edge_cases(P):
+    N, V = 64, 40
+    plan = P.Plan(N, V, max_batch=4)
+    sino = _sinos(4, V, N, 11)
+    out = torch.full((4, N, N), 7.0, device=DEV)
+    ws = plan.workspace(4)
+    # batch 0: nothing enqueued, output untouched
+    st = P.lib().bst_backproject(plan.handle, sino.data_ptr(), out.data_ptr(), 0, ws.data_ptr(),
+                                 ws.numel(), None)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+    # workspace too small
+    with pytest.raises(P.BstError) as e:
+        plan.backproject(sino, out=out, workspace=ws[: ws.numel() // 2])
+    assert e.value.status == 5
+    assert torch.all(out == 7.0)
+    # input/output overlap
+    with pytest.raises(P.BstError) as e:
+        flat = torch.empty(4 * V * N + 4 * N * N, device=DEV)
+        st = P.lib().bst_backproject(plan.handle, flat.data_ptr(), flat.data_ptr() + 4 * 16,
+                                     4, ws.data_ptr(), ws.numel(), None)
+        P.binding._check(st, "bst_backproject")
+    assert e.value.status == 10
+    # batch above max
+    big = _sinos(5, V, N, 12)
+    with pytest.raises(P.BstError) as e:
+        plan.backproject(big)
+    assert e.value.status == 9
+    # the adjoint is declared but not implemented in this version
+    with pytest.raises(P.BstError) as e:
+        plan.project(torch.zeros(1, N, N, device=DEV))
+    assert e.value.status == 8
+    # non-uniform angles: FFT path refuses, brute force accepts
+    th = np.sort(np.random.default_rng(1).uniform(0, np.pi, V))
+    p2 = P.Plan(N, V, angles=th, max_batch=1)
+    with pytest.raises(P.BstError) as e:
+        p2.backproject(sino[0])
+    assert e.value.status == 8
+    p2.bruteforce(sino[0])
+    torch.cuda.synchronize()
+    assert math.isfinite(float(out.sum()))

@@ -174,6 +174,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::vector<float> taper(n), kt(M / 2), bf_w(V);
     std::vector<float2> twM(M), twG(G);
     std::vector<double> bf_c(V), bf_s(V), theta(V);
+    std::vector<double2> ang(V);
     for (int i = 0; i < n; ++i) {
         const double t = (i - n / 2) * pl->dt;
         double w = 1.0;
@@ -203,6 +204,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     }
     for (int j = 0; j < V; ++j) theta[j] = p->angles ? p->angles[j] : (double)j * M_PI / (double)V;
     const double ratio = d / pl->dt;
+    for (int j = 0; j < V; ++j) ang[j] = make_double2(std::cos(theta[j]), std::sin(theta[j]));
     for (int j = 0; j < V; ++j) {
         bf_c[j] = std::cos(theta[j]) * ratio;
         bf_s[j] = std::sin(theta[j]) * ratio;
@@ -227,6 +229,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     const size_t o_c = off;     off = up(off + V * sizeof(double));
     const size_t o_s = off;     off = up(off + V * sizeof(double));
     const size_t o_w = off;     off = up(off + V * sizeof(float));
+    const size_t o_ang = off;   off = up(off + V * sizeof(double2));
     const size_t total = off;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
@@ -236,6 +239,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::memcpy(host.data() + o_c, bf_c.data(), V * sizeof(double));
     std::memcpy(host.data() + o_s, bf_s.data(), V * sizeof(double));
     std::memcpy(host.data() + o_w, bf_w.data(), V * sizeof(float));
+    std::memcpy(host.data() + o_ang, ang.data(), V * sizeof(double2));
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -269,6 +273,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->bf_c = reinterpret_cast<double*>(base + o_c);
     pl->bf_s = reinterpret_cast<double*>(base + o_s);
     pl->bf_w = reinterpret_cast<float*>(base + o_w);
+    pl->ang = reinterpret_cast<double2*>(base + o_ang);
     *out = pl;
     return BST_OK;
 }
@@ -368,7 +373,8 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.batch = batch;
     ga.slices_per_block = 16;
     ga.rscale = plan->rscale;
-    ga.vpi = plan->vpi;
+    ga.vpi_f = (float)plan->vpi;
+    ga.ang = plan->ang;
     ga.dc_scale = plan->dc_scale;
     e = bst::launch_gather_colifft(*plan, ga, s);
     if (e != hipSuccess) return device_fail(e);

@@ -27,6 +27,7 @@ struct bst_plan_s {
     double* bf_c;        // [V]          cos(theta_j) * d/dt   (brute force)
     double* bf_s;        // [V]          sin(theta_j) * d/dt
     float* bf_w;         // [V]          w_j
+    double2* ang;        // [V]          (cos theta_j, sin theta_j), gather angle residuals
 };
 
 namespace bst {
@@ -54,8 +55,10 @@ struct GatherArgs {
     const float2* tw;
     int V, S, N, Mh;
     int batch, slices_per_block;
-    double rscale, vpi;
+    double rscale;
+    float vpi_f;             // V / pi
     float dc_scale;
+    const double2* ang;      // [V] (cos theta_j, sin theta_j)
 };
 
 struct RowArgs {

@@ -8,9 +8,11 @@
 // The Stockham auto-sort indexing (Govindaraju et al., SC'08) keeps every pass
 // in natural order, so no bit reversal is needed.
 //
-// Inter-pass twiddles come from a table tw[k] = exp(-2 pi i k / L) computed in
-// FP64 on the host and rounded to FP32, so no twiddle carries more than half
-// an ulp of error. The inverse direction conjugates them.
+// Inter-pass twiddles: one value w = tw[(jj mod NS) * L/(NS R)] per butterfly
+// from a table tw[k] = exp(-2 pi i k / L) computed in FP64 on the host and
+// rounded to FP32; the other powers w^r are products of its squarings (at most
+// six roundings deep), which replaces R-1 scattered table reads by one
+// coalesced read. The inverse direction conjugates them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -117,11 +119,25 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[16], float2* lds, int 
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = v[k + r * BPT];
         if constexpr (NS > 1) {
+            // one table anchor w = tw[m * STEP] per butterfly; w^r is the product
+            // of the anchors' binary powers w, w^2, w^4, w^8 picked by the bits
+            // of r (at most three products after at most three squarings), formed
+            // just before use so that few twiddles are live at once
             constexpr int STEP = L / (NS * R);
+            float2 w1 = tw[m * STEP];
+            if constexpr (DIR > 0) w1.y = -w1.y;
+            float2 w2 = w1, w4 = w1, w8 = w1;
+            if constexpr (R >= 4) w2 = cmul(w1, w1);
+            if constexpr (R >= 8) w4 = cmul(w2, w2);
+            if constexpr (R >= 16) w8 = cmul(w4, w4);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[m * r * STEP];
-                if constexpr (DIR > 0) w.y = -w.y;
+                float2 w;
+                bool first = true;
+                if (r & 1) { w = w1; first = false; }
+                if (r & 2) { w = first ? w2 : cmul(w, w2); first = false; }
+                if (r & 4) { w = first ? w4 : cmul(w, w4); first = false; }
+                if (r & 8) { w = first ? w8 : cmul(w, w8); }
                 x[r] = cmul(x[r], w);
             }
         }
@@ -164,6 +180,18 @@ __device__ __forceinline__ void fft(float2 (&v)[16], float2* lds, int j, const f
     } else {
         radix16_passes<L, DIR, 1>(v, lds, j, tw);
     }
+}
+
+// Blocks of a 1D grid are dispatched round-robin over the 8 XCDs of an
+// MI355X (block b runs on XCD b mod 8), each with its own L2. This maps the
+// hardware block index to a logical one so that every XCD receives one
+// contiguous range of logical blocks, and neighbouring logical blocks -- which
+// read neighbouring data -- share an L2.
+__device__ __forceinline__ int xcd_contiguous(int bid, int nblocks) {
+    constexpr int kXcd = 8;
+    const int per = nblocks / kXcd, rem = nblocks % kXcd;
+    const int x = bid % kXcd, k = bid / kXcd;
+    return x * per + (x < rem ? x : rem) + k;
 }
 
 template <int LOGL>

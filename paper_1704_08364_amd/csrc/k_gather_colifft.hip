@@ -2,17 +2,26 @@
 // frequency domain, Section 2) fused with the first half of P6 (the inverse
 // DFT along k_y) and the row part of P7/P8 (shift and crop).
 //
-// A block owns one Cartesian column k_x = a*dk (a in [0, G/2)) -- or several
-// for small G -- and all G rows k_y = b*dk, b in FFT order. Each thread keeps
-// the interpolation coordinates of its 16 points in registers: they are
-// computed once in FP64 (radius index r = |(a,b)| P_r/P_c, angle index
-// q = theta V/pi), which keeps the fractional weights exact to FP32 rounding
-// even where r and q are near 3000, and reused for every slice the block
-// processes. Per slice the column is gathered straight into the registers
-// the FFT starts from, inverse-transformed along b, and only the N rows that
-// survive the crop are written, to a grid laid out [N/8][G/2][8] (complex) so
-// each group of 8 output rows of one column is a 64-byte segment and the row
-// kernel reads its 8-row tile contiguously.
+// A block owns F neighbouring Cartesian columns k_x = a*dk (a in [0, G/2))
+// and all G rows k_y = b*dk of each, b in FFT order; thread t works on column
+// t mod F, so the lanes of a wave cover F neighbouring columns times 64/F
+// neighbouring rows, and their polar reads fall on few cache lines (the same
+// angle row, consecutive radii). Columns go to XCDs in contiguous ranges so
+// neighbouring columns share an L2.
+//
+// Each thread keeps the interpolation coordinates of its 16 points in three
+// registers each and reuses them for every slice of its chunk. They are exact
+// to FP32 rounding although radius and angle indices reach a few thousand:
+//   radius index r = |(a,b)| P_r/P_c from an FP64 square root;
+//   angle index: an FP32 atan2 picks the interval [theta_j0, theta_j0+1), then
+//   the offset inside it is atan2(cross, dot) of the point direction against
+//   (cos theta_j0, sin theta_j0) from an FP64 table (cross and dot in FP64,
+//   the small angle in FP32), so the fraction f carries no cancellation.
+// Per slice, the column is gathered straight into the registers the FFT
+// starts from, inverse-transformed along b, and only the N rows that survive
+// the crop are written, to a grid laid out [N/8][G/2][8] (complex): the 8 rows
+// of a tile and neighbouring columns form contiguous runs, and the row kernel
+// reads each 8-row tile contiguously.
 //
 // Gather rules (bilinear in (r, q)):
 //   b >= 0: theta = atan2(b, a), sample as stored; b < 0: theta + pi, conjugate
@@ -25,17 +34,29 @@
 
 namespace bst {
 
-constexpr int kZero = -1;
-constexpr int kDc = -2;
-constexpr int kConj = 1 << 30;
-constexpr int kOffMask = kConj - 1;
+// point code: bits 0-13 j0, 14-26 m0, 27 conjugate the j0 samples, 28 conjugate the j1 samples
+constexpr unsigned kCodeZero = 0xFFFFFFFFu;
+constexpr unsigned kCodeDc = 0xFFFFFFFEu;
+constexpr unsigned kConj0 = 1u << 27;
+constexpr unsigned kConj1 = 1u << 28;
+constexpr unsigned kWrapShift = 29;  // bit 29: the j1 neighbour wraps to angle 0
+
+// threads per block of the gather kernel (the columns per block follow from it)
+#ifndef BST_GATHER_THREADS
+#define BST_GATHER_THREADS 512
+#endif
 
 template <int LOGG>
 struct GatherCfg {
     static constexpr int G = 1 << LOGG;
     static constexpr int T = G / 16;
-    static constexpr int F = T >= 256 ? 1 : 256 / T;   // columns per block
+    static constexpr int MAXT = BST_GATHER_THREADS > T ? BST_GATHER_THREADS : T;
+    static constexpr int F0 = 16384 / G > G / 2 ? G / 2 : 16384 / G;
+    static constexpr int F = F0 > 1 ? (T * F0 > MAXT ? MAXT / T : F0) : 1;  // columns per block
     static constexpr int WG = F * T;
+    // transform stride in LDS: padded length plus 8 float2, so that F regions
+    // start 16 banks apart and lanes of different columns do not collide
+    static constexpr int STRIDE = FftShape<LOGG>::LDS + 8;
 };
 
 template <int WG>
@@ -54,58 +75,94 @@ __device__ float block_sum(float x, float* red) {
     return t;
 }
 
+// Interpolation coordinates of Cartesian point (col, bs); bs signed.
+__device__ __forceinline__ unsigned point_code(int col, int bs, const GatherArgs& a, float& f_out, float& g_out) {
+    f_out = 0.f;
+    g_out = 0.f;
+    if (col == 0 && bs == 0) return kCodeDc;
+    const double r = sqrt((double)(col * col + bs * bs)) * a.rscale;
+    if (r >= (double)a.Mh) return kCodeZero;
+    const double mf = floor(r);
+    g_out = (float)(r - mf);
+    const unsigned m0 = (unsigned)mf;
+
+    // direction of the point on [0, pi): (x, y) with y >= 0
+    const bool lower = bs < 0;
+    const int x = lower ? -col : col;
+    const int y = lower ? -bs : bs;
+    const float th = atan2f((float)y, (float)x);
+    int j0 = (int)floorf(th * a.vpi_f);
+    j0 = j0 < 0 ? 0 : (j0 >= a.V ? a.V - 1 : j0);
+    const double2 cs = a.ang[j0];
+    const double cross = (double)y * cs.x - (double)x * cs.y;
+    const double dot = (double)x * cs.x + (double)y * cs.y;
+    float f = atan2f((float)cross, (float)dot) * a.vpi_f;
+    if (f < 0.f) {
+        if (j0 > 0) { j0 -= 1; f += 1.f; } else { f = 0.f; }
+    } else if (f >= 1.f) {
+        if (j0 < a.V - 1) { j0 += 1; f -= 1.f; } else { f = 1.f; }
+    }
+    f_out = f;
+    const bool wrap = (j0 + 1 == a.V);
+    unsigned code = (unsigned)j0 | (m0 << 14);
+    if (lower) code |= kConj0;
+    if (lower != wrap) code |= kConj1;
+    if (wrap) code |= 1u << kWrapShift;
+    return code;
+}
+
 template <int LOGG>
 __global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherArgs a) {
     using C = GatherCfg<LOGG>;
-    constexpr int G = C::G, T = C::T;
-    __shared__ float2 lds[C::F * FftShape<LOGG>::LDS];
+    constexpr int G = C::G, T = C::T, F = C::F;
+    __shared__ float2 lds[F * C::STRIDE];
     __shared__ float red[(C::WG + 63) / 64];
-    const int fid = threadIdx.x / T;
-    const int j = threadIdx.x - fid * T;
-    float2* my = lds + fid * FftShape<LOGG>::LDS;
-    const int col = blockIdx.x * C::F + fid;
+    const int fid = threadIdx.x % F;
+    const int j = threadIdx.x / F;
+    float2* my = lds + fid * C::STRIDE;
+    const int lblock = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int col = lblock * F + fid;
     const bool live = col < G / 2;
 
-    int off0[16], off1[16];
+    // Coordinates: computed in a rolled loop (one copy of the trigonometry in
+    // registers), staged through the still unused transform LDS in two halves
+    // of 8 points, then held in registers for the whole chunk.
+    unsigned code[16];
     float fr[16], gr[16];
+    static_assert(C::F * C::STRIDE * 2 >= C::WG * 8 * 3, "coordinate staging needs LDS");
+    unsigned* st_code = reinterpret_cast<unsigned*>(lds);
+    float* st_f = reinterpret_cast<float*>(lds) + C::WG * 8;
+    float* st_g = st_f + C::WG * 8;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int b = j + e * T;
-        const int bs = b < G / 2 ? b : b - G;
-        off0[e] = kZero;
-        off1[e] = 0;
-        fr[e] = 0.f;
-        gr[e] = 0.f;
-        if (!live) continue;
-        if (col == 0 && bs == 0) { off0[e] = kDc; continue; }
-        const double r = sqrt((double)(col * col + bs * bs)) * a.rscale;
-        if (r >= (double)a.Mh) continue;
-        const double phi = atan2((double)bs, (double)col);
-        const bool lower = phi < 0.0;
-        const double th = lower ? phi + M_PI : phi;
-        const double q = th * a.vpi;
-        const double qf = floor(q);
-        double f = q - qf;
-        int j0 = (int)qf;
-        if (j0 >= a.V) { j0 = a.V - 1; f = 1.0; }
-        int j1 = j0 + 1;
-        const bool wrap = (j1 == a.V);
-        if (wrap) j1 = 0;
-        const double mf = floor(r);
-        const int m0 = (int)mf;
-        off0[e] = (j0 * a.S + m0) | (lower ? kConj : 0);
-        off1[e] = (j1 * a.S + m0) | ((lower != wrap) ? kConj : 0);
-        fr[e] = (float)f;
-        gr[e] = (float)(r - mf);
+    for (int half = 0; half < 2; ++half) {
+#pragma unroll 1
+        for (int h = 0; h < 8; ++h) {
+            const int e = half * 8 + h;
+            const int b = j + e * T;
+            const int bs = b < G / 2 ? b : b - G;
+            float f = 0.f, g = 0.f;
+            const unsigned c = live ? point_code(col, bs, a, f, g) : kCodeZero;
+            st_code[h * C::WG + threadIdx.x] = c;
+            st_f[h * C::WG + threadIdx.x] = f;
+            st_g[h * C::WG + threadIdx.x] = g;
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            code[half * 8 + h] = st_code[h * C::WG + threadIdx.x];
+            fr[half * 8 + h] = st_f[h * C::WG + threadIdx.x];
+            gr[half * 8 + h] = st_g[h * C::WG + threadIdx.x];
+        }
     }
+    __syncthreads();  // the transform reuses this LDS
 
     const int s_begin = blockIdx.y * a.slices_per_block;
     const int s_end = min(a.batch, s_begin + a.slices_per_block);
     const int half_n = a.N >> 1;
+    const int S = a.S;
     for (int s = s_begin; s < s_end; ++s) {
-        const float2* P = a.polar + (size_t)s * a.V * a.S;
+        const float2* P = a.polar + (size_t)s * a.V * S;
         float dcv = 0.f;
-        if (blockIdx.x == 0) {
+        if (lblock == 0) {
             float acc = 0.f;
             for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)s * a.V + i];
             dcv = block_sum<C::WG>(acc, red) * a.dc_scale;
@@ -113,19 +170,20 @@ __global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherAr
         float2 v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int o0 = off0[e];
-            if (o0 >= 0) {
-                const int o1 = off1[e];
-                const float2* p0 = P + (o0 & kOffMask);
-                const float2* p1 = P + (o1 & kOffMask);
-                const float2 A0 = p0[0], A1 = p0[1], B0 = p1[0], B1 = p1[1];
+            const unsigned c = code[e];
+            if (c < kCodeDc) {
+                const int j0 = c & 0x3FFF;
+                const int m0 = (c >> 14) & 0x1FFF;
+                const int o0 = j0 * S + m0;
+                const int o1 = ((c >> kWrapShift) & 1u) ? m0 : o0 + S;
+                const float2 A0 = P[o0], A1 = P[o0 + 1], B0 = P[o1], B1 = P[o1 + 1];
                 const float g = gr[e], f = fr[e];
                 float2 u0 = make_float2(fmaf(g, A1.x - A0.x, A0.x), fmaf(g, A1.y - A0.y, A0.y));
                 float2 u1 = make_float2(fmaf(g, B1.x - B0.x, B0.x), fmaf(g, B1.y - B0.y, B0.y));
-                if (o0 & kConj) u0.y = -u0.y;
-                if (o1 & kConj) u1.y = -u1.y;
+                if (c & kConj0) u0.y = -u0.y;
+                if (c & kConj1) u1.y = -u1.y;
                 v[e] = make_float2(fmaf(f, u1.x - u0.x, u0.x), fmaf(f, u1.y - u0.y, u0.y));
-            } else if (o0 == kDc) {
+            } else if (c == kCodeDc) {
                 v[e] = make_float2(dcv, 0.f);
             } else {
                 v[e] = make_float2(0.f, 0.f);

@@ -8,7 +8,8 @@
 // As in the usual C2R convention the imaginary part of the k = 0 sample is
 // ignored, and the k = G/2 sample is zero (no polar data reaches |k_x| = G/2).
 // A block takes up to 8 rows, i.e. one contiguous [G/2][8] tile of the grid
-// written by the column kernel.
+// written by the column kernel, with the row pairs interleaved across lanes so
+// that each wave's loads are contiguous.
 #include "bst_internal.h"
 #include "fft_lds.h"
 
@@ -27,8 +28,10 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     using C = RowCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
     __shared__ float2 lds[C::F * FftShape<LOGG>::LDS];
-    const int fid = threadIdx.x / T;
-    const int j = threadIdx.x - fid * T;
+    // thread t serves row pair t mod F: the lanes of a wave read F neighbouring
+    // 16-byte pairs of each k, i.e. contiguous runs of the [G/2][8] tile
+    const int fid = threadIdx.x % C::F;
+    const int j = threadIdx.x / C::F;
     float2* my = lds + fid * FftShape<LOGG>::LDS;
     const int row0 = blockIdx.x * (2 * C::F) + 2 * fid;
     const int s = blockIdx.y;

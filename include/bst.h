@@ -86,7 +86,23 @@ typedef struct {
     double taper_beta;      /* Kaiser-Bessel beta, >= 0                                  */
     int32_t max_batch;      /* largest batch a call may pass; >= 1                       */
     int32_t device;         /* HIP device ordinal the plan's tables live on              */
+    int32_t adjoint;        /* nonzero: also build the tables of bst_project (the
+                               transposed gather, ~8 bytes per Cartesian-point stencil
+                               entry: ~210 MB at N = 2048, P = 2)                       */
+    int32_t apodization;    /* bst_apodization: low-pass window A(sigma/sigma_Nyquist)
+                               multiplying the radial weight of P4 (the "low-pass
+                               filtering" stage F of Section 3)                          */
+    double center_shift;    /* known rotation-axis offset beta, detector bins: the data
+                               are y(t - beta*dt, theta) (Section 1, "Centering"); P4
+                               multiplies by exp(+2 pi i sigma beta dt). |beta| < n/4    */
 } bst_params;
+
+typedef enum {
+    BST_APOD_RAMLAK = 0,    /* A = 1                                  */
+    BST_APOD_SHEPP = 1,     /* sin(pi x/2) / (pi x/2)                 */
+    BST_APOD_HANN = 2,      /* (1 + cos(pi x)) / 2                    */
+    BST_APOD_COSINE = 3     /* cos(pi x/2)                            */
+} bst_apodization;
 
 /* Fill *p with the defaults: P_r = P_c = 2, RAMP, de-apodising taper, max_batch 1. */
 void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t n_out);
@@ -94,9 +110,12 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
 /* Host-only validation of *p (no device call). */
 bst_status bst_validate(const bst_params* p);
 
-/* Workspace bytes bst_backproject needs for `batch` slices (host only, no plan
- * needed): polar spectra [batch][V][M/2+2] complex64, per-projection DC terms
- * [batch][V] float32 and the half-transformed grid [batch][N][G/2] complex64. */
+/* Workspace bytes for `batch` slices (host only, no plan needed).
+ * bst_backproject: polar spectra [batch][V][M/2+2] complex64, per-projection DC
+ * terms [batch][V] float32 and the half-transformed grid [batch][N][G/2]
+ * complex64. With p->adjoint set, the size also covers bst_project: the grid,
+ * the full Cartesian half-plane spectrum [batch][G/2][G] and the polar adjoint
+ * [batch][V][M/2] (complex64); the larger of the two needs is returned. */
 bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes);
 
 /* Validate *p, then build the plan on p->device: FP64-derived tables (twiddles
@@ -116,6 +135,13 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes);
 bst_status bst_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* As bst_backproject, but the input is raw detector counts I [batch][V][n] with
+ * per-slice flat (I0) and dark (D) fields [batch][n]; the spectrum kernel forms
+ * y = -log((I - D) / (I0 - D)) as it loads (Section 1, "Normalization").
+ * Requires I > D and I0 > D; other values give non-finite results. */
+bst_status bst_backproject_counts(bst_plan_t plan, const float* counts, const float* flat, const float* dark,
+                                  float* img, int32_t batch, void* ws, size_t ws_bytes, void* stream);
+
 /* As bst_backproject, and records 4 caller-created HIP events (hipEvent_t
  * passed as void*) on `stream`: before the spectrum kernel, between the
  * kernels, and after the last one, so per-kernel time is measurable. */
@@ -130,9 +156,19 @@ bst_status bst_backproject_timed(bst_plan_t plan, const float* sino, float* img,
 bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float* img,
                                       int32_t batch, void* stream);
 
-/* Fourier-slice forward projector, the exact adjoint of bst_backproject
- * (P8..P0 transposed). Not implemented in this version: BST_E_UNSUPPORTED
- * after argument validation. */
+/* Projector R, the exact adjoint of bst_backproject: steps P8..P1 of Section 2
+ * transposed one by one (crop -> zero-embed, C2R inverse FFT -> forward FFT,
+ * bilinear gather -> the same weights scattered back, 1D FFT -> its transpose,
+ * pad -> crop, taper -> taper), scaled so that under the weighted inner products
+ * <f,f'> = d^2 sum f f' and <g,g'> = dt sum_j (pi/V) sum_i g g'
+ *     <R f, g> = <f, B g>   (B = R* as in Section 1).
+ * With a BST_FILTER_NONE plan R is a Fourier-slice (Eq. 1) projector; its
+ * transposed gridding is exact as an adjoint but, where polar samples are denser
+ * than Cartesian ones (radius < V/pi grid steps), it weights lattice-aligned
+ * angles unevenly, so as a stand-alone Radon approximation it is coarse at low
+ * frequencies. img: device float32 [batch][N][N]; sino: device float32
+ * [batch][V][n]. Needs a plan built with adjoint != 0 (else BST_E_UNSUPPORTED)
+ * and a workspace of bst_workspace_size bytes. Deterministic (no atomics). */
 bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t batch,
                        void* ws, size_t ws_bytes, void* stream);
 

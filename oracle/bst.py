@@ -45,16 +45,29 @@ from .geometry import Geometry
 KAPPA = 4.0 * np.arcsinh(1.0)
 
 
+APODIZATIONS = ("ramlak", "shepp", "hann", "cosine")
+
+
 class Params:
+    """Plan parameters. `apod` is the low-pass window A(sigma) multiplying the
+    radial weight (the filtering stage F of Section 3 is named "low-pass");
+    `center_shift` is a known rotation-axis offset beta in detector bins: the
+    measured sinogram is y(t - beta dt, theta) (Section 1, centering), undone in
+    P4 by the phase exp(+2 pi i sigma beta dt)."""
+
     def __init__(self, pad_radial: int = 2, pad_cart: int = 2, filter: str = "ramp",
-                 taper: str = "deapod", beta: float = 8.0):
+                 taper: str = "deapod", beta: float = 8.0, apod: str = "ramlak",
+                 center_shift: float = 0.0):
         assert filter in ("ramp", "none")
         assert taper in ("deapod", "none", "kb")
+        assert apod in APODIZATIONS
         self.P_r = int(pad_radial)
         self.P_c = int(pad_cart)
         self.filter = filter
         self.taper = taper
         self.beta = float(beta)
+        self.apod = apod
+        self.center_shift = float(center_shift)
 
 
 def sizes(geom: Geometry, prm: Params):
@@ -90,15 +103,39 @@ def transform(z: np.ndarray, dt: float) -> np.ndarray:
 
 
 # P4 ---------------------------------------------------------------------------
-def radial_weights(M: int, dt: float, filter: str) -> np.ndarray:
+def apodization(x: np.ndarray, apod: str) -> np.ndarray:
+    """Window A at x = sigma / sigma_Nyquist in [0, 1]."""
+    if apod == "ramlak":
+        return np.ones_like(x)
+    if apod == "shepp":
+        return np.sinc(x / 2.0)          # sin(pi x/2) / (pi x/2)
+    if apod == "hann":
+        return 0.5 * (1.0 + np.cos(np.pi * x))
+    return np.cos(np.pi * x / 2.0)       # cosine
+
+
+def radial_weights(M: int, dt: float, filter: str, apod: str = "ramlak") -> np.ndarray:
     m = np.arange(M // 2 + 1, dtype=np.float64)
     if filter == "ramp":
         K = np.ones_like(m)
     else:
         K = np.zeros_like(m)
         K[1:] = (M * dt) / m[1:]  # 1 / sigma_m
+    K = K * apodization(2.0 * m / M, apod)
     K[M // 2] = 0.0
     return K
+
+
+def shift_phase(M: int, dt: float, center_shift: float) -> np.ndarray:
+    """exp(+2 pi i sigma_m beta dt), m = 0..M/2, sigma_m = m / (M dt)."""
+    m = np.arange(M // 2 + 1, dtype=np.float64)
+    return np.exp(2j * np.pi * m * center_shift / M)
+
+
+def normalize(counts: np.ndarray, flat: np.ndarray, dark: np.ndarray) -> np.ndarray:
+    """Flat/dark correction of Section 1: y = -log((I - D) / (I0 - D))."""
+    c = np.asarray(counts, dtype=np.float64)
+    return -np.log((c - dark) / (flat - dark))
 
 
 # P5 ---------------------------------------------------------------------------
@@ -170,7 +207,10 @@ def spectrum(sino: np.ndarray, geom: Geometry, prm: Params):
     M, _, _, _ = sizes(geom, prm)
     z = pad(y * taper(geom, prm)[None, :], M)
     Y = transform(z, geom.dt)
-    Yh = Y * radial_weights(M, geom.dt, prm.filter)[None, :]
+    W = radial_weights(M, geom.dt, prm.filter, prm.apod).astype(np.complex128)
+    if prm.center_shift != 0.0:
+        W = W * shift_phase(M, geom.dt, prm.center_shift)
+    Yh = Y * W[None, :]
     return Yh, Y[:, 0].real.copy()
 
 
@@ -185,3 +225,101 @@ def backproject(sino: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndar
 
 def backproject_batch(sinos: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndarray:
     return np.stack([backproject(s, geom, prm) for s in sinos])
+
+
+# ----------------------------------------------------------------------------
+# Adjoint: the exact real-linear transpose of steps P1..P8, stage by stage.
+#
+# With the weighted inner products <f, f'> = d^2 sum f f' (images) and
+# <g, g'> = dt sum_j w_j sum_i g g' (sinograms, uniform w = pi/V), the
+# projector R = (d^2 / (dt w)) B^T satisfies <R f, g> = <f, B g> exactly,
+# mirroring B = R* of Section 1. With a plain-B plan R approximates the Radon
+# transform (Eq. 1) through the Fourier-slice theorem: the Cartesian density
+# of the transposed gather (~sigma) cancels the 1/sigma weight of P4.
+# Transposes used (real-linear maps, complex values as pairs of reals):
+#   crop            -> zero-embed
+#   C2R inverse     -> forward 2D DFT with c_a = 1 for a in {0, G/2}, else 2,
+#                      times dk^2
+#   bilinear gather -> scatter-add with the same weights and conjugations;
+#                      origin rule -> its factor times Re of the origin value,
+#                      added to the unweighted DC of every projection
+#   K[m]            -> K[m]
+#   real DFT        -> dt * sum_m Re(X[m] e^{+2 pi i k m / M}), m = 0..M/2
+#   pad             -> crop;  taper -> taper
+# ----------------------------------------------------------------------------
+def _gather_stencil(geom: Geometry, prm: Params):
+    """Per Cartesian point (b, a) of the half plane: the four (j, m, weight,
+    conjugate) entries of P5, as flat arrays (origin excluded)."""
+    M, G, _, _ = sizes(geom, prm)
+    V = geom.V
+    a = np.arange(G // 2 + 1, dtype=np.float64)[None, :]
+    b = np.arange(G, dtype=np.float64)
+    b = np.where(b < G // 2, b, b - G)[:, None]
+    r = np.sqrt(a * a + b * b) * (prm.P_r / prm.P_c)
+    phi = np.arctan2(b, a) + 0.0 * a
+    lower = phi < 0.0
+    theta = np.where(lower, phi + np.pi, phi)
+    q = theta * (V / np.pi)
+    j0 = np.floor(q)
+    f = q - j0
+    j0 = j0.astype(np.int64)
+    over = j0 >= V
+    j0 = np.where(over, V - 1, j0)
+    f = np.where(over, 1.0, f)
+    j1 = j0 + 1
+    wrap = j1 == V
+    j1 = np.where(wrap, 0, j1)
+    m0 = np.floor(r)
+    g = r - m0
+    m0 = m0.astype(np.int64)
+    bb, aa = np.meshgrid(np.arange(G), np.arange(G // 2 + 1), indexing="ij")
+    keep = ~((bb == 0) & (aa == 0))
+    entries = []
+    for jj, mm, ww, cc in ((j0, m0, (1 - f) * (1 - g), lower),
+                           (j0, m0 + 1, (1 - f) * g, lower),
+                           (j1, m0, f * (1 - g), lower ^ wrap),
+                           (j1, m0 + 1, f * g, lower ^ wrap)):
+        ok = keep & (mm < M // 2)
+        entries.append((bb[ok], aa[ok], jj[ok], mm[ok], ww[ok], cc[ok]))
+    return entries
+
+
+def project(img: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndarray:
+    """R f = (d^2 / (dt w)) B^T f for one image [N][N] -> sinogram [V][n], FP64."""
+    prm = prm or Params()
+    if not geom.uniform:
+        raise NotImplementedError("the BST oracle takes uniform angles theta_j = j pi / V")
+    f = np.asarray(img, dtype=np.float64)
+    assert f.shape == (geom.N, geom.N)
+    M, G, _, dk = sizes(geom, prm)
+    V, n, N = geom.V, geom.n, geom.N
+    # P8/P7 transpose: zero-embed at (p - N/2) mod G
+    idx = (np.arange(N) - N // 2) % G
+    full = np.zeros((G, G))
+    full[np.ix_(idx, idx)] = f
+    # P6 transpose
+    ca = np.full(G // 2 + 1, 2.0)
+    ca[0] = 1.0
+    ca[G // 2] = 1.0
+    Ct = (dk * dk) * np.fft.rfft2(full) * ca[None, :]       # [b][a]
+    # P5 transpose: scatter-add, plus the origin rule
+    Yh_t = np.zeros((V, M // 2 + 1), dtype=np.complex128)
+    for bb, aa, jj, mm, ww, cc in _gather_stencil(geom, prm):
+        v = Ct[bb, aa]
+        v = np.where(cc, np.conj(v), v)
+        np.add.at(Yh_t, (jj, mm), ww * v)
+    # P4 transpose (a complex weight transposes to its conjugate)
+    W = radial_weights(M, geom.dt, prm.filter, prm.apod).astype(np.complex128)
+    if prm.center_shift != 0.0:
+        W = W * shift_phase(M, geom.dt, prm.center_shift)
+    Y_t = Yh_t * np.conj(W)[None, :]
+    dc_rule = 1.0 if prm.filter == "ramp" else KAPPA / dk
+    Y_t[:, 0] += (dc_rule / V) * Ct[0, 0].real
+    # P3 transpose: dt * sum_m Re(X[m] e^{+2 pi i k m/M}) over m = 0..M/2
+    X = np.zeros((V, M), dtype=np.complex128)
+    X[:, :M // 2 + 1] = Y_t
+    z_t = geom.dt * M * np.fft.ifft(X, axis=-1).real
+    # P2 transpose (crop) and P1 (taper)
+    y_t = z_t[:, (np.arange(n) - n // 2) % M] * taper(geom, prm)[None, :]
+    w = np.pi / V
+    return (geom.d ** 2 / (geom.dt * w)) * y_t

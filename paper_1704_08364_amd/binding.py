@@ -24,6 +24,7 @@ STATUS_NAMES = {
 }
 FILTERS = {"none": 0, "ramp": 1}
 TAPERS = {"deapod": 0, "none": 1, "kaiser": 2, "kb": 2}
+APODIZATIONS = {"ramlak": 0, "shepp": 1, "hann": 2, "cosine": 3}
 
 # Every symbol include/bst.h declares, with its ctypes signature.
 _P = C.c_void_p
@@ -37,7 +38,8 @@ class bst_params(C.Structure):
         ("angles", C.POINTER(C.c_double)),
         ("pad_radial", C.c_int32), ("pad_cart", C.c_int32),
         ("filter", C.c_int32), ("taper", C.c_int32), ("taper_beta", C.c_double),
-        ("max_batch", C.c_int32), ("device", C.c_int32),
+        ("max_batch", C.c_int32), ("device", C.c_int32), ("adjoint", C.c_int32),
+        ("apodization", C.c_int32), ("center_shift", C.c_double),
     ]
 
 
@@ -49,6 +51,7 @@ SIGNATURES = {
     "bst_workspace_size": (C.c_int, [_P, _I, C.POINTER(_S)]),
     "bst_backproject": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
     "bst_backproject_timed": (C.c_int, [_P, _P, _P, _I, _P, _S, _P, C.POINTER(_P)]),
+    "bst_backproject_counts": (C.c_int, [_P, _P, _P, _P, _P, _I, _P, _S, _P]),
     "bst_backproject_bruteforce": (C.c_int, [_P, _P, _P, _I, _P]),
     "bst_project": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
     "bst_debug_spectrum": (C.c_int, [_P, _P, _P, _P, _I, _P, _S, _P]),
@@ -105,7 +108,8 @@ def _check(status: int, where: str):
 def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_radial: int = 2,
                 pad_cart: int = 2, filter: str = "ramp", taper: str = "deapod",
                 taper_beta: float = 8.0, max_batch: int = 1, device: int = 0,
-                angles: Optional[Sequence[float]] = None):
+                angles: Optional[Sequence[float]] = None, adjoint: bool = False,
+                apodization: str = "ramlak", center_shift: float = 0.0):
     """bst_params plus the ctypes array that backs `angles` (keep both alive)."""
     p = bst_params()
     lib().bst_params_default(C.byref(p), n_det, n_angles, n_det if n_out is None else n_out)
@@ -116,6 +120,9 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
     p.taper_beta = taper_beta
     p.max_batch = max_batch
     p.device = device
+    p.adjoint = 1 if adjoint else 0
+    p.apodization = APODIZATIONS[apodization] if isinstance(apodization, str) else int(apodization)
+    p.center_shift = center_shift
     keep = None
     if angles is not None:
         arr = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
@@ -235,6 +242,25 @@ class Plan:
             st = lib().bst_backproject_timed(self.handle, s3.data_ptr(), out.data_ptr(), B,
                                              workspace.data_ptr(), workspace.numel(), sp, arr)
             _check(st, "bst_backproject_timed")
+        return out if batched else out[0]
+
+    def backproject_counts(self, counts, flat, dark, out=None, workspace=None, stream=None):
+        """BST of raw counts with per-slice flat/dark fields [B][n] (normalised on load)."""
+        import torch
+        c3, batched = self._prep(counts)
+        B = c3.shape[0]
+        flat = _dev_tensor(flat, "flat", torch.float32, (self.n,)).reshape(-1, self.n)
+        dark = _dev_tensor(dark, "dark", torch.float32, (self.n,)).reshape(-1, self.n)
+        if flat.shape[0] != B or dark.shape[0] != B:
+            raise ValueError("flat and dark need one row of n values per slice")
+        if out is None:
+            out = torch.empty(B, self.N, self.N, dtype=torch.float32, device=c3.device)
+        _dev_tensor(out, "out", torch.float32, (self.N, self.N))
+        if workspace is None:
+            workspace = self.workspace(B)
+        _check(lib().bst_backproject_counts(self.handle, c3.data_ptr(), flat.data_ptr(), dark.data_ptr(),
+                                            out.data_ptr(), B, workspace.data_ptr(), workspace.numel(),
+                                            _stream_ptr(stream)), "bst_backproject_counts")
         return out if batched else out[0]
 
     def bruteforce(self, sino, out=None, stream=None):

@@ -1,5 +1,6 @@
 // bst_api.cpp -- the C ABI declared in include/bst.h: host-side validation,
 // FP64 plan tables, workspace carving and kernel enqueueing.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -8,6 +9,15 @@
 #include <vector>
 
 #include "bst_internal.h"
+
+// slices per gather block: the interpolation coordinates are computed once per block
+#ifndef BST_GATHER_SLICES
+#define BST_GATHER_SLICES 16
+#endif
+
+namespace bst {
+bool build_adjoint_tables(int V, int M, int G, double rscale, std::vector<int>& off, std::vector<uint2>& ent);
+}
 
 namespace {
 
@@ -78,6 +88,27 @@ WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch) {
     return L;
 }
 
+ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    ProjWsLayout L{};
+    const size_t B = (size_t)batch;
+    L.grid_off = 0;
+    L.cart_off = up(B * (size_t)N * (size_t)(G / 2) * sizeof(float2));
+    L.polar_off = up(L.cart_off + B * (size_t)(G / 2) * (size_t)G * sizeof(float2));
+    L.total = up(L.polar_off + B * (size_t)V * (size_t)(M / 2) * sizeof(float2));
+    return L;
+}
+
+size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint) {
+    if (batch == 0) return 0;
+    size_t need = workspace_layout(n, V, N, M, G, batch).total;
+    if (adjoint) {
+        const size_t pj = project_workspace_layout(V, N, M, G, batch).total;
+        if (pj > need) need = pj;
+    }
+    return need;
+}
+
 }  // namespace bst
 
 extern "C" {
@@ -96,6 +127,9 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
     p->taper_beta = 8.0;
     p->max_batch = 1;
     p->device = 0;
+    p->adjoint = 0;
+    p->apodization = BST_APOD_RAMLAK;
+    p->center_shift = 0.0;
 }
 
 bst_status bst_validate(const bst_params* p) {
@@ -112,6 +146,8 @@ bst_status bst_validate(const bst_params* p) {
     if (p->taper == BST_TAPER_KAISER && !(std::isfinite(p->taper_beta) && p->taper_beta >= 0.0 &&
                                           p->taper_beta <= 700.0))
         return BST_E_PARAM;
+    if (p->apodization < BST_APOD_RAMLAK || p->apodization > BST_APOD_COSINE) return BST_E_PARAM;
+    if (!std::isfinite(p->center_shift) || std::fabs(p->center_shift) >= 0.25 * p->n_det) return BST_E_PARAM;
     if (p->max_batch < 1) return BST_E_BATCH;
     if (p->device < 0) return BST_E_PARAM;
     if (p->angles) {
@@ -132,7 +168,8 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     if (batch < 0 || batch > p->max_batch) return BST_E_BATCH;
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
-    *bytes = batch == 0 ? 0 : bst::workspace_layout(p->n_det, p->n_angles, p->n_out, M, G, batch).total;
+    *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
+                                  p->adjoint != 0 && p->angles == nullptr);
     return BST_OK;
 }
 
@@ -167,11 +204,14 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->dc_scale = (float)(dc_rule / pl->V);
     pl->out_scale = (float)(pl->dk * pl->dk);
     pl->device = p->device;
+    pl->adjoint = (p->adjoint != 0) && pl->uniform;
+    pl->proj_scale = (float)(d * d / (pl->dt * (M_PI / pl->V)));
 
     // ---- FP64 tables ----
     const int n = pl->n, M = pl->M, G = pl->G, V = pl->V;
     const double dsig = 1.0 / (M * pl->dt);
-    std::vector<float> taper(n), kt(M / 2), bf_w(V);
+    std::vector<float> taper(n), bf_w(V);
+    std::vector<float2> kc(M / 2);
     std::vector<float2> twM(M), twG(G);
     std::vector<double> bf_c(V), bf_s(V), theta(V);
     std::vector<double2> ang(V);
@@ -192,7 +232,14 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
         double K;
         if (p->filter == BST_FILTER_RAMP) K = 1.0;
         else K = (m == 0) ? 0.0 : (M * pl->dt) / (double)m;
-        kt[m] = (float)(pl->dt * K);
+        const double x = 2.0 * m / (double)M;  // sigma_m / sigma_Nyquist
+        double A = 1.0;
+        if (p->apodization == BST_APOD_SHEPP) A = (x == 0.0) ? 1.0 : std::sin(M_PI * x / 2) / (M_PI * x / 2);
+        else if (p->apodization == BST_APOD_HANN) A = 0.5 * (1.0 + std::cos(M_PI * x));
+        else if (p->apodization == BST_APOD_COSINE) A = std::cos(M_PI * x / 2);
+        const double ph = 2.0 * M_PI * (double)m * p->center_shift / (double)M;
+        const double wr = pl->dt * K * A;
+        kc[m] = make_float2((float)(wr * std::cos(ph)), (float)(wr * std::sin(ph)));
     }
     for (int k = 0; k < M; ++k) {
         const double a = -2.0 * M_PI * (double)k / (double)M;
@@ -223,7 +270,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
     const size_t o_taper = off; off = up(off + n * sizeof(float));
-    const size_t o_kt = off;    off = up(off + (M / 2) * sizeof(float));
+    const size_t o_kc = off;    off = up(off + (M / 2) * sizeof(float2));
     const size_t o_twM = off;   off = up(off + M * sizeof(float2));
     const size_t o_twG = off;   off = up(off + G * sizeof(float2));
     const size_t o_c = off;     off = up(off + V * sizeof(double));
@@ -233,7 +280,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     const size_t total = off;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
-    std::memcpy(host.data() + o_kt, kt.data(), (M / 2) * sizeof(float));
+    std::memcpy(host.data() + o_kc, kc.data(), (M / 2) * sizeof(float2));
     std::memcpy(host.data() + o_twM, twM.data(), M * sizeof(float2));
     std::memcpy(host.data() + o_twG, twG.data(), G * sizeof(float2));
     std::memcpy(host.data() + o_c, bf_c.data(), V * sizeof(double));
@@ -265,9 +312,36 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
         delete pl;
         return device_fail(e);
     }
+    if (pl->adjoint) {
+        std::vector<int> off;
+        std::vector<uint2> ent;
+        bst::build_adjoint_tables(V, M, G, pl->rscale, off, ent);
+        pl->n_entries = ent.size();
+        const size_t o_ent = up(off.size() * sizeof(int));
+        const size_t adj_total = o_ent + std::max<size_t>(ent.size(), 1) * sizeof(uint2);
+        e = hipMalloc(&pl->adj_block, adj_total);
+        if (e != hipSuccess) {
+            g_last_error = hipGetErrorString(e);
+            (void)hipFree(pl->dev_block);
+            delete pl;
+            return BST_E_NOMEM;
+        }
+        e = hipMemcpy(pl->adj_block, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !ent.empty())
+            e = hipMemcpy(static_cast<unsigned char*>(pl->adj_block) + o_ent, ent.data(),
+                          ent.size() * sizeof(uint2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(pl->adj_block);
+            (void)hipFree(pl->dev_block);
+            delete pl;
+            return device_fail(e);
+        }
+        pl->csr_off = static_cast<int*>(pl->adj_block);
+        pl->csr_ent = reinterpret_cast<uint2*>(static_cast<unsigned char*>(pl->adj_block) + o_ent);
+    }
     unsigned char* base = static_cast<unsigned char*>(pl->dev_block);
     pl->taper = reinterpret_cast<float*>(base + o_taper);
-    pl->kt = reinterpret_cast<float*>(base + o_kt);
+    pl->kc = reinterpret_cast<float2*>(base + o_kc);
     pl->tw_M = reinterpret_cast<float2*>(base + o_twM);
     pl->tw_G = reinterpret_cast<float2*>(base + o_twG);
     pl->bf_c = reinterpret_cast<double*>(base + o_c);
@@ -281,8 +355,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
 bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
     if (!plan || !bytes) return BST_E_NULL;
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
-    *bytes = batch == 0 ? 0
-                        : bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch).total;
+    *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint);
     return BST_OK;
 }
 
@@ -313,7 +386,8 @@ bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const vo
 
 bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
                            size_t ws_bytes, void* stream, void* const* ev, bool spectrum_only,
-                           void* spec_out, float* dc_out) {
+                           void* spec_out, float* dc_out, const float* flat = nullptr,
+                           const float* dark = nullptr) {
     if (!plan) return BST_E_NULL;
     const size_t in_bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
     const size_t out_bytes = (size_t)batch * plan->N * plan->N * sizeof(float);
@@ -344,8 +418,8 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         e = hipEventRecord(static_cast<hipEvent_t>(ev[0]), s);
         if (e != hipSuccess) return device_fail(e);
     }
-    bst::SpecArgs sa{sino, polar, dc, plan->taper, plan->kt, plan->tw_M, plan->n, plan->V, plan->S,
-                     (float)plan->dt};
+    bst::SpecArgs sa{sino, flat, dark, polar, dc, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
+                     plan->S, (float)plan->dt};
     e = bst::launch_spectrum(*plan, sa, batch, s);
     if (e != hipSuccess) return device_fail(e);
     if (ev && ev[1]) {
@@ -371,7 +445,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.N = plan->N;
     ga.Mh = plan->M / 2;
     ga.batch = batch;
-    ga.slices_per_block = 16;
+    ga.slices_per_block = BST_GATHER_SLICES;
     ga.rscale = plan->rscale;
     ga.vpi_f = (float)plan->vpi;
     ga.ang = plan->ang;
@@ -399,6 +473,20 @@ extern "C" {
 bst_status bst_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
                            size_t ws_bytes, void* stream) {
     return run_backproject(plan, sino, img, batch, ws, ws_bytes, stream, nullptr, false, nullptr, nullptr);
+}
+
+bst_status bst_backproject_counts(bst_plan_t plan, const float* counts, const float* flat, const float* dark,
+                                  float* img, int32_t batch, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan) return BST_E_NULL;
+    if (batch > 0 && (!flat || !dark)) return BST_E_NULL;
+    if (batch > 0 && batch <= plan->prm.max_batch) {
+        const size_t fb = (size_t)batch * plan->n * sizeof(float);
+        const Range rf{(uintptr_t)flat, (uintptr_t)flat + fb}, rd{(uintptr_t)dark, (uintptr_t)dark + fb};
+        const Range ro{(uintptr_t)img, (uintptr_t)img + (size_t)batch * plan->N * plan->N * sizeof(float)};
+        if (overlap(rf, ro) || overlap(rd, ro)) return BST_E_ALIAS;
+    }
+    return run_backproject(plan, counts, img, batch, ws, ws_bytes, stream, nullptr, false, nullptr, nullptr, flat,
+                           dark);
 }
 
 bst_status bst_backproject_timed(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
@@ -432,23 +520,59 @@ bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float*
 
 bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t batch, void* ws,
                        size_t ws_bytes, void* stream) {
-    (void)stream;
     if (!plan) return BST_E_NULL;
     const size_t in_bytes = (size_t)batch * plan->N * plan->N * sizeof(float);
     const size_t out_bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
-    size_t need = 0;
-    const bst_status st = check_call(plan, img, in_bytes, sino, out_bytes, batch, ws, ws_bytes, true, &need);
-    if (st != BST_OK || batch == 0) return st;
-    return BST_E_UNSUPPORTED;
+    if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
+    if (batch == 0) return BST_OK;
+    if (!img || !sino || !ws) return BST_E_NULL;
+    if (!plan->adjoint) return BST_E_UNSUPPORTED;
+    const bst::ProjWsLayout L = bst::project_workspace_layout(plan->V, plan->N, plan->M, plan->G, batch);
+    if (ws_bytes < L.total) return BST_E_WORKSPACE;
+    const Range ri{(uintptr_t)img, (uintptr_t)img + in_bytes};
+    const Range ro{(uintptr_t)sino, (uintptr_t)sino + out_bytes};
+    const Range rw{(uintptr_t)ws, (uintptr_t)ws + L.total};
+    if (overlap(ri, ro) || overlap(rw, ri) || overlap(rw, ro)) return BST_E_ALIAS;
+
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return device_fail(guard.err);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
+    float2* cart = reinterpret_cast<float2*>(w + L.cart_off);
+    float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
+    const int cart_stride = (plan->G / 2) * plan->G;
+
+    bst::ProjRowArgs ra{img, grid, plan->tw_G, plan->N, plan->out_scale};
+    hipError_t e = bst::launch_proj_rows(*plan, ra, batch, s);
+    if (e != hipSuccess) return device_fail(e);
+    bst::ProjColArgs ca{grid, cart, plan->tw_G, plan->N};
+    e = bst::launch_proj_cols(*plan, ca, batch, s);
+    if (e != hipSuccess) return device_fail(e);
+    bst::ProjGatherArgs ga{cart, polar, plan->csr_off, plan->csr_ent, plan->V * (plan->M / 2), cart_stride,
+                           batch, 8};
+    e = bst::launch_proj_gather(*plan, ga, s);
+    if (e != hipSuccess) return device_fail(e);
+    bst::ProjPolarArgs pa{polar, cart, sino, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
+                          cart_stride, (float)(plan->dt * plan->dc_scale), plan->proj_scale};
+    e = bst::launch_proj_polar(*plan, pa, batch, s);
+    if (e != hipSuccess) return device_fail(e);
+    return BST_OK;
 }
 
 bst_status bst_destroy(bst_plan_t plan) {
     if (!plan) return BST_OK;
     bst_status st = BST_OK;
-    if (plan->dev_block) {
+    if (plan->dev_block || plan->adj_block) {
         DeviceGuard guard(plan->device);
-        const hipError_t e = hipFree(plan->dev_block);
-        if (e != hipSuccess) st = device_fail(e);
+        if (plan->dev_block) {
+            const hipError_t e = hipFree(plan->dev_block);
+            if (e != hipSuccess) st = device_fail(e);
+        }
+        if (plan->adj_block) {
+            const hipError_t e = hipFree(plan->adj_block);
+            if (e != hipSuccess) st = device_fail(e);
+        }
     }
     delete plan;
     return st;

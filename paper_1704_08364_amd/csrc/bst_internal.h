@@ -21,13 +21,20 @@ struct bst_plan_s {
     // device tables, one allocation
     void* dev_block;
     float* taper;        // [n]          P1 taper w[i]
-    float* kt;           // [M/2]        dt * K[m] of P4
+    float2* kc;          // [M/2]        dt * K[m] * A(sigma_m) * exp(2 pi i sigma_m beta dt) of P4
     float2* tw_M;        // [M]          exp(-2 pi i k/M)
     float2* tw_G;        // [G]          exp(-2 pi i k/G)
     double* bf_c;        // [V]          cos(theta_j) * d/dt   (brute force)
     double* bf_s;        // [V]          sin(theta_j) * d/dt
     float* bf_w;         // [V]          w_j
     double2* ang;        // [V]          (cos theta_j, sin theta_j), gather angle residuals
+    // adjoint (bst_project): transposed gather as CSR lists per polar sample
+    bool adjoint;
+    void* adj_block;
+    int* csr_off;        // [V*M/2 + 1]  entry range of polar sample j*M/2 + m
+    uint2* csr_ent;      // [entries]    (point index a*G + b | conj << 31, weight bits)
+    size_t n_entries;
+    float proj_scale;    // d^2 / (dt * pi/V): makes R the weighted adjoint of B
 };
 
 namespace bst {
@@ -37,12 +44,19 @@ struct WsLayout {
 };
 WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch);
 
+struct ProjWsLayout {
+    size_t grid_off, cart_off, polar_off, total;
+};
+ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch);
+
 struct SpecArgs {
-    const float* sino;
+    const float* sino;      // y, or raw counts when flat != nullptr
+    const float* flat;      // [batch][n] or nullptr
+    const float* dark;      // [batch][n]
     float2* polar;
     float* dc;
     const float* taper;
-    const float* kt;
+    const float2* kc;
     const float2* tw;
     int n, V, S;
     float dt;
@@ -77,6 +91,46 @@ struct BfArgs {
     const float* w;
     int n, V, N;
 };
+
+// adjoint kernels
+struct ProjRowArgs {       // image rows -> grid^T tiles
+    const float* img;
+    float2* grid;
+    const float2* tw;      // length G
+    int N;
+    float scale;           // dk^2
+};
+struct ProjColArgs {       // grid^T columns -> Cartesian half-plane spectrum^T [G/2][G]
+    const float2* grid;
+    float2* cart;
+    const float2* tw;
+    int N;
+};
+struct ProjGatherArgs {    // CSR transposed gather -> polar^T [V][M/2]
+    const float2* cart;
+    float2* polar;
+    const int* off;
+    const uint2* ent;
+    int samples;           // V * M/2
+    int cart_stride;       // G/2 * G complex per slice
+    int batch, slices_per_block;
+};
+struct ProjPolarArgs {     // polar^T rows -> sinogram rows
+    const float2* polar;
+    const float2* cart;    // origin value per slice at cart[s * cart_stride]
+    float* sino;
+    const float* taper;
+    const float2* kc;      // dt * K[m] * A * phase (conjugated on use)
+    const float2* tw;      // length M
+    int n, V, cart_stride;
+    float dc_dt;           // dt * dc_scale
+    float scale;           // proj_scale
+};
+
+hipError_t launch_proj_rows(const bst_plan_s& p, const ProjRowArgs& a, int batch, hipStream_t st);
+hipError_t launch_proj_cols(const bst_plan_s& p, const ProjColArgs& a, int batch, hipStream_t st);
+hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipStream_t st);
+hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int batch, hipStream_t st);
 
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st);
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st);

@@ -34,6 +34,14 @@
 
 namespace bst {
 
+#ifndef BST_GATHER_LD16
+#define BST_GATHER_LD16 1
+#endif
+// two adjacent complex samples; 8-byte aligned, read with one 16-byte load
+struct __attribute__((aligned(8))) Pair8 {
+    float x0, y0, x1, y1;
+};
+
 // point code: bits 0-13 j0, 14-26 m0, 27 conjugate the j0 samples, 28 conjugate the j1 samples
 constexpr unsigned kCodeZero = 0xFFFFFFFFu;
 constexpr unsigned kCodeDc = 0xFFFFFFFEu;
@@ -176,7 +184,15 @@ __global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherAr
                 const int m0 = (c >> 14) & 0x1FFF;
                 const int o0 = j0 * S + m0;
                 const int o1 = ((c >> kWrapShift) & 1u) ? m0 : o0 + S;
+#if BST_GATHER_LD16
+                // samples m0 and m0+1 of a row are adjacent: one 16-byte load each
+                const Pair8 pa = *reinterpret_cast<const Pair8*>(P + o0);
+                const Pair8 pb = *reinterpret_cast<const Pair8*>(P + o1);
+                const float2 A0 = make_float2(pa.x0, pa.y0), A1 = make_float2(pa.x1, pa.y1);
+                const float2 B0 = make_float2(pb.x0, pb.y0), B1 = make_float2(pb.x1, pb.y1);
+#else
                 const float2 A0 = P[o0], A1 = P[o0 + 1], B0 = P[o1], B1 = P[o1 + 1];
+#endif
                 const float g = gr[e], f = fr[e];
                 float2 u0 = make_float2(fmaf(g, A1.x - A0.x, A0.x), fmaf(g, A1.y - A0.y, A0.y));
                 float2 u1 = make_float2(fmaf(g, B1.x - B0.x, B0.x), fmaf(g, B1.y - B0.y, B0.y));

@@ -1,0 +1,259 @@
+// k_project.hip -- the projector R of bst_project: the exact adjoint of the
+// BST backprojection (Section 2, steps P8 .. P1 transposed one by one).
+//
+//   k_proj_rows    transpose of the row C2R + crop + dk^2: image rows are
+//                  zero-embedded at (q - N/2) mod G, forward-transformed two
+//                  rows per complex FFT, split, and scaled by dk^2 * c_a
+//                  (c_0 = 1, c_a = 2 otherwise: the C2R counts interior
+//                  columns twice); written to 8-row tiles [N/8][G/2][8].
+//   k_proj_cols    transpose of the column inverse DFT + crop: each column's N
+//                  rows are zero-embedded at (p - N/2) mod G and forward
+//                  transformed; the full half-plane spectrum is written
+//                  [G/2][G] (column-major).
+//   k_proj_gather  transpose of the bilinear polar -> Cartesian gather: every
+//                  polar sample sums, in a fixed order, the Cartesian values
+//                  whose stencil contains it (CSR lists built once per plan,
+//                  weight and conjugation per entry). No atomics, so the result
+//                  is bitwise reproducible. Each list is read once for up to 8
+//                  slices.
+//   k_proj_polar   transpose of P4..P1: the conjugate of the complex radial
+//                  weight dt*K[m]*A*phase (plus the origin rule's share
+//                  on m = 0), the transpose of the real DFT as the inverse FFT
+//                  of the Hermitian extension (two projections per complex
+//                  FFT), crop of the zero padding, taper, and the factor
+//                  d^2 / (dt pi/V) that makes R the weighted-inner-product
+//                  adjoint of B.
+#include "bst_internal.h"
+#include "fft_lds.h"
+
+namespace bst {
+
+template <int LOGG>
+struct ProjRowCfg {
+    static constexpr int G = 1 << LOGG;
+    static constexpr int T = G / 16;
+    static constexpr int F = G <= 4096 ? 4 : 2;   // row pairs per block
+    static constexpr int WG = F * T;
+};
+
+template <int LOGG>
+__global__ void __launch_bounds__(ProjRowCfg<LOGG>::WG) k_proj_rows(ProjRowArgs a) {
+    using C = ProjRowCfg<LOGG>;
+    constexpr int G = C::G, T = C::T;
+    __shared__ float2 lds[C::F * FftShape<LOGG>::LDS];
+    const int fid = threadIdx.x % C::F;
+    const int j = threadIdx.x / C::F;
+    float2* my = lds + fid * FftShape<LOGG>::LDS;
+    const int row0 = blockIdx.x * (2 * C::F) + 2 * fid;
+    const int s = blockIdx.y;
+    const float* r0 = a.img + ((size_t)s * a.N + row0) * a.N;
+    const float* r1 = r0 + a.N;
+    const int half_n = a.N >> 1;
+
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int x = j + e * T;
+        const int q = (x + half_n) & (G - 1);
+        v[e] = q < a.N ? make_float2(r0[q], r1[q]) : make_float2(0.f, 0.f);
+    }
+    fft<LOGG, -1>(v, my, j, a.tw);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) my[lds_pad(j + e * T)] = v[e];
+    __syncthreads();
+
+    float4* tile = reinterpret_cast<float4*>(a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * (G / 2));
+    const int sub = row0 & 7;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = j + e * T;  // 0 .. G/2-1
+        const float2 z = my[lds_pad(k)];
+        const float2 zc = my[lds_pad((G - k) & (G - 1))];
+        const float c = (k == 0 ? 0.5f : 1.0f) * a.scale;  // dk^2 * c_a / 2
+        tile[k * 4 + (sub >> 1)] = make_float4(c * (z.x + zc.x), c * (z.y - zc.y),
+                                               c * (z.y + zc.y), -c * (z.x - zc.x));
+    }
+}
+
+template <int LOGG>
+struct ProjColCfg {
+    static constexpr int G = 1 << LOGG;
+    static constexpr int T = G / 16;
+    static constexpr int F0 = T >= 512 ? 1 : 512 / T;
+    static constexpr int F = F0 > G / 2 ? G / 2 : F0;   // columns per block
+    static constexpr int WG = F * T;
+};
+
+template <int LOGG>
+__global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs a) {
+    using C = ProjColCfg<LOGG>;
+    constexpr int G = C::G, T = C::T;
+    __shared__ float2 lds[C::F * (FftShape<LOGG>::LDS + 8)];
+    const int fid = threadIdx.x % C::F;
+    const int j = threadIdx.x / C::F;
+    float2* my = lds + fid * (FftShape<LOGG>::LDS + 8);
+    const int col = blockIdx.x * C::F + fid;
+    const bool live = col < G / 2;
+    const int s = blockIdx.y;
+    const float2* D = a.grid + (size_t)s * a.N * (G / 2);
+    const int half_n = a.N >> 1;
+
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int y = j + e * T;
+        const int p = (y + half_n) & (G - 1);
+        v[e] = (live && p < a.N) ? D[((size_t)(p >> 3) * (G / 2) + col) * 8 + (p & 7)] : make_float2(0.f, 0.f);
+    }
+    fft<LOGG, -1>(v, my, j, a.tw);
+    if (live) {
+        float2* out = a.cart + (size_t)s * (G / 2) * G + (size_t)col * G;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) out[j + e * T] = v[e];
+    }
+}
+
+constexpr int kProjSlices = 8;
+
+__global__ void __launch_bounds__(256) k_proj_gather(ProjGatherArgs a) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.samples) return;
+    const int s0 = blockIdx.y * a.slices_per_block;
+    const int ns = min(a.slices_per_block, a.batch - s0);
+    float2 acc[kProjSlices];
+#pragma unroll
+    for (int k = 0; k < kProjSlices; ++k) acc[k] = make_float2(0.f, 0.f);
+    const int e1 = a.off[idx + 1];
+    for (int e = a.off[idx]; e < e1; ++e) {
+        const uint2 en = a.ent[e];
+        const size_t pidx = en.x & 0x7FFFFFFFu;
+        const bool cj = (en.x >> 31) != 0u;
+        const float w = __uint_as_float(en.y);
+        const float2* src = a.cart + (size_t)s0 * a.cart_stride + pidx;
+#pragma unroll
+        for (int k = 0; k < kProjSlices; ++k) {
+            if (k < ns) {
+                float2 v = src[(size_t)k * a.cart_stride];
+                if (cj) v.y = -v.y;
+                acc[k].x = fmaf(w, v.x, acc[k].x);
+                acc[k].y = fmaf(w, v.y, acc[k].y);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kProjSlices; ++k)
+        if (k < ns) a.polar[(size_t)(s0 + k) * a.samples + idx] = acc[k];
+}
+
+template <int LOGM>
+struct ProjPolarCfg {
+    static constexpr int M = 1 << LOGM;
+    static constexpr int T = M / 16;
+    static constexpr int F = T >= 256 ? 1 : 256 / T;   // projection pairs per block
+    static constexpr int WG = F * T;
+};
+
+template <int LOGM>
+__global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG) k_proj_polar(ProjPolarArgs a) {
+    using C = ProjPolarCfg<LOGM>;
+    constexpr int M = C::M, T = C::T;
+    __shared__ float2 lds[C::F * FftShape<LOGM>::LDS];
+    const int fid = threadIdx.x / T;
+    const int j = threadIdx.x - fid * T;
+    float2* my = lds + fid * FftShape<LOGM>::LDS;
+    const int pair = blockIdx.x * C::F + fid;
+    const int s = blockIdx.y;
+    const int ja = 2 * pair, jb = 2 * pair + 1;
+    const bool va = ja < a.V, vb = jb < a.V;
+    const float2* PA = a.polar + ((size_t)s * a.V + (va ? ja : 0)) * (M / 2);
+    const float2* PB = a.polar + ((size_t)s * a.V + (vb ? jb : 0)) * (M / 2);
+    const float dct = a.dc_dt * a.cart[(size_t)s * a.cart_stride].x;
+
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int k = j + e * T;
+        float2 ha = make_float2(0.f, 0.f), hb = ha;
+        if (k == 0) {
+            const float k0 = a.kc[0].x;  // real: the phase is 1 at sigma = 0
+            if (va) ha.x = k0 * PA[0].x + dct;
+            if (vb) hb.x = k0 * PB[0].x + dct;
+        } else if (k != M / 2) {
+            const bool up = k < M / 2;
+            const int m = up ? k : M - k;
+            float2 w = a.kc[m];
+            w = make_float2(0.5f * w.x, -0.5f * w.y);  // conj(weight)/2
+            if (va) { const float2 x = cmul(PA[m], w); ha = up ? x : make_float2(x.x, -x.y); }
+            if (vb) { const float2 x = cmul(PB[m], w); hb = up ? x : make_float2(x.x, -x.y); }
+        }
+        v[e] = make_float2(ha.x - hb.y, ha.y + hb.x);
+    }
+    fft<LOGM, +1>(v, my, j, a.tw);
+
+    const int h = a.n >> 1;
+    float* oa = a.sino + ((size_t)s * a.V + ja) * a.n;
+    float* ob = oa + a.n;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int x = j + e * T;
+        const int i = (x < h) ? x + h : ((x >= M - h) ? x - M + h : -1);
+        if (i >= 0) {
+            const float w = a.taper[i] * a.scale;
+            if (va) oa[i] = w * v[e].x;
+            if (vb) ob[i] = w * v[e].y;
+        }
+    }
+}
+
+#define BST_SWITCH_LOG(L, FN, ...)                  \
+    switch (L) {                                    \
+        case 4: return FN<4>(__VA_ARGS__);          \
+        case 5: return FN<5>(__VA_ARGS__);          \
+        case 6: return FN<6>(__VA_ARGS__);          \
+        case 7: return FN<7>(__VA_ARGS__);          \
+        case 8: return FN<8>(__VA_ARGS__);          \
+        case 9: return FN<9>(__VA_ARGS__);          \
+        case 10: return FN<10>(__VA_ARGS__);        \
+        case 11: return FN<11>(__VA_ARGS__);        \
+        case 12: return FN<12>(__VA_ARGS__);        \
+        case 13: return FN<13>(__VA_ARGS__);        \
+        default: return hipErrorInvalidValue;       \
+    }
+
+template <int LOGG>
+static hipError_t proj_rows_t(const ProjRowArgs& a, int batch, hipStream_t st) {
+    using C = ProjRowCfg<LOGG>;
+    hipLaunchKernelGGL(k_proj_rows<LOGG>, dim3(a.N / (2 * C::F), batch), dim3(C::WG), 0, st, a);
+    return hipGetLastError();
+}
+template <int LOGG>
+static hipError_t proj_cols_t(const ProjColArgs& a, int batch, hipStream_t st) {
+    using C = ProjColCfg<LOGG>;
+    hipLaunchKernelGGL(k_proj_cols<LOGG>, dim3((C::G / 2 + C::F - 1) / C::F, batch), dim3(C::WG), 0, st, a);
+    return hipGetLastError();
+}
+template <int LOGM>
+static hipError_t proj_polar_t(const ProjPolarArgs& a, int batch, hipStream_t st) {
+    using C = ProjPolarCfg<LOGM>;
+    const int pairs = (a.V + 1) / 2;
+    hipLaunchKernelGGL(k_proj_polar<LOGM>, dim3((pairs + C::F - 1) / C::F, batch), dim3(C::WG), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_proj_rows(const bst_plan_s& p, const ProjRowArgs& a, int batch, hipStream_t st) {
+    BST_SWITCH_LOG(p.logG, proj_rows_t, a, batch, st)
+}
+hipError_t launch_proj_cols(const bst_plan_s& p, const ProjColArgs& a, int batch, hipStream_t st) {
+    BST_SWITCH_LOG(p.logG, proj_cols_t, a, batch, st)
+}
+hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int batch, hipStream_t st) {
+    BST_SWITCH_LOG(p.logM, proj_polar_t, a, batch, st)
+}
+hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipStream_t st) {
+    (void)p;
+    const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
+    hipLaunchKernelGGL(k_proj_gather, dim3((a.samples + 255) / 256, chunks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace bst

@@ -6,8 +6,10 @@
 // (z[(i - n/2) mod M] = w[i] y[i]); the padded zeros exist only in registers.
 // After the transform Z, the two real spectra separate as
 //   Y_j[m] = (Z[m] + conj Z[M-m]) / 2,   Y_{j+1}[m] = (Z[m] - conj Z[M-m]) / (2i),
-// and each is scaled by dt*K[m] (K = 1/sigma for plain B, 1 for FBP, 0 at
-// m = M/2). Output rows hold m = 0..M/2-1 plus two zero slots (row stride
+// and each is multiplied by the complex weight dt*K[m]*A(sigma_m)*exp(2 pi i
+// sigma_m beta dt) (K = 1/sigma for plain B, 1 for FBP, 0 at m = M/2; A the
+// apodising window; beta a known rotation-axis offset). With raw counts the
+// load forms y = -log((I - D)/(I0 - D)) first (flat/dark normalisation). Output rows hold m = 0..M/2-1 plus two zero slots (row stride
 // S = M/2 + 2) so the gather may read samples m0 and m0+1 without a bound test.
 // The unweighted DC values dt*Y_j[0] go to a separate array for the origin rule.
 #include "bst_internal.h"
@@ -39,6 +41,9 @@ __global__ void __launch_bounds__(SpecCfg<LOGM>::WG) k_spectrum(SpecArgs a) {
     const float* ya = a.sino + ((size_t)s * a.V + (va ? ja : 0)) * a.n;
     const float* yb = a.sino + ((size_t)s * a.V + (vb ? jb : 0)) * a.n;
 
+    // raw counts: y = -log((I - D) / (I0 - D)) with the slice's flat/dark rows
+    const float* fl = a.flat ? a.flat + (size_t)s * a.n : nullptr;
+    const float* dk = a.flat ? a.dark + (size_t)s * a.n : nullptr;
     float2 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -47,8 +52,14 @@ __global__ void __launch_bounds__(SpecCfg<LOGM>::WG) k_spectrum(SpecArgs a) {
         float x = 0.f, y = 0.f;
         if (i >= 0) {
             const float w = a.taper[i];
-            if (va) x = w * ya[i];
-            if (vb) y = w * yb[i];
+            float ra = va ? ya[i] : 0.f, rb = vb ? yb[i] : 0.f;
+            if (fl) {
+                const float d = dk[i], inv = 1.0f / (fl[i] - d);
+                ra = va ? -logf((ra - d) * inv) : 0.f;
+                rb = vb ? -logf((rb - d) * inv) : 0.f;
+            }
+            x = w * ra;
+            y = w * rb;
         }
         v[e] = make_float2(x, y);
     }
@@ -66,9 +77,9 @@ __global__ void __launch_bounds__(SpecCfg<LOGM>::WG) k_spectrum(SpecArgs a) {
         const int m = j + e * T;  // 0 .. M/2-1
         const float2 z = my[lds_pad(m)];
         const float2 zc = my[lds_pad((M - m) & (M - 1))];
-        const float kt = a.kt[m];
-        const float2 ra = make_float2(0.5f * (z.x + zc.x) * kt, 0.5f * (z.y - zc.y) * kt);
-        const float2 rb = make_float2(0.5f * (z.y + zc.y) * kt, -0.5f * (z.x - zc.x) * kt);
+        const float2 kc = a.kc[m];
+        const float2 ra = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc);
+        const float2 rb = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc);
         if (va) pa[m] = ra;
         if (vb) pb[m] = rb;
     }

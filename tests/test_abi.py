@@ -130,3 +130,15 @@ def test_plan_without_device_fails_cleanly():
     assert h.value is None
     with pytest.raises(P.BstError):
         P.Plan(256, 256)
+
+
+def test_adjoint_workspace_covers_both_directions():
+    p, _ = _params(n=1024, V=1024, max_batch=8)
+    plain = P.query_workspace(p, 8)
+    p.adjoint = 1
+    both = P.query_workspace(p, 8)
+    # projector: grid [N][G/2] + Cartesian half plane [G/2][G] + polar [V][M/2], complex64
+    N = V = 1024
+    G = M = 2048
+    proj = 8 * 8 * (N * G // 2 + G // 2 * G + V * M // 2)
+    assert both >= plain and abs(both - max(plain, proj)) < 4 * 256

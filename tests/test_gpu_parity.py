@@ -5,7 +5,9 @@ FP64 oracle on the same FP32 input bytes; the polar spectrum stage within 1e-6;
 brute force within 1e-5. Sizes span several FFT lengths, odd and ragged
 angle counts, every padding combination, both filters and all tapers, plus
 the full 64 x 2048 x 2048 batch in the launch configuration the benchmark
-times (two of its slices checked in full against the oracle).
+times (two of its slices checked in full against the oracle). The projector
+(the exact adjoint) is held to the same 1e-5 against the oracle's transpose,
+plus the adjoint identity, determinism and autograd gradient checks.
 """
 import math
 import sys
@@ -30,8 +32,11 @@ def _say(*a):
 
 
 def rel_l2(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
+    a = np.asarray(a)
+    b = np.asarray(b)
+    dt = np.complex128 if (np.iscomplexobj(a) or np.iscomplexobj(b)) else np.float64
+    a = a.astype(dt)
+    b = b.astype(dt)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
@@ -159,7 +164,7 @@ def test_largest_transform_4096(P):
 
 
 @pytest.mark.parametrize("N,V,angles", [(16, 12, None), (64, 45, None), (256, 256, None),
-                                        (128, 90, "random"), (96 * 0 + 32, 17, "random")])
+                                        (128, 90, "random"), (32, 17, "random")])
 def test_bruteforce_matches_oracle(P, N, V, angles):
     _say(f"[bruteforce] N={N} V={V} {angles}")
     rng = np.random.default_rng(N + V)
@@ -278,3 +283,143 @@ def test_edge_cases(P):
     p2.bruteforce(sino[0])
     torch.cuda.synchronize()
     assert math.isfinite(float(out.sum()))
+
+
+# --- the adjoint projector and autograd ---------------------------------------
+
+PROJ_CASES = [(16, 10, "ramp", 2, 2), (32, 21, "none", 1, 2), (64, 50, "ramp", 2, 1),
+              (128, 96, "none", 2, 2), (256, 200, "ramp", 4, 2), (512, 300, "none", 2, 2)]
+
+
+@pytest.mark.parametrize("N,V,filt,P_r,P_c", PROJ_CASES)
+def test_project_matches_oracle(P, N, V, filt, P_r, P_c):
+    _say(f"[project] N={N} V={V} {filt} Pr={P_r} Pc={P_c}")
+    B = 3
+    plan = P.Plan(N, V, pad_radial=P_r, pad_cart=P_c, filter=filt, max_batch=B, adjoint=True)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(N + V)
+    img = torch.randn(B, N, N, generator=g).to(DEV)
+    out = plan.project(img)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    prm = obst.Params(P_r, P_c, filt)
+    for b in range(B):
+        ref = obst.project(img[b].double().cpu().numpy(), geom, prm)
+        err = rel_l2(out[b].cpu().numpy(), ref)
+        _say(f"   slice {b}: rel-L2 {err:.2e}")
+        assert err <= 1e-5
+
+
+@pytest.mark.parametrize("filt", ["ramp", "none"])
+def test_gpu_adjoint_identity(P, filt):
+    N, V, B = 256, 180, 2
+    plan = P.Plan(N, V, filter=filt, max_batch=B, adjoint=True)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(3)
+    f = torch.randn(B, N, N, generator=g).to(DEV)
+    y = torch.randn(B, V, N, generator=g).to(DEV)
+    Rf = plan.project(f).double().cpu().numpy()
+    By = plan.backproject(y).double().cpu().numpy()
+    torch.cuda.synchronize()
+    d, dt, w = 2.0 / N, 2.0 / N, math.pi / V
+    lhs = dt * w * float(np.sum(Rf * y.double().cpu().numpy()))
+    rhs = d * d * float(np.sum(f.double().cpu().numpy() * By))
+    assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
+
+
+def test_project_deterministic_and_batch_independent(P):
+    N, V, B = 128, 100, 11
+    plan = P.Plan(N, V, max_batch=B, adjoint=True)
+    f = torch.randn(B, N, N, device=DEV)
+    a = plan.project(f).clone()
+    b = plan.project(f).clone()
+    one = plan.project(f[B - 1:B].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a[B - 1], one[0])
+
+
+def test_autograd_gradients(P):
+    from paper_1704_08364_amd import autograd as AG
+    N, V, B = 64, 48, 2
+    plan = P.Plan(N, V, filter="none", max_batch=B, adjoint=True)
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(5)
+    f = torch.randn(B, N, N, generator=gen).to(DEV).requires_grad_(True)
+    gs = torch.randn(B, V, N, generator=gen).to(DEV)
+    v = torch.randn(B, N, N, generator=gen).to(DEV)
+
+    def loss64(x):
+        r = AG.project(x, plan).double() - gs.double()
+        return float((r * r).sum())
+
+    r = AG.project(f, plan) - gs
+    loss = (r * r).sum()
+    (grad,) = torch.autograd.grad(loss, f)
+    # explicit form: 2 c B (R f - g)
+    c = AG.adjoint_scale(plan)
+    explicit = 2.0 * c * plan.backproject((plan.project(f.detach()) - gs).contiguous())
+    assert rel_l2(grad.cpu().numpy(), explicit.cpu().numpy()) <= 1e-6
+    # central finite difference along v (exact for a quadratic up to rounding)
+    eps = 1e-2
+    with torch.no_grad():
+        fd = (loss64(f + eps * v) - loss64(f - eps * v)) / (2 * eps)
+    dd = float((grad.double() * v.double()).sum())
+    assert abs(fd - dd) <= 1e-3 * abs(dd)
+    # backward of the backprojection: d/dsino <h, B sino> = B^T h = R h / c
+    s = gs.clone().requires_grad_(True)
+    h = torch.randn(B, N, N, generator=gen).to(DEV)
+    (gsino,) = torch.autograd.grad((AG.backproject(s, plan) * h).sum(), s)
+    expect = plan.project(h) / c
+    assert rel_l2(gsino.cpu().numpy(), expect.cpu().numpy()) <= 1e-6
+
+
+def test_least_squares_descends(P):
+    from paper_1704_08364_amd import autograd as AG
+    N, V, B = 128, 128, 2
+    plan = P.Plan(N, V, filter="none", max_batch=B, adjoint=True)
+    sino = synth.batch_sinograms(B, N, V, seed=21, device=DEV, noise=0.0)
+    f, losses = AG.least_squares(plan, sino, steps=20)
+    _say(f"[ls] losses {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:]))
+    assert losses[-1] < 0.5 * losses[0]
+
+
+# --- apodised ramp, known centre shift, flat/dark normalisation ----------------
+
+@pytest.mark.parametrize("N,V,filt,apod,shift", [(128, 100, "ramp", "hann", 2.5),
+                                                 (64, 48, "none", "shepp", -1.25),
+                                                 (256, 256, "ramp", "cosine", 7.0)])
+def test_backproject_and_project_with_apodisation_and_shift(P, N, V, filt, apod, shift):
+    _say(f"[apod/shift] N={N} V={V} {filt} {apod} {shift}")
+    B = 2
+    plan = P.Plan(N, V, filter=filt, apodization=apod, center_shift=shift, max_batch=B, adjoint=True)
+    sino = _sinos(B, V, N, 500 + N)
+    img = plan.backproject(sino)
+    f = torch.randn(B, N, N, device=DEV)
+    proj = plan.project(f)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    prm = obst.Params(2, 2, filt, apod=apod, center_shift=shift)
+    for b in range(B):
+        assert rel_l2(img[b].cpu().numpy(), obst.backproject(sino[b].double().cpu().numpy(), geom, prm)) <= 1e-5
+        assert rel_l2(proj[b].cpu().numpy(), obst.project(f[b].double().cpu().numpy(), geom, prm)) <= 1e-5
+
+
+def test_backproject_counts(P):
+    N, V, B = 256, 200, 3
+    sino = _sinos(B, V, N, 900, kind="plain")
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(9)
+    flat = 1000.0 + 100.0 * torch.rand(B, N, device=DEV, generator=gen)
+    dark = 10.0 * torch.rand(B, N, device=DEV, generator=gen)
+    ymax = float(sino.abs().max())
+    counts = (dark[:, None, :] + (flat - dark)[:, None, :] * torch.exp(-sino / ymax)).contiguous()
+    plan = P.Plan(N, V, max_batch=B)
+    img = plan.backproject_counts(counts, flat, dark)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    for b in range(B):
+        y = obst.normalize(counts[b].double().cpu().numpy(), flat[b].double().cpu().numpy(),
+                           dark[b].double().cpu().numpy())
+        assert rel_l2(img[b].cpu().numpy(), obst.backproject(y, geom, obst.Params())) <= 1e-5

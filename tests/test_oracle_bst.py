@@ -5,7 +5,9 @@
 - closed forms: FBP of an analytic Gaussian returns the Gaussian (RAMP);
   y = cos(2 pi s0 t) backprojects to pi J0(2 pi s0 |u|) and a Gaussian's
   sinogram to pi sqrt(2 pi) s e^{-z} I0(z), z = r^2/4s^2 (NONE);
-- the taper options reduce to each other where they must.
+- the taper options reduce to each other where they must;
+- the projector is the exact adjoint: weighted inner-product identity and the
+  transpose of the literal-sum backprojection's dense matrix.
 """
 import math
 
@@ -15,6 +17,7 @@ from scipy.special import i0e, j0
 
 import synth
 from oracle import bst, bst_naive
+from oracle.bruteforce import inner_image, inner_sino
 from oracle.geometry import Geometry
 
 
@@ -188,3 +191,120 @@ def test_plain_backprojection_of_gaussian_closed_form():
     disk = np.hypot(u[None, :], u[:, None]) <= 0.9
     b = bst.backproject(y, g, bst.Params(2, 2, "none"))
     assert _rel(b[disk], ex[disk]) < 2e-2
+
+
+# --- the adjoint (projector) -------------------------------------------------
+
+
+@pytest.mark.parametrize("N,V,P_r,P_c,filt", [(16, 12, 2, 2, "ramp"), (32, 21, 1, 2, "none"),
+                                              (64, 50, 2, 1, "ramp"), (32, 24, 4, 2, "none"),
+                                              (64, 64, 2, 4, "ramp")])
+def test_project_is_the_adjoint(N, V, P_r, P_c, filt):
+    # <R f, g> = <f, B g> under the weighted inner products (B = R*, Section 1)
+    rng = np.random.default_rng(N + V + P_r)
+    g = Geometry(N, V, N)
+    prm = bst.Params(P_r, P_c, filt)
+    f = rng.standard_normal((N, N))
+    y = rng.standard_normal((V, N))
+    lhs = inner_sino(bst.project(f, g, prm), y, g)
+    rhs = inner_image(f, bst.backproject(y, g, prm), g)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+@pytest.mark.parametrize("filt", ["ramp", "none"])
+def test_project_equals_transpose_of_literal_backprojection(filt):
+    # dense matrix of the literal-sum backprojection at a tiny size, transposed
+    N, V = 8, 6
+    g = Geometry(N, V, N)
+    cols = []
+    for k in range(V * N):
+        e = np.zeros(V * N)
+        e[k] = 1.0
+        cols.append(bst_naive.backproject(e.reshape(V, N), g, 2, 2, filt).ravel())
+    Bmat = np.stack(cols, axis=1)  # [N*N][V*N]
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((N, N))
+    scale = g.d ** 2 / (g.dt * np.pi / V)
+    expect = scale * (Bmat.T @ f.ravel()).reshape(V, N)
+    got = bst.project(f, g, bst.Params(2, 2, filt))
+    assert np.max(np.abs(got - expect)) <= 1e-12 * np.max(np.abs(expect))
+
+
+# --- pre-processing stages folded into P1/P4: apodised ramp, centre shift, flat/dark ---
+
+def _smooth_gauss(N, s=0.03):
+    sg = synth.Geometry(N, N, N)
+    gs = synth.Gaussian(0.1, -0.2, s)
+    return sg, gs, synth.gaussian_sinogram(sg, gs).numpy()
+
+
+@pytest.mark.parametrize("apod", ["shepp", "hann", "cosine"])
+def test_apodised_ramp_equals_prefiltered_sinogram(apod):
+    # K[m] = A(sigma_m / sigma_Nyq) in P4 is the same as filtering every
+    # projection by A(|sigma|) first (done here with a long zero-padded FFT)
+    N = 128
+    g = Geometry(N, N, N)
+    _, _, y = _smooth_gauss(N)
+    L = 8 * N
+    x = np.arange(L // 2 + 1) / (L * g.dt) * (2 * g.dt)
+    A = bst.apodization(np.minimum(x, 1.0), apod) * (x < 1.0)
+    yf = np.fft.irfft(np.fft.rfft(y, L, axis=1) * A, L, axis=1)[:, :N]
+    a = bst.backproject(yf, g, bst.Params(apod="ramlak"))
+    b = bst.backproject(y, g, bst.Params(apod=apod))
+    c = bst.backproject(y, g, bst.Params(apod="ramlak"))
+    assert _rel(a, b) < 1e-3
+    assert _rel(c, b) > 1e-2
+
+
+@pytest.mark.parametrize("filt", ["ramp", "none"])
+@pytest.mark.parametrize("shift", [3, -5])
+def test_integer_centre_shift_is_exact(filt, shift):
+    # a sinogram measured with the axis k bins off, y_m[i] = y[i - k]: with no
+    # taper (which is not shift invariant) the phase ramp undoes the shift exactly
+    rng = np.random.default_rng(10 + shift)
+    N, V = 64, 40
+    g = Geometry(N, V, N)
+    y = np.zeros((V, N))
+    y[:, 8:N - 8] = rng.standard_normal((V, N - 16))
+    ym = np.roll(y, shift, axis=1)
+    a = bst.backproject(y, g, bst.Params(2, 2, filt, "none"))
+    b = bst.backproject(ym, g, bst.Params(2, 2, filt, "none", center_shift=shift))
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_fractional_centre_shift_of_analytic_sinogram():
+    import torch
+    N = 128
+    g = Geometry(N, N, N)
+    sg, gs, y = _smooth_gauss(N, 0.08)
+    beta = 3.37
+    t = sg.t()[None, :] - beta * sg.dt
+    th = sg.theta()[:, None]
+    sc = t - (gs.cx * torch.cos(th) + gs.cy * torch.sin(th))
+    ym = (math.sqrt(2 * math.pi) * gs.s * torch.exp(-sc * sc / (2 * gs.s ** 2))).numpy()
+    a = bst.backproject(y, g)
+    assert _rel(bst.backproject(ym, g, bst.Params(center_shift=beta)), a) < 1e-2
+    assert _rel(bst.backproject(ym, g, bst.Params(center_shift=-beta)), a) > 0.3
+
+
+def test_flat_dark_normalisation_inverts_lambert_beer():
+    # I = D + (I0 - D) exp(-y)  =>  -log((I - D)/(I0 - D)) = y
+    rng = np.random.default_rng(12)
+    y = rng.uniform(0.0, 3.0, (20, 32))
+    flat = rng.uniform(900.0, 1100.0, 32)
+    dark = rng.uniform(5.0, 20.0, 32)
+    counts = dark + (flat - dark) * np.exp(-y)
+    assert np.max(np.abs(bst.normalize(counts, flat, dark) - y)) < 1e-12
+
+
+def test_adjoint_with_shift_and_apodisation():
+    rng = np.random.default_rng(13)
+    N, V = 64, 48
+    g = Geometry(N, V, N)
+    f = rng.standard_normal((N, N))
+    y = rng.standard_normal((V, N))
+    for prm in (bst.Params(center_shift=2.5, apod="hann"),
+                bst.Params(filter="none", center_shift=-1.25, apod="shepp")):
+        lhs = inner_sino(bst.project(f, g, prm), y, g)
+        rhs = inner_image(f, bst.backproject(y, g, prm), g)
+        assert abs(lhs - rhs) <= 1e-12 * abs(rhs)

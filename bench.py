@@ -90,6 +90,85 @@ def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices):
     return slices / dt, dt, errs
 
 
+def volume_workload(args):
+    """Full volume: 2048 slices x 2048 angles x 2048 bins (32 GiB in, 32 GiB out),
+    sinograms of a seeded 30-ellipsoid phantom with Poisson-like noise at 1e5
+    photons, all resident in HBM; BST FBP in batches of 64 with one plan."""
+    import numpy as np
+    import torch
+
+    import paper_1704_08364_amd as P
+    import synth
+
+    S, n, V, Bt = args.slices, args.n, args.angles, args.batch
+    N = n
+    dev = "cuda:0"
+    geom = synth.Geometry(n, V, N)
+    params = synth.ellipsoid_volume_params(170408367, 30)
+    log(f"generating the {S}-slice volume on the GPU ...")
+    t0 = time.perf_counter()
+    sino = torch.empty(S, V, n, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(170408367)
+    for k in range(S):
+        s_k = -1.0 + (k + 0.5) * 2.0 / S
+        y = synth.ellipse_sinogram(geom, synth.ellipsoid_slice_ellipses(params, s_k), dev)
+        sino[k] = synth.poisson_like_noise(y, 1e5, gen).to(torch.float32) if float(y.max()) > 0 else 0.0
+    torch.cuda.synchronize()
+    log(f"  {time.perf_counter() - t0:.1f} s")
+    img = torch.empty(S, N, N, dtype=torch.float32, device=dev)
+    plan = P.Plan(n, V, max_batch=Bt)
+    ws = plan.workspace(Bt)
+    for b0 in range(0, min(S, Bt * args.warmup), Bt):
+        plan.backproject(sino[b0:b0 + Bt], out=img[b0:b0 + Bt], workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for b0 in range(0, S, Bt):
+        plan.backproject(sino[b0:b0 + Bt], out=img[b0:b0 + Bt], workspace=ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    out = {"metric": "BST FBP of a full volume", "value": round(S / el, 2), "unit": "slices/s",
+           "seconds": round(el, 4), "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{S} slices x {V} angles x {n} bins, 30-ellipsoid phantom, "
+                                  f"Poisson-like noise 1e5 photons, batches of {Bt}", "slices": S}}
+    if args.cpu_slices > 0:
+        from oracle import bst as obst
+        from oracle.geometry import Geometry
+        errs = []
+        for k in (S // 3, S // 2):
+            ref = obst.backproject(sino[k].double().cpu().numpy(), Geometry(n, V, N), obst.Params())
+            errs.append(float(np.linalg.norm(img[k].double().cpu().numpy() - ref) / np.linalg.norm(ref)))
+        out["parity"] = {"slices_checked": 2, "max_rel_l2_vs_fp64_oracle": max(errs)}
+    print(json.dumps(out), flush=True)
+
+
+def ls_workload(args):
+    """Least-squares reconstruction ||R f - g||^2 by 20 gradient steps from f = 0
+    with the exact adjoint pair (autograd), 32 slices x 1024 angles x 1024 bins."""
+    import torch
+
+    import paper_1704_08364_amd as P
+    from paper_1704_08364_amd import autograd as AG
+    import synth
+
+    B, n, V = args.batch, args.n, args.angles
+    dev = "cuda:0"
+    g = synth.batch_sinograms(B, n, V, seed=170408369, device=dev)
+    plan = P.Plan(n, V, filter="none", max_batch=B, adjoint=True)
+    step = 1.0 / AG.lipschitz(plan, (B, n, n))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f, losses = AG.least_squares(plan, g, steps=args.steps, step=step)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"metric": "least-squares gradient steps (forward R + backward B per step)",
+           "value": round(args.steps / el, 3), "unit": "steps/s", "ms_per_step": round(el * 1e3 / args.steps, 3),
+           "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "loss_first": losses[0], "loss_last": losses[-1],
+           "config": {"workload": f"{B} slices x {V} angles x {n} bins, random ellipse phantoms", "steps": args.steps}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +181,15 @@ def main():
     ap.add_argument("--bf-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bruteforce", action="store_true")
+    ap.add_argument("--workload", choices=("batch", "volume", "ls"), default="batch",
+                    help="batch: 64 x 2048^2 FBP (default); volume: the full 2048^3 volume; "
+                         "ls: 32 x 1024^2 least squares by gradient descent")
+    ap.add_argument("--slices", type=int, default=2048)
+    ap.add_argument("--input", choices=("phantom", "random"), default="phantom",
+                    help="random: N(0,1) sinograms (for hardware-counter runs, where generating "
+                         "phantoms with thousands of small kernels is slow)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy a 1 GiB buffer first, to scale FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -110,6 +198,11 @@ def main():
               "run is the single-GPU path on a slab of slices per GPU (no collectives); "
               "this build measures N=1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "volume":
+        return volume_workload(args)
+    if args.workload == "ls":
+        return ls_workload(args)
 
     import numpy as np
     import torch
@@ -121,8 +214,18 @@ def main():
     N = n
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
     log(f"generating {B} sinograms {V}x{n} on the GPU ...")
-    sino = synth.batch_sinograms(B, n, V, seed=170408366, device=dev)
+    if args.input == "random":
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(170408366)
+        sino = torch.randn(B, V, n, device=dev, generator=gen)
+    else:
+        sino = synth.batch_sinograms(B, n, V, seed=170408366, device=dev)
     plan = P.Plan(n, V, max_batch=B)
     M, G = plan.M, plan.G
     ws = plan.workspace(B)
@@ -209,7 +312,7 @@ def main():
             "workload": f"FBP of {B} slices x {V} angles x {n} bins -> {B} x {N}x{N}, "
                         f"random 5-20 ellipse phantoms + 1% noise, P_r=P_c=2, de-apodising taper",
             "batch": B, "n_det": n, "n_angles": V, "n_out": N, "pad_radial": 2, "pad_cart": 2,
-            "filter": "ramp",
+            "filter": "ramp", "input": args.input,
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -447,6 +447,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.batch = batch;
     ga.slices_per_block = BST_GATHER_SLICES;
     ga.rscale = plan->rscale;
+    ga.rscale_log2 = ilog2(plan->prm.pad_radial) - ilog2(plan->prm.pad_cart);
     ga.vpi_f = (float)plan->vpi;
     ga.ang = plan->ang;
     ga.dc_scale = plan->dc_scale;

@@ -1,8 +1,8 @@
 // fft_lds.h -- in-register / LDS Stockham FFT used by every BST kernel.
 //
-// A transform of length L = 2^l is held by T = L/16 threads; thread j keeps the
-// 16 values x[j + e*T], e = 0..15, in registers on entry and X[j + e*T] on exit
-// (natural order). Passes are radix 2^(l mod 4) first (if l is not a multiple
+// A transform of length L = 2^l is held by T = L/E threads (E = 16 or 32);
+// thread j keeps the E values x[j + e*T], e = 0..E-1, in registers on entry and
+// X[j + e*T] on exit (natural order). Passes are radix 2^(l mod 4) first (if l is not a multiple
 // of 4) and then radix 16. Each pass computes its butterflies in registers;
 // between passes the values go through LDS once (write, barrier, read, barrier).
 // The Stockham auto-sort indexing (Govindaraju et al., SC'08) keeps every pass
@@ -106,10 +106,10 @@ __device__ __forceinline__ void dft(float2* v) {
 // v[k + r*(16/R)] in this thread's registers -- twiddles it by
 // w^((jj mod NS) * r) with w = exp(DIR 2 pi i / (NS R)), transforms, and
 // writes output r to position (jj / NS) * NS * R + (jj mod NS) + r * NS.
-template <int L, int DIR, int R, int NS>
-__device__ __forceinline__ void stockham_pass(float2 (&v)[16], float2* lds, int j, const float2* __restrict__ tw) {
-    constexpr int T = L / 16;
-    constexpr int BPT = 16 / R;
+template <int L, int DIR, int R, int NS, int E>
+__device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
+    constexpr int T = L / E;
+    constexpr int BPT = E / R;
     constexpr bool LAST = (NS * R == L);
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
@@ -154,31 +154,36 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[16], float2* lds, int 
     if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = lds[lds_pad(j + e * T)];
+        for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(j + e * T)];
         __syncthreads();
     }
 }
 
-template <int L, int DIR, int NS>
-__device__ __forceinline__ void radix16_passes(float2 (&v)[16], float2* lds, int j, const float2* tw) {
+template <int L, int DIR, int R, int NS, int E>
+__device__ __forceinline__ void radix_passes(float2 (&v)[E], float2* lds, int j, const float2* tw) {
     if constexpr (NS < L) {
-        stockham_pass<L, DIR, 16, NS>(v, lds, j, tw);
-        radix16_passes<L, DIR, NS * 16>(v, lds, j, tw);
+        stockham_pass<L, DIR, R, NS, E>(v, lds, j, tw);
+        radix_passes<L, DIR, R, NS * R, E>(v, lds, j, tw);
     }
 }
 
-// Full transform. Requires every thread of the block to call it (barriers);
-// `lds` must hold lds_pad(L) float2 for this transform and not be read by
-// anyone else meanwhile. Ends with a barrier if any LDS exchange happened.
-template <int LOGL, int DIR>
-__device__ __forceinline__ void fft(float2 (&v)[16], float2* lds, int j, const float2* __restrict__ tw) {
+// Full transform of length 2^LOGL by L/E threads holding E (8, 16 or 32)
+// values each; passes are radix min(E, 16) after one smaller first pass when
+// needed. Requires every thread of the block to call it (barriers); `lds` must
+// hold lds_pad(L) float2 for this transform and not be read by anyone else
+// meanwhile. Ends with a barrier if any LDS exchange happened.
+template <int LOGL, int DIR, int E = 16>
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
+    static_assert(E == 8 || E == 16 || E == 32, "8, 16 or 32 values per thread");
     constexpr int L = 1 << LOGL;
-    constexpr int REM = LOGL % 4;
+    constexpr int LR = E >= 16 ? 4 : 3;     // log2 of the main radix
+    constexpr int R = 1 << LR;
+    constexpr int REM = LOGL % LR;
     if constexpr (REM != 0) {
-        stockham_pass<L, DIR, (1 << REM), 1>(v, lds, j, tw);
-        radix16_passes<L, DIR, (1 << REM)>(v, lds, j, tw);
+        stockham_pass<L, DIR, (1 << REM), 1, E>(v, lds, j, tw);
+        radix_passes<L, DIR, R, (1 << REM), E>(v, lds, j, tw);
     } else {
-        radix16_passes<L, DIR, 1>(v, lds, j, tw);
+        radix_passes<L, DIR, R, 1, E>(v, lds, j, tw);
     }
 }
 

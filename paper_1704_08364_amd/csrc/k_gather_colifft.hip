@@ -9,8 +9,9 @@
 // angle row, consecutive radii). Columns go to XCDs in contiguous ranges so
 // neighbouring columns share an L2.
 //
-// Each thread keeps the interpolation coordinates of its 16 points in three
-// registers each and reuses them for every slice of its chunk. They are exact
+// Each thread keeps the interpolation coordinates of its E points (8 by
+// default) in three registers each and reuses them for every slice of its
+// chunk. They are exact
 // to FP32 rounding although radius and angle indices reach a few thousand:
 //   radius index r = |(a,b)| P_r/P_c from an FP64 square root;
 //   angle index: an FP32 atan2 picks the interval [theta_j0, theta_j0+1), then
@@ -34,9 +35,22 @@
 
 namespace bst {
 
-#ifndef BST_GATHER_LD16
-#define BST_GATHER_LD16 1
+// values per thread of the column transform (8 or 16): fewer values mean less
+// per-thread state (interpolation coordinates, in-flight gathers) and more
+// resident waves
+#ifndef BST_GATHER_E
+#define BST_GATHER_E 8
 #endif
+// threads per block of the gather kernel (the columns per block follow from it)
+#ifndef BST_GATHER_THREADS
+#define BST_GATHER_THREADS 512
+#endif
+
+// waves per SIMD the register allocation must leave room for
+#ifndef BST_GATHER_WAVES
+#define BST_GATHER_WAVES 4
+#endif
+
 // two adjacent complex samples; 8-byte aligned, read with one 16-byte load
 struct __attribute__((aligned(8))) Pair8 {
     float x0, y0, x1, y1;
@@ -49,18 +63,16 @@ constexpr unsigned kConj0 = 1u << 27;
 constexpr unsigned kConj1 = 1u << 28;
 constexpr unsigned kWrapShift = 29;  // bit 29: the j1 neighbour wraps to angle 0
 
-// threads per block of the gather kernel (the columns per block follow from it)
-#ifndef BST_GATHER_THREADS
-#define BST_GATHER_THREADS 512
-#endif
-
 template <int LOGG>
 struct GatherCfg {
     static constexpr int G = 1 << LOGG;
-    static constexpr int T = G / 16;
+    static constexpr int E = BST_GATHER_E;
+    static constexpr int T = G / E;
     static constexpr int MAXT = BST_GATHER_THREADS > T ? BST_GATHER_THREADS : T;
-    static constexpr int F0 = 16384 / G > G / 2 ? G / 2 : 16384 / G;
-    static constexpr int F = F0 > 1 ? (T * F0 > MAXT ? MAXT / T : F0) : 1;  // columns per block
+    static constexpr int FL = 16384 / G;                 // LDS: about 140 KB of transforms
+    static constexpr int F1 = FL < G / 2 ? FL : G / 2;   // no more columns than exist
+    static constexpr int F2 = MAXT / T;
+    static constexpr int F = F1 < F2 ? F1 : F2;          // columns per block
     static constexpr int WG = F * T;
     // transform stride in LDS: padded length plus 8 float2, so that F regions
     // start 16 banks apart and lanes of different columns do not collide
@@ -120,9 +132,10 @@ __device__ __forceinline__ unsigned point_code(int col, int bs, const GatherArgs
 }
 
 template <int LOGG>
-__global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherArgs a) {
+__global__ void __launch_bounds__(GatherCfg<LOGG>::WG)
+__attribute__((amdgpu_waves_per_eu(BST_GATHER_WAVES, 8))) k_gather_colifft(GatherArgs a) {
     using C = GatherCfg<LOGG>;
-    constexpr int G = C::G, T = C::T, F = C::F;
+    constexpr int G = C::G, T = C::T, F = C::F, E = C::E;
     __shared__ float2 lds[F * C::STRIDE];
     __shared__ float red[(C::WG + 63) / 64];
     const int fid = threadIdx.x % F;
@@ -133,20 +146,20 @@ __global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherAr
     const bool live = col < G / 2;
 
     // Coordinates: computed in a rolled loop (one copy of the trigonometry in
-    // registers), staged through the still unused transform LDS in two halves
-    // of 8 points, then held in registers for the whole chunk.
-    unsigned code[16];
-    float fr[16], gr[16];
-    static_assert(C::F * C::STRIDE * 2 >= C::WG * 8 * 3, "coordinate staging needs LDS");
+    // registers), staged through the still unused transform LDS in chunks of
+    // 4 points, then held in registers for the whole chunk of slices.
+    constexpr int CH = 4;
+    unsigned code[E];
+    float fr[E], gr[E];
+    static_assert(C::F * C::STRIDE * 2 >= C::WG * CH * 3, "coordinate staging needs LDS");
     unsigned* st_code = reinterpret_cast<unsigned*>(lds);
-    float* st_f = reinterpret_cast<float*>(lds) + C::WG * 8;
-    float* st_g = st_f + C::WG * 8;
+    float* st_f = reinterpret_cast<float*>(lds) + C::WG * CH;
+    float* st_g = st_f + C::WG * CH;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    for (int c0 = 0; c0 < E; c0 += CH) {
 #pragma unroll 1
-        for (int h = 0; h < 8; ++h) {
-            const int e = half * 8 + h;
-            const int b = j + e * T;
+        for (int h = 0; h < CH; ++h) {
+            const int b = j + (c0 + h) * T;
             const int bs = b < G / 2 ? b : b - G;
             float f = 0.f, g = 0.f;
             const unsigned c = live ? point_code(col, bs, a, f, g) : kCodeZero;
@@ -155,10 +168,10 @@ __global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherAr
             st_g[h * C::WG + threadIdx.x] = g;
         }
 #pragma unroll
-        for (int h = 0; h < 8; ++h) {
-            code[half * 8 + h] = st_code[h * C::WG + threadIdx.x];
-            fr[half * 8 + h] = st_f[h * C::WG + threadIdx.x];
-            gr[half * 8 + h] = st_g[h * C::WG + threadIdx.x];
+        for (int h = 0; h < CH; ++h) {
+            code[c0 + h] = st_code[h * C::WG + threadIdx.x];
+            fr[c0 + h] = st_f[h * C::WG + threadIdx.x];
+            gr[c0 + h] = st_g[h * C::WG + threadIdx.x];
         }
     }
     __syncthreads();  // the transform reuses this LDS
@@ -175,27 +188,21 @@ __global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherAr
             for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)s * a.V + i];
             dcv = block_sum<C::WG>(acc, red) * a.dc_scale;
         }
-        float2 v[16];
+        float2 v[E];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < E; ++e) {
             const unsigned c = code[e];
             if (c < kCodeDc) {
                 const int j0 = c & 0x3FFF;
                 const int m0 = (c >> 14) & 0x1FFF;
                 const int o0 = j0 * S + m0;
                 const int o1 = ((c >> kWrapShift) & 1u) ? m0 : o0 + S;
-#if BST_GATHER_LD16
                 // samples m0 and m0+1 of a row are adjacent: one 16-byte load each
                 const Pair8 pa = *reinterpret_cast<const Pair8*>(P + o0);
                 const Pair8 pb = *reinterpret_cast<const Pair8*>(P + o1);
-                const float2 A0 = make_float2(pa.x0, pa.y0), A1 = make_float2(pa.x1, pa.y1);
-                const float2 B0 = make_float2(pb.x0, pb.y0), B1 = make_float2(pb.x1, pb.y1);
-#else
-                const float2 A0 = P[o0], A1 = P[o0 + 1], B0 = P[o1], B1 = P[o1 + 1];
-#endif
                 const float g = gr[e], f = fr[e];
-                float2 u0 = make_float2(fmaf(g, A1.x - A0.x, A0.x), fmaf(g, A1.y - A0.y, A0.y));
-                float2 u1 = make_float2(fmaf(g, B1.x - B0.x, B0.x), fmaf(g, B1.y - B0.y, B0.y));
+                float2 u0 = make_float2(fmaf(g, pa.x1 - pa.x0, pa.x0), fmaf(g, pa.y1 - pa.y0, pa.y0));
+                float2 u1 = make_float2(fmaf(g, pb.x1 - pb.x0, pb.x0), fmaf(g, pb.y1 - pb.y0, pb.y0));
                 if (c & kConj0) u0.y = -u0.y;
                 if (c & kConj1) u1.y = -u1.y;
                 v[e] = make_float2(fmaf(f, u1.x - u0.x, u0.x), fmaf(f, u1.y - u0.y, u0.y));
@@ -206,12 +213,12 @@ __global__ void __launch_bounds__(GatherCfg<LOGG>::WG) k_gather_colifft(GatherAr
             }
         }
 
-        fft<LOGG, +1>(v, my, j, a.tw);
+        fft<LOGG, +1, E>(v, my, j, a.tw);
 
         if (live) {
             float2* D = a.grid + (size_t)s * a.N * (G / 2);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
+            for (int e = 0; e < E; ++e) {
                 const int y = j + e * T;
                 const int p = (y + half_n) & (G - 1);
                 if (p < a.N) D[((size_t)(p >> 3) * (G / 2) + col) * 8 + (p & 7)] = v[e];

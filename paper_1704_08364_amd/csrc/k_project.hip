@@ -40,10 +40,11 @@ template <int LOGG>
 __global__ void __launch_bounds__(ProjRowCfg<LOGG>::WG) k_proj_rows(ProjRowArgs a) {
     using C = ProjRowCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
-    __shared__ float2 lds[C::F * FftShape<LOGG>::LDS];
+    constexpr int STRIDE = FftShape<LOGG>::LDS + 8;  // regions 16 banks apart
+    __shared__ float2 lds[C::F * STRIDE];
     const int fid = threadIdx.x % C::F;
     const int j = threadIdx.x / C::F;
-    float2* my = lds + fid * FftShape<LOGG>::LDS;
+    float2* my = lds + fid * STRIDE;
     const int row0 = blockIdx.x * (2 * C::F) + 2 * fid;
     const int s = blockIdx.y;
     const float* r0 = a.img + ((size_t)s * a.N + row0) * a.N;

@@ -15,11 +15,16 @@
 
 namespace bst {
 
+// row pairs per block for G <= 4096 (one 8-row tile is 4 pairs)
+#ifndef BST_ROW_PAIRS
+#define BST_ROW_PAIRS 4
+#endif
+
 template <int LOGG>
 struct RowCfg {
     static constexpr int G = 1 << LOGG;
     static constexpr int T = G / 16;
-    static constexpr int F = G <= 4096 ? 4 : (G == 8192 ? 2 : 1);  // row pairs per block
+    static constexpr int F = G <= 4096 ? BST_ROW_PAIRS : (G == 8192 ? 2 : 1);  // row pairs per block
     static constexpr int WG = F * T;
 };
 
@@ -27,12 +32,15 @@ template <int LOGG>
 __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     using C = RowCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
-    __shared__ float2 lds[C::F * FftShape<LOGG>::LDS];
+    // regions 8 float2 (16 banks) apart, so interleaved lanes of different row
+    // pairs fall on different banks
+    constexpr int STRIDE = FftShape<LOGG>::LDS + 8;
+    __shared__ float2 lds[C::F * STRIDE];
     // thread t serves row pair t mod F: the lanes of a wave read F neighbouring
     // 16-byte pairs of each k, i.e. contiguous runs of the [G/2][8] tile
     const int fid = threadIdx.x % C::F;
     const int j = threadIdx.x / C::F;
-    float2* my = lds + fid * FftShape<LOGG>::LDS;
+    float2* my = lds + fid * STRIDE;
     const int row0 = blockIdx.x * (2 * C::F) + 2 * fid;
     const int s = blockIdx.y;
     const int sub = row0 & 7;

@@ -15,6 +15,14 @@
 #include "bst_internal.h"
 #include "fft_lds.h"
 
+// groups of projection pairs each block walks (software-pipelined loads)
+#ifndef BST_SPEC_WAVES
+#define BST_SPEC_WAVES 4
+#endif
+#ifndef BST_SPEC_PAIRS
+#define BST_SPEC_PAIRS 1
+#endif
+
 namespace bst {
 
 template <int LOGM>
@@ -25,96 +33,147 @@ struct SpecCfg {
     static constexpr int WG = F * T;
 };
 
-template <int LOGM>
-__global__ void __launch_bounds__(SpecCfg<LOGM>::WG) k_spectrum(SpecArgs a) {
+// LOGP = log2(P_r). Thread j's padded positions k = j + e*T hold data only for
+// e < E0 or e >= 16 - E0 (E0 = 8 / P_r): the middle of every line is padding,
+// known at compile time, so it is never loaded.
+template <int LOGM, int LOGP>
+__global__ void __launch_bounds__(SpecCfg<LOGM>::WG) __attribute__((amdgpu_waves_per_eu(BST_SPEC_WAVES, 8)))
+k_spectrum(SpecArgs a) {
     using C = SpecCfg<LOGM>;
     constexpr int M = C::M, T = C::T;
+    constexpr int E0 = 8 >> LOGP;
     __shared__ float2 lds[C::F * FftShape<LOGM>::LDS];
     const int fid = threadIdx.x / T;
     const int j = threadIdx.x - fid * T;
     float2* my = lds + fid * FftShape<LOGM>::LDS;
-    const int pair = blockIdx.x * C::F + fid;
     const int s = blockIdx.y;
-    const int ja = 2 * pair, jb = 2 * pair + 1;
-    const bool va = ja < a.V, vb = jb < a.V;
     const int h = a.n >> 1;
-    const float* ya = a.sino + ((size_t)s * a.V + (va ? ja : 0)) * a.n;
-    const float* yb = a.sino + ((size_t)s * a.V + (vb ? jb : 0)) * a.n;
+    const bool counts = a.flat != nullptr;
+    const float* fl = counts ? a.flat + (size_t)s * a.n : nullptr;
+    const float* dkr = counts ? a.dark + (size_t)s * a.n : nullptr;
 
-    // raw counts: y = -log((I - D) / (I0 - D)) with the slice's flat/dark rows
-    const float* fl = a.flat ? a.flat + (size_t)s * a.n : nullptr;
-    const float* dk = a.flat ? a.dark + (size_t)s * a.n : nullptr;
-    float2 v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    // detector bin of data slot q (q < 2*E0): positions e = q (q < E0) and
+    // e = 16 - 2*E0 + q (q >= E0)
+    auto bin_of = [&](int q) {
+        const int e = q < E0 ? q : 16 - 2 * E0 + q;
         const int k = j + e * T;
-        const int i = (k < h) ? k + h : ((k >= M - h) ? k - M + h : -1);
-        float x = 0.f, y = 0.f;
-        if (i >= 0) {
+        return k < h ? k + h : k - M + h;
+    };
+    auto load = [&](int pair, float2 (&raw)[2 * E0]) {
+        const int ja = 2 * pair, jb = 2 * pair + 1;
+        const bool va = ja < a.V, vb = jb < a.V;
+        const float* ya = a.sino + ((size_t)s * a.V + (va ? ja : 0)) * a.n;
+        const float* yb = a.sino + ((size_t)s * a.V + (vb ? jb : 0)) * a.n;
+#pragma unroll
+        for (int q = 0; q < 2 * E0; ++q) {
+            const int i = bin_of(q);
+            raw[q] = make_float2(va ? ya[i] : 0.f, vb ? yb[i] : 0.f);
+        }
+    };
+
+    // Each block walks BST_SPEC_PAIRS groups of F projection pairs; the next
+    // group's loads are issued before the current group's transform so that
+    // they are in flight while it computes.
+    constexpr int PAIRS = BST_SPEC_PAIRS;
+    const int group0 = blockIdx.x * PAIRS;
+    float2 cur[2 * E0];
+    load(group0 * C::F + fid, cur);
+#pragma unroll 1
+    for (int it = 0; it < PAIRS; ++it) {
+        const int pair = (group0 + it) * C::F + fid;
+        float2 nxt[2 * E0];
+        if (it + 1 < PAIRS) load(pair + C::F, nxt);
+        const int ja = 2 * pair, jb = 2 * pair + 1;
+        const bool va = ja < a.V, vb = jb < a.V;
+
+        float2 v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < 2 * E0; ++q) {
+            const int i = bin_of(q);
             const float w = a.taper[i];
-            float ra = va ? ya[i] : 0.f, rb = vb ? yb[i] : 0.f;
-            if (fl) {
-                const float d = dk[i], inv = 1.0f / (fl[i] - d);
+            float ra = cur[q].x, rb = cur[q].y;
+            if (counts) {
+                // flat/dark normalisation, y = -log((I - D) / (I0 - D))
+                const float d = dkr[i], inv = 1.0f / (fl[i] - d);
                 ra = va ? -logf((ra - d) * inv) : 0.f;
                 rb = vb ? -logf((rb - d) * inv) : 0.f;
             }
-            x = w * ra;
-            y = w * rb;
+            v[q < E0 ? q : 16 - 2 * E0 + q] = make_float2(w * ra, w * rb);
         }
-        v[e] = make_float2(x, y);
-    }
 
-    fft<LOGM, -1>(v, my, j, a.tw);
+        fft<LOGM, -1>(v, my, j, a.tw);
 
 #pragma unroll
-    for (int e = 0; e < 16; ++e) my[lds_pad(j + e * T)] = v[e];
-    __syncthreads();
+        for (int e = 0; e < 16; ++e) my[lds_pad(j + e * T)] = v[e];
+        __syncthreads();
 
-    float2* pa = a.polar + ((size_t)s * a.V + ja) * a.S;
-    float2* pb = pa + a.S;
+        float2* pa = a.polar + ((size_t)s * a.V + ja) * a.S;
+        float2* pb = pa + a.S;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int m = j + e * T;  // 0 .. M/2-1
-        const float2 z = my[lds_pad(m)];
-        const float2 zc = my[lds_pad((M - m) & (M - 1))];
-        const float2 kc = a.kc[m];
-        const float2 ra = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc);
-        const float2 rb = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc);
-        if (va) pa[m] = ra;
-        if (vb) pb[m] = rb;
-    }
-    if (j < 2) {
-        if (va) pa[M / 2 + j] = make_float2(0.f, 0.f);
-        if (vb) pb[M / 2 + j] = make_float2(0.f, 0.f);
-    }
-    if (j == 0) {
-        const float2 z0 = my[0];
-        if (va) a.dc[(size_t)s * a.V + ja] = a.dt * z0.x;
-        if (vb) a.dc[(size_t)s * a.V + jb] = a.dt * z0.y;
+        for (int e = 0; e < 8; ++e) {
+            const int m = j + e * T;  // 0 .. M/2-1
+            const float2 z = my[lds_pad(m)];
+            const float2 zc = my[lds_pad((M - m) & (M - 1))];
+            const float2 kc = a.kc[m];
+            const float2 ra = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc);
+            const float2 rb = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc);
+            if (va) pa[m] = ra;
+            if (vb) pb[m] = rb;
+        }
+        if (j < 2) {
+            if (va) pa[M / 2 + j] = make_float2(0.f, 0.f);
+            if (vb) pb[M / 2 + j] = make_float2(0.f, 0.f);
+        }
+        if (j == 0) {
+            const float2 z0 = my[0];
+            if (va) a.dc[(size_t)s * a.V + ja] = a.dt * z0.x;
+            if (vb) a.dc[(size_t)s * a.V + jb] = a.dt * z0.y;
+        }
+        __syncthreads();  // the next transform overwrites this LDS
+#pragma unroll
+        for (int q = 0; q < 2 * E0; ++q) cur[q] = nxt[q];
     }
 }
 
-template <int LOGM>
+template <int LOGM, int LOGP>
 static hipError_t launch_spec_t(const SpecArgs& a, int batch, hipStream_t st) {
     using C = SpecCfg<LOGM>;
     const int pairs = (a.V + 1) / 2;
-    dim3 grid((pairs + C::F - 1) / C::F, batch);
-    hipLaunchKernelGGL(k_spectrum<LOGM>, grid, dim3(C::WG), 0, st, a);
+    const int groups = (pairs + C::F - 1) / C::F;
+    dim3 grid((groups + BST_SPEC_PAIRS - 1) / BST_SPEC_PAIRS, batch);
+    hipLaunchKernelGGL((k_spectrum<LOGM, LOGP>), grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }
 
+template <int LOGM>
+static hipError_t launch_spec_p(const SpecArgs& a, int pr, int batch, hipStream_t st) {
+    if constexpr (LOGM >= 4) {
+        if (pr == 1) return launch_spec_t<LOGM, 0>(a, batch, st);
+    }
+    if constexpr (LOGM >= 5) {
+        if (pr == 2) return launch_spec_t<LOGM, 1>(a, batch, st);
+    }
+    if constexpr (LOGM >= 6) {
+        if (pr == 4) return launch_spec_t<LOGM, 2>(a, batch, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st) {
+    const int pr = p.prm.pad_radial;
     switch (p.logM) {
-        case 4: return launch_spec_t<4>(a, batch, st);
-        case 5: return launch_spec_t<5>(a, batch, st);
-        case 6: return launch_spec_t<6>(a, batch, st);
-        case 7: return launch_spec_t<7>(a, batch, st);
-        case 8: return launch_spec_t<8>(a, batch, st);
-        case 9: return launch_spec_t<9>(a, batch, st);
-        case 10: return launch_spec_t<10>(a, batch, st);
-        case 11: return launch_spec_t<11>(a, batch, st);
-        case 12: return launch_spec_t<12>(a, batch, st);
-        case 13: return launch_spec_t<13>(a, batch, st);
+        case 4: return launch_spec_p<4>(a, pr, batch, st);
+        case 5: return launch_spec_p<5>(a, pr, batch, st);
+        case 6: return launch_spec_p<6>(a, pr, batch, st);
+        case 7: return launch_spec_p<7>(a, pr, batch, st);
+        case 8: return launch_spec_p<8>(a, pr, batch, st);
+        case 9: return launch_spec_p<9>(a, pr, batch, st);
+        case 10: return launch_spec_p<10>(a, pr, batch, st);
+        case 11: return launch_spec_p<11>(a, pr, batch, st);
+        case 12: return launch_spec_p<12>(a, pr, batch, st);
+        case 13: return launch_spec_p<13>(a, pr, batch, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -169,6 +169,55 @@ def ls_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def uneven_workload(args):
+    """Uneven-size batch: 512 sinograms, N drawn from {256, 512, 1024, 2048},
+    n_angles uniform in [N/2, 2N], random 2D ellipse phantoms, one graph
+    launch; the gather variant is tuned per size class first."""
+    import numpy as np
+    import torch
+
+    import paper_1704_08364_amd as P
+    import synth
+
+    rng = np.random.default_rng(170408368)
+    count = args.count
+    sizes = []
+    for _ in range(count):
+        n = int(rng.choice([256, 512, 1024, 2048]))
+        sizes.append((n, int(rng.integers(n // 2, 2 * n + 1))))
+    batch = P.Batch(sizes)
+    dev = "cuda:0"
+    sinos = torch.empty(batch.sino_elems, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(170408368)
+    log(f"generating {count} uneven sinograms ...")
+    for i, (n, v) in enumerate(sizes):
+        batch.sino_view(sinos, i).copy_(torch.randn(v, n, device=dev, generator=gen)
+                                        if args.input == "random" else
+                                        synth.batch_sinograms(1, n, v, 170408368 + i, device=dev)[0])
+    imgs = torch.empty(batch.img_elems, dtype=torch.float32, device=dev)
+    ws = batch.workspace()
+    t0 = time.perf_counter()
+    batch.tune(sinos, imgs, ws)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    for _ in range(max(args.warmup, 1)):
+        batch.backproject(sinos, imgs, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.backproject(sinos, imgs, ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t1) / args.steps
+    pix = sum(n * n for n, _ in sizes)
+    out = {"metric": "uneven-size BST batch in one graph launch", "value": round(count / el, 2),
+           "unit": "sinograms/s", "ms_per_step": round(el * 1e3, 3), "n_gpus": 1, "dtype": "f32",
+           "data": "synthetic", "classes": batch.classes(), "tune_seconds": round(tune_s, 2),
+           "equivalent_2048_slices_per_s": round(pix / (2048 * 2048) / el, 1),
+           "config": {"workload": f"{count} sinograms, N in {{256,512,1024,2048}}, V uniform in [N/2, 2N]"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,7 +230,8 @@ def main():
     ap.add_argument("--bf-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bruteforce", action="store_true")
-    ap.add_argument("--workload", choices=("batch", "volume", "ls"), default="batch",
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--workload", choices=("batch", "volume", "ls", "uneven"), default="batch",
                     help="batch: 64 x 2048^2 FBP (default); volume: the full 2048^3 volume; "
                          "ls: 32 x 1024^2 least squares by gradient descent")
     ap.add_argument("--slices", type=int, default=2048)
@@ -203,6 +253,8 @@ def main():
         return volume_workload(args)
     if args.workload == "ls":
         return ls_workload(args)
+    if args.workload == "uneven":
+        return uneven_workload(args)
 
     import numpy as np
     import torch

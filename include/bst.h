@@ -178,6 +178,32 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
 bst_status bst_debug_spectrum(bst_plan_t plan, const float* sino, void* spec, float* dc,
                               int32_t batch, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Uneven-size batches ------------------------------------------------
+ * Many sinograms of different sizes (n_det[i], n_angles[i]) in one graph
+ * launch; every other parameter comes from *base (uniform angles only).
+ * Instances of equal (n, V) form a class with its own plan and workspace
+ * region; classes run concurrently. Sinograms and images live in two packed
+ * device buffers at the element offsets sino_off[i] and img_off[i] (host
+ * arrays of `count`), each instance float32 [V_i][n_i] and [n_i][n_i].
+ * The first bst_batch_backproject with a given workspace captures all launches
+ * into a hipGraph; later calls only upload the pointer lists and replay it.
+ * Calls on one batch must not overlap in time (they share the pointer lists).
+ */
+typedef struct bst_batch_s* bst_batch_t;
+
+bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t* n_det,
+                            const int32_t* n_angles, bst_batch_t* out);
+bst_status bst_batch_workspace_size(bst_batch_t b, size_t* bytes);
+bst_status bst_batch_classes(bst_batch_t b, int32_t* n_classes);
+/* Time the gather kernel's variants (values per thread 8 or 16; 4 to 32 slices
+ * per block) for every class on these inputs, keep the fastest, and drop any
+ * captured graph. Synchronizes the stream. Outputs are overwritten. */
+bst_status bst_batch_tune(bst_batch_t b, const float* sinos, const int64_t* sino_off, float* imgs,
+                          const int64_t* img_off, void* ws, size_t ws_bytes, void* stream);
+bst_status bst_batch_backproject(bst_batch_t b, const float* sinos, const int64_t* sino_off, float* imgs,
+                                 const int64_t* img_off, void* ws, size_t ws_bytes, void* stream);
+bst_status bst_batch_destroy(bst_batch_t b);
+
 /* Free the plan's device tables and the plan. NULL is accepted. */
 bst_status bst_destroy(bst_plan_t plan);
 

@@ -6,6 +6,7 @@ include/bst.h) and its thin ctypes binding.
     img = plan.backproject(sino)            # sino: cuda float32 [B][V][n]
 """
 from .binding import (  # noqa: F401
+    Batch,
     BstError,
     BstNativeMissing,
     Event,

@@ -62,6 +62,12 @@ SIGNATURES = {
     "bst_event_destroy": (C.c_int, [_P]),
     "bst_event_elapsed_ms": (C.c_int, [_P, _P, C.POINTER(C.c_float)]),
     "bst_stream_synchronize": (C.c_int, [_P]),
+    "bst_batch_create": (C.c_int, [C.POINTER(bst_params), _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_P)]),
+    "bst_batch_workspace_size": (C.c_int, [_P, C.POINTER(_S)]),
+    "bst_batch_classes": (C.c_int, [_P, C.POINTER(_I)]),
+    "bst_batch_tune": (C.c_int, [_P, _P, C.POINTER(C.c_int64), _P, C.POINTER(C.c_int64), _P, _S, _P]),
+    "bst_batch_backproject": (C.c_int, [_P, _P, C.POINTER(C.c_int64), _P, C.POINTER(C.c_int64), _P, _S, _P]),
+    "bst_batch_destroy": (C.c_int, [_P]),
 }
 
 
@@ -300,3 +306,76 @@ class Plan:
         _check(lib().bst_project(self.handle, i3.data_ptr(), out.data_ptr(), B, workspace.data_ptr(),
                                  workspace.numel(), _stream_ptr(stream)), "bst_project")
         return out if img.dim() == 3 else out[0]
+
+
+class Batch:
+    """Uneven-size batch (bst_batch_*): sinograms of sizes (n_i, V_i) packed in
+    one float32 device buffer, images in another, run as one graph launch."""
+
+    def __init__(self, sizes, device: int = 0, **kw):
+        """sizes: sequence of (n_det, n_angles); other parameters as for Plan."""
+        self.sizes = [(int(n), int(v)) for n, v in sizes]
+        self.count = len(self.sizes)
+        self.params, self._keep = make_params(self.sizes[0][0], self.sizes[0][1], device=device, **kw)
+        n_arr = (C.c_int32 * self.count)(*[n for n, _ in self.sizes])
+        v_arr = (C.c_int32 * self.count)(*[v for _, v in self.sizes])
+        h = C.c_void_p()
+        _check(lib().bst_batch_create(C.byref(self.params), self.count, n_arr, v_arr, C.byref(h)),
+               "bst_batch_create")
+        self.handle = h
+        self.device = device
+        self.sino_off, self.img_off = [], []
+        so = io = 0
+        for n, v in self.sizes:
+            self.sino_off.append(so)
+            self.img_off.append(io)
+            so += v * n
+            io += n * n
+        self.sino_elems, self.img_elems = so, io
+        self._so = (C.c_int64 * self.count)(*self.sino_off)
+        self._io = (C.c_int64 * self.count)(*self.img_off)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bst_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def classes(self) -> int:
+        out = C.c_int32()
+        _check(lib().bst_batch_classes(self.handle, C.byref(out)), "bst_batch_classes")
+        return int(out.value)
+
+    def workspace(self):
+        import torch
+        out = C.c_size_t()
+        _check(lib().bst_batch_workspace_size(self.handle, C.byref(out)), "bst_batch_workspace_size")
+        return torch.empty(max(int(out.value), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def _args(self, sinos, imgs, workspace):
+        import torch
+        _dev_tensor(sinos, "sinos", torch.float32, (self.sino_elems,))
+        _dev_tensor(imgs, "imgs", torch.float32, (self.img_elems,))
+        return (self.handle, sinos.data_ptr(), self._so, imgs.data_ptr(), self._io,
+                workspace.data_ptr(), workspace.numel())
+
+    def tune(self, sinos, imgs, workspace, stream=None):
+        _check(lib().bst_batch_tune(*self._args(sinos, imgs, workspace), _stream_ptr(stream)), "bst_batch_tune")
+
+    def backproject(self, sinos, imgs, workspace, stream=None):
+        _check(lib().bst_batch_backproject(*self._args(sinos, imgs, workspace), _stream_ptr(stream)),
+               "bst_batch_backproject")
+        return imgs
+
+    def sino_view(self, sinos, i):
+        n, v = self.sizes[i]
+        return sinos[self.sino_off[i]:self.sino_off[i] + v * n].view(v, n)
+
+    def img_view(self, imgs, i):
+        n, _ = self.sizes[i]
+        return imgs[self.img_off[i]:self.img_off[i] + n * n].view(n, n)

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbst.so")
 
-SOURCES = ["bst_api.cpp", "plan_adjoint.cpp", "k_spectrum.hip", "k_gather_colifft.hip", "k_row_c2r.hip",
+SOURCES = ["bst_api.cpp", "plan_adjoint.cpp", "batch.cpp", "k_spectrum.hip", "k_gather_colifft.hip", "k_row_c2r.hip",
            "k_bruteforce.hip", "k_project.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

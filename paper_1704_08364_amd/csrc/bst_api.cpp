@@ -14,6 +14,10 @@
 #ifndef BST_GATHER_SLICES
 #define BST_GATHER_SLICES 16
 #endif
+// default values per thread of the gather kernel's column transform (8 or 16)
+#ifndef BST_GATHER_E
+#define BST_GATHER_E 8
+#endif
 
 namespace bst {
 bool build_adjoint_tables(int V, int M, int G, double rscale, std::vector<int>& off, std::vector<uint2>& ent);
@@ -72,6 +76,8 @@ struct DeviceGuard {
 }  // namespace
 
 namespace bst {
+
+void set_last_error(hipError_t e) { g_last_error = hipGetErrorString(e); }
 
 WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch) {
     (void)n;
@@ -206,6 +212,8 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->device = p->device;
     pl->adjoint = (p->adjoint != 0) && pl->uniform;
     pl->proj_scale = (float)(d * d / (pl->dt * (M_PI / pl->V)));
+    pl->gather_slices = BST_GATHER_SLICES;
+    pl->gather_e = BST_GATHER_E;
 
     // ---- FP64 tables ----
     const int n = pl->n, M = pl->M, G = pl->G, V = pl->V;
@@ -387,7 +395,8 @@ bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const vo
 bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
                            size_t ws_bytes, void* stream, void* const* ev, bool spectrum_only,
                            void* spec_out, float* dc_out, const float* flat = nullptr,
-                           const float* dark = nullptr) {
+                           const float* dark = nullptr, const float* const* sino_list = nullptr,
+                           float* const* img_list = nullptr) {
     if (!plan) return BST_E_NULL;
     const size_t in_bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
     const size_t out_bytes = (size_t)batch * plan->N * plan->N * sizeof(float);
@@ -418,7 +427,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         e = hipEventRecord(static_cast<hipEvent_t>(ev[0]), s);
         if (e != hipSuccess) return device_fail(e);
     }
-    bst::SpecArgs sa{sino, flat, dark, polar, dc, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
+    bst::SpecArgs sa{sino, sino_list, flat, dark, polar, dc, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
                      plan->S, (float)plan->dt};
     e = bst::launch_spectrum(*plan, sa, batch, s);
     if (e != hipSuccess) return device_fail(e);
@@ -445,7 +454,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.N = plan->N;
     ga.Mh = plan->M / 2;
     ga.batch = batch;
-    ga.slices_per_block = BST_GATHER_SLICES;
+    ga.slices_per_block = plan->gather_slices;
     ga.rscale = plan->rscale;
     ga.rscale_log2 = ilog2(plan->prm.pad_radial) - ilog2(plan->prm.pad_cart);
     ga.vpi_f = (float)plan->vpi;
@@ -457,7 +466,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         e = hipEventRecord(static_cast<hipEvent_t>(ev[2]), s);
         if (e != hipSuccess) return device_fail(e);
     }
-    bst::RowArgs ra{grid, img, plan->tw_G, plan->N, plan->out_scale};
+    bst::RowArgs ra{grid, img, img_list, plan->tw_G, plan->N, plan->out_scale};
     e = bst::launch_row_c2r(*plan, ra, batch, s);
     if (e != hipSuccess) return device_fail(e);
     if (ev && ev[3]) {

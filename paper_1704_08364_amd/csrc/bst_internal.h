@@ -35,9 +35,15 @@ struct bst_plan_s {
     uint2* csr_ent;      // [entries]    (point index a*G + b | conj << 31, weight bits)
     size_t n_entries;
     float proj_scale;    // d^2 / (dt * pi/V): makes R the weighted adjoint of B
+    int gather_slices;   // slices per gather block (coordinates reused across them)
+    int gather_e;        // values per thread of the column transform, 8 or 16: fewer
+                         // values mean less per-thread state and more resident waves
 };
 
 namespace bst {
+
+// record a HIP error for bst_last_error_string (calling thread)
+void set_last_error(hipError_t e);
 
 struct WsLayout {
     size_t polar_off, dc_off, grid_off, total;
@@ -50,7 +56,8 @@ struct ProjWsLayout {
 ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch);
 
 struct SpecArgs {
-    const float* sino;      // y, or raw counts when flat != nullptr
+    const float* sino;      // y, or raw counts when flat != nullptr; [batch][V][n]
+    const float* const* sino_list;  // or one pointer per slice (device array), if non-null
     const float* flat;      // [batch][n] or nullptr
     const float* dark;      // [batch][n]
     float2* polar;
@@ -78,7 +85,8 @@ struct GatherArgs {
 
 struct RowArgs {
     const float2* grid;
-    float* img;
+    float* img;                 // [batch][N][N]
+    float* const* img_list;     // or one pointer per slice (device array), if non-null
     const float2* tw;
     int N;
     float scale;

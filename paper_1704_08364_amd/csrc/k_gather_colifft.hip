@@ -35,12 +35,6 @@
 
 namespace bst {
 
-// values per thread of the column transform (8 or 16): fewer values mean less
-// per-thread state (interpolation coordinates, in-flight gathers) and more
-// resident waves
-#ifndef BST_GATHER_E
-#define BST_GATHER_E 8
-#endif
 // threads per block of the gather kernel (the columns per block follow from it)
 #ifndef BST_GATHER_THREADS
 #define BST_GATHER_THREADS 512
@@ -63,10 +57,10 @@ constexpr unsigned kConj0 = 1u << 27;
 constexpr unsigned kConj1 = 1u << 28;
 constexpr unsigned kWrapShift = 29;  // bit 29: the j1 neighbour wraps to angle 0
 
-template <int LOGG>
+template <int LOGG, int EV>
 struct GatherCfg {
     static constexpr int G = 1 << LOGG;
-    static constexpr int E = BST_GATHER_E;
+    static constexpr int E = EV;
     static constexpr int T = G / E;
     static constexpr int MAXT = BST_GATHER_THREADS > T ? BST_GATHER_THREADS : T;
     static constexpr int FL = 16384 / G;                 // LDS: about 140 KB of transforms
@@ -131,10 +125,10 @@ __device__ __forceinline__ unsigned point_code(int col, int bs, const GatherArgs
     return code;
 }
 
-template <int LOGG>
-__global__ void __launch_bounds__(GatherCfg<LOGG>::WG)
-__attribute__((amdgpu_waves_per_eu(BST_GATHER_WAVES, 8))) k_gather_colifft(GatherArgs a) {
-    using C = GatherCfg<LOGG>;
+template <int LOGG, int EV>
+__global__ void __launch_bounds__((GatherCfg<LOGG, EV>::WG))
+__attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather_colifft(GatherArgs a) {
+    using C = GatherCfg<LOGG, EV>;
     constexpr int G = C::G, T = C::T, F = C::F, E = C::E;
     __shared__ float2 lds[F * C::STRIDE];
     __shared__ float red[(C::WG + 63) / 64];
@@ -227,28 +221,35 @@ __attribute__((amdgpu_waves_per_eu(BST_GATHER_WAVES, 8))) k_gather_colifft(Gathe
     }
 }
 
-template <int LOGG>
+template <int LOGG, int EV>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
-    using C = GatherCfg<LOGG>;
+    using C = GatherCfg<LOGG, EV>;
     const int cols = C::G / 2;
     const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
     dim3 grid((cols + C::F - 1) / C::F, chunks);
-    hipLaunchKernelGGL(k_gather_colifft<LOGG>, grid, dim3(C::WG), 0, st, a);
+    hipLaunchKernelGGL((k_gather_colifft<LOGG, EV>), grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }
 
+template <int LOGG>
+static hipError_t launch_gather_e(const GatherArgs& a, int e, hipStream_t st) {
+    if (e == 16) return launch_gather_t<LOGG, 16>(a, st);
+    return launch_gather_t<LOGG, 8>(a, st);
+}
+
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st) {
+    const int e = p.gather_e;
     switch (p.logG) {
-        case 4: return launch_gather_t<4>(a, st);
-        case 5: return launch_gather_t<5>(a, st);
-        case 6: return launch_gather_t<6>(a, st);
-        case 7: return launch_gather_t<7>(a, st);
-        case 8: return launch_gather_t<8>(a, st);
-        case 9: return launch_gather_t<9>(a, st);
-        case 10: return launch_gather_t<10>(a, st);
-        case 11: return launch_gather_t<11>(a, st);
-        case 12: return launch_gather_t<12>(a, st);
-        case 13: return launch_gather_t<13>(a, st);
+        case 4: return launch_gather_e<4>(a, e, st);
+        case 5: return launch_gather_e<5>(a, e, st);
+        case 6: return launch_gather_e<6>(a, e, st);
+        case 7: return launch_gather_e<7>(a, e, st);
+        case 8: return launch_gather_e<8>(a, e, st);
+        case 9: return launch_gather_e<9>(a, e, st);
+        case 10: return launch_gather_e<10>(a, e, st);
+        case 11: return launch_gather_e<11>(a, e, st);
+        case 12: return launch_gather_e<12>(a, e, st);
+        case 13: return launch_gather_e<13>(a, e, st);
         default: return hipErrorInvalidValue;
     }
 }

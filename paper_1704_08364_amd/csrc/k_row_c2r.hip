@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
 
     fft<LOGG, +1>(v, my, j, a.tw);
 
-    float* o0 = a.img + ((size_t)s * a.N + row0) * a.N;
+    float* o0 = (a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N) + (size_t)row0 * a.N;
     float* o1 = o0 + a.N;
     const int half_n = a.N >> 1;
 #pragma unroll

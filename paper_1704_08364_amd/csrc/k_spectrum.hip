@@ -62,8 +62,9 @@ k_spectrum(SpecArgs a) {
     auto load = [&](int pair, float2 (&raw)[2 * E0]) {
         const int ja = 2 * pair, jb = 2 * pair + 1;
         const bool va = ja < a.V, vb = jb < a.V;
-        const float* ya = a.sino + ((size_t)s * a.V + (va ? ja : 0)) * a.n;
-        const float* yb = a.sino + ((size_t)s * a.V + (vb ? jb : 0)) * a.n;
+        const float* base = a.sino_list ? a.sino_list[s] : a.sino + (size_t)s * a.V * a.n;
+        const float* ya = base + (size_t)(va ? ja : 0) * a.n;
+        const float* yb = base + (size_t)(vb ? jb : 0) * a.n;
 #pragma unroll
         for (int q = 0; q < 2 * E0; ++q) {
             const int i = bin_of(q);

@@ -142,3 +142,16 @@ def test_adjoint_workspace_covers_both_directions():
     G = M = 2048
     proj = 8 * 8 * (N * G // 2 + G // 2 * G + V * M // 2)
     assert both >= plain and abs(both - max(plain, proj)) < 4 * 256
+
+
+def test_batch_create_validates_before_device_work():
+    L = P.lib()
+    p, _ = _params()
+    h = C.c_void_p()
+    n = (C.c_int32 * 3)(256, 512, 100)
+    v = (C.c_int32 * 3)(128, 256, 64)
+    assert L.bst_batch_create(None, 3, n, v, C.byref(h)) == 1
+    assert L.bst_batch_create(C.byref(p), 0, n, v, C.byref(h)) == 9
+    assert L.bst_batch_create(C.byref(p), 3, n, v, C.byref(h)) == 2  # 100 is not a power of two
+    assert h.value is None
+    assert L.bst_batch_destroy(None) == 0

@@ -426,3 +426,52 @@ def test_backproject_counts(P):
         y = obst.normalize(counts[b].double().cpu().numpy(), flat[b].double().cpu().numpy(),
                            dark[b].double().cpu().numpy())
         assert rel_l2(img[b].cpu().numpy(), obst.backproject(y, geom, obst.Params())) <= 1e-5
+
+
+# --- uneven-size batches (one graph launch) ------------------------------------
+
+def _uneven(B_sizes, seed):
+    from paper_1704_08364_amd import Batch
+    batch = Batch(B_sizes)
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(seed)
+    sinos = torch.empty(batch.sino_elems, dtype=torch.float32, device=DEV)
+    for i, (n, v) in enumerate(B_sizes):
+        batch.sino_view(sinos, i).copy_(synth.batch_sinograms(1, n, v, seed + i, device=DEV)[0])
+    imgs = torch.zeros(batch.img_elems, dtype=torch.float32, device=DEV)
+    return batch, sinos, imgs
+
+
+def test_uneven_batch_matches_oracle_and_replays(P):
+    sizes = [(64, 40), (128, 100), (64, 40), (256, 130), (128, 100), (64, 90), (256, 512), (128, 64)]
+    batch, sinos, imgs = _uneven(sizes, 77)
+    assert batch.classes() == 6
+    ws = batch.workspace()
+    batch.backproject(sinos, imgs, ws)           # captures the graph
+    torch.cuda.synchronize()
+    first = imgs.clone()
+    for i, (n, v) in enumerate(sizes):
+        _say(f"[uneven] instance {i}: n={n} V={v}")
+        ref = obst.backproject(batch.sino_view(sinos, i).double().cpu().numpy(), Geometry(n, v, n))
+        assert rel_l2(batch.img_view(imgs, i).cpu().numpy(), ref) <= 1e-5
+    # replays, with eager work and synchronisation in between, equal the first run
+    for r in range(3):
+        imgs.zero_()
+        _ = (sinos * 2.0).sum()
+        torch.cuda.synchronize()
+        batch.backproject(sinos, imgs, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(imgs, first), f"replay {r}"
+
+
+def test_uneven_batch_tuned(P):
+    sizes = [(128, 96), (256, 200), (128, 96), (512, 300)]
+    batch, sinos, imgs = _uneven(sizes, 91)
+    ws = batch.workspace()
+    batch.tune(sinos, imgs, ws)
+    imgs.zero_()
+    batch.backproject(sinos, imgs, ws)
+    torch.cuda.synchronize()
+    for i, (n, v) in enumerate(sizes):
+        ref = obst.backproject(batch.sino_view(sinos, i).double().cpu().numpy(), Geometry(n, v, n))
+        assert rel_l2(batch.img_view(imgs, i).cpu().numpy(), ref) <= 1e-5

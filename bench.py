@@ -114,6 +114,8 @@ def volume_workload(args):
         s_k = -1.0 + (k + 0.5) * 2.0 / S
         y = synth.ellipse_sinogram(geom, synth.ellipsoid_slice_ellipses(params, s_k), dev)
         sino[k] = synth.poisson_like_noise(y, 1e5, gen).to(torch.float32) if float(y.max()) > 0 else 0.0
+        if k % 256 == 255:
+            log(f"  {k + 1} slices")
     torch.cuda.synchronize()
     log(f"  {time.perf_counter() - t0:.1f} s")
     img = torch.empty(S, N, N, dtype=torch.float32, device=dev)

@@ -12,7 +12,7 @@
 
 // slices per gather block: the interpolation coordinates are computed once per block
 #ifndef BST_GATHER_SLICES
-#define BST_GATHER_SLICES 16
+#define BST_GATHER_SLICES 32
 #endif
 // default values per thread of the gather kernel's column transform (8 or 16)
 #ifndef BST_GATHER_E
@@ -456,7 +456,6 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.batch = batch;
     ga.slices_per_block = plan->gather_slices;
     ga.rscale = plan->rscale;
-    ga.rscale_log2 = ilog2(plan->prm.pad_radial) - ilog2(plan->prm.pad_cart);
     ga.vpi_f = (float)plan->vpi;
     ga.ang = plan->ang;
     ga.dc_scale = plan->dc_scale;

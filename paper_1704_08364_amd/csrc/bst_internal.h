@@ -77,7 +77,6 @@ struct GatherArgs {
     int V, S, N, Mh;
     int batch, slices_per_block;
     double rscale;
-    int rscale_log2;         // log2(P_r / P_c) in [-2, 2]
     float vpi_f;             // V / pi
     float dc_scale;
     const double2* ang;      // [V] (cos theta_j, sin theta_j)

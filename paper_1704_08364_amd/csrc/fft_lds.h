@@ -12,7 +12,10 @@
 // from a table tw[k] = exp(-2 pi i k / L) computed in FP64 on the host and
 // rounded to FP32; the other powers w^r are products of its squarings (at most
 // six roundings deep), which replaces R-1 scattered table reads by one
-// coalesced read. The inverse direction conjugates them.
+// coalesced read. The inverse direction conjugates them. The anchors of all
+// passes are read together before the first pass (FftTwiddles), so no pass
+// waits on a table read, and a thread that runs many transforms of one length
+// can read them once and keep them in registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -106,26 +109,24 @@ __device__ __forceinline__ void dft(float2* v) {
 // v[k + r*(16/R)] in this thread's registers -- twiddles it by
 // w^((jj mod NS) * r) with w = exp(DIR 2 pi i / (NS R)), transforms, and
 // writes output r to position (jj / NS) * NS * R + (jj mod NS) + r * NS.
+// anc[k]: the twiddle anchor of butterfly k, already conjugated for DIR > 0
 template <int L, int DIR, int R, int NS, int E>
-__device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j, const float2* anc) {
     constexpr int T = L / E;
     constexpr int BPT = E / R;
     constexpr bool LAST = (NS * R == L);
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int jj = j + k * T;
-        const int m = jj & (NS - 1);
         float2 x[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = v[k + r * BPT];
         if constexpr (NS > 1) {
-            // one table anchor w = tw[m * STEP] per butterfly; w^r is the product
-            // of the anchors' binary powers w, w^2, w^4, w^8 picked by the bits
-            // of r (at most three products after at most three squarings), formed
+            // one table anchor w per butterfly; w^r is the product of the
+            // anchor's binary powers w, w^2, w^4, w^8 picked by the bits of r
+            // (at most three products after at most three squarings), formed
             // just before use so that few twiddles are live at once
-            constexpr int STEP = L / (NS * R);
-            float2 w1 = tw[m * STEP];
-            if constexpr (DIR > 0) w1.y = -w1.y;
+            const float2 w1 = anc[k];
             float2 w2 = w1, w4 = w1, w8 = w1;
             if constexpr (R >= 4) w2 = cmul(w1, w1);
             if constexpr (R >= 8) w4 = cmul(w2, w2);
@@ -146,7 +147,7 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j
 #pragma unroll
             for (int r = 0; r < R; ++r) v[k + r * BPT] = x[r];
         } else {
-            const int base = (jj / NS) * NS * R + m;
+            const int base = (jj / NS) * NS * R + (jj & (NS - 1));
 #pragma unroll
             for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = x[r];
         }
@@ -159,11 +160,59 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j
     }
 }
 
-template <int L, int DIR, int R, int NS, int E>
-__device__ __forceinline__ void radix_passes(float2 (&v)[E], float2* lds, int j, const float2* tw) {
+// Twiddle anchors of every pass of one transform of length 2^LOGL held by
+// threads with E values each (the pass plan of fft below): w[p][k] belongs to
+// butterfly k of the p-th pass that has twiddles (the first pass has none).
+template <int LOGL, int DIR, int E>
+struct FftTwiddles {
+    static constexpr int L = 1 << LOGL;
+    static constexpr int T = L / E;
+    static constexpr int LR = E >= 16 ? 4 : 3;           // log2 of the main radix
+    static constexpr int R = 1 << LR;
+    static constexpr int REM = LOGL % LR;
+    static constexpr int NS0 = REM != 0 ? (1 << REM) : R;  // NS of the first twiddled pass
+    static constexpr int BPT = E / R;
+    static constexpr int count() {
+        int c = 0;
+        for (int ns = NS0; ns < L; ns *= R) ++c;
+        return c;
+    }
+    static constexpr int NT = count();
+    float2 w[NT > 0 ? NT : 1][BPT];
+
+    __device__ __forceinline__ FftTwiddles(int j, const float2* __restrict__ tw) {
+#pragma unroll
+        for (int p = 0; p < NT; ++p) {
+            const int ns = NS0 << (LR * p);
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                const int m = (j + k * T) & (ns - 1);
+                float2 x = tw[m * (L / (ns * R))];
+                if constexpr (DIR > 0) x.y = -x.y;
+                w[p][k] = x;
+            }
+        }
+    }
+
+    // Make the anchors opaque to the optimiser at this point. A caller that
+    // runs one transform per loop iteration with loop-invariant anchors calls
+    // this on a copy inside the loop; otherwise every derived power w^r is
+    // hoisted out of the loop and held in registers for its whole length.
+    __device__ __forceinline__ void pin() {
+#pragma unroll
+        for (int p = 0; p < NT; ++p) {
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) asm volatile("" : "+v"(w[p][k].x), "+v"(w[p][k].y));
+        }
+    }
+};
+
+template <int LOGL, int DIR, int R, int NS, int E, int P>
+__device__ __forceinline__ void radix_passes(float2 (&v)[E], float2* lds, int j, const FftTwiddles<LOGL, DIR, E>& tw) {
+    constexpr int L = 1 << LOGL;
     if constexpr (NS < L) {
-        stockham_pass<L, DIR, R, NS, E>(v, lds, j, tw);
-        radix_passes<L, DIR, R, NS * R, E>(v, lds, j, tw);
+        stockham_pass<L, DIR, R, NS, E>(v, lds, j, tw.w[P]);
+        radix_passes<LOGL, DIR, R, NS * R, E, (NS > 1 ? P + 1 : P)>(v, lds, j, tw);
     }
 }
 
@@ -173,18 +222,23 @@ __device__ __forceinline__ void radix_passes(float2 (&v)[E], float2* lds, int j,
 // hold lds_pad(L) float2 for this transform and not be read by anyone else
 // meanwhile. Ends with a barrier if any LDS exchange happened.
 template <int LOGL, int DIR, int E = 16>
-__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const FftTwiddles<LOGL, DIR, E>& tw) {
     static_assert(E == 8 || E == 16 || E == 32, "8, 16 or 32 values per thread");
+    using TW = FftTwiddles<LOGL, DIR, E>;
     constexpr int L = 1 << LOGL;
-    constexpr int LR = E >= 16 ? 4 : 3;     // log2 of the main radix
-    constexpr int R = 1 << LR;
-    constexpr int REM = LOGL % LR;
-    if constexpr (REM != 0) {
-        stockham_pass<L, DIR, (1 << REM), 1, E>(v, lds, j, tw);
-        radix_passes<L, DIR, R, (1 << REM), E>(v, lds, j, tw);
+    if constexpr (TW::REM != 0) {
+        stockham_pass<L, DIR, (1 << TW::REM), 1, E>(v, lds, j, tw.w[0]);
+        radix_passes<LOGL, DIR, TW::R, (1 << TW::REM), E, 0>(v, lds, j, tw);
     } else {
-        radix_passes<L, DIR, R, 1, E>(v, lds, j, tw);
+        radix_passes<LOGL, DIR, TW::R, 1, E, 0>(v, lds, j, tw);
     }
+}
+
+// The same, reading the twiddle anchors from the table first.
+template <int LOGL, int DIR, int E = 16>
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
+    const FftTwiddles<LOGL, DIR, E> t(j, tw);
+    fft<LOGL, DIR, E>(v, lds, j, t);
 }
 
 // Blocks of a 1D grid are dispatched round-robin over the 8 XCDs of an

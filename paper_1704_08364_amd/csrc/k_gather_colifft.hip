@@ -37,7 +37,7 @@ namespace bst {
 
 // threads per block of the gather kernel (the columns per block follow from it)
 #ifndef BST_GATHER_THREADS
-#define BST_GATHER_THREADS 512
+#define BST_GATHER_THREADS 1024
 #endif
 
 // waves per SIMD the register allocation must leave room for
@@ -50,12 +50,20 @@ struct __attribute__((aligned(8))) Pair8 {
     float x0, y0, x1, y1;
 };
 
-// point code: bits 0-13 j0, 14-26 m0, 27 conjugate the j0 samples, 28 conjugate the j1 samples
-constexpr unsigned kCodeZero = 0xFFFFFFFFu;
-constexpr unsigned kCodeDc = 0xFFFFFFFEu;
-constexpr unsigned kConj0 = 1u << 27;
-constexpr unsigned kConj1 = 1u << 28;
-constexpr unsigned kWrapShift = 29;  // bit 29: the j1 neighbour wraps to angle 0
+// Word 3 of a CDNA buffer resource for plain dword data (32-bit data format,
+// no swizzle, raw offsets).
+constexpr int kBufferWord3 = 0x00020000;
+
+// One slice's polar block as a buffer resource: loads take a 32-bit byte
+// offset in one VGPR against a base held in SGPRs, and read 0 past the end.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t polar_rsrc(const float2* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), 0, bytes, kBufferWord3);
+}
+
+__device__ __forceinline__ Pair8 load_pair(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return Pair8{__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3])};
+}
 
 template <int LOGG, int EV>
 struct GatherCfg {
@@ -89,16 +97,32 @@ __device__ float block_sum(float x, float* red) {
     return t;
 }
 
-// Interpolation coordinates of Cartesian point (col, bs); bs signed.
-__device__ __forceinline__ unsigned point_code(int col, int bs, const GatherArgs& a, float& f_out, float& g_out) {
-    f_out = 0.f;
-    g_out = 0.f;
-    if (col == 0 && bs == 0) return kCodeDc;
+// Interpolation stencil of one Cartesian point, fixed for all slices:
+//   o0, o1  byte offsets (inside one slice's polar block) of the sample pairs
+//           (j0, m0..m0+1) and (j1, m0..m0+1);
+//   g       radial fraction;
+//   w1      angular weight f of the j1 pair, negative when that pair is
+//           conjugated. The j0 pair has weight 1 - f and is conjugated
+//           exactly for the lower half-plane b < 0, which is known at compile
+//           time from the point's slot in the thread.
+// Points outside the radial data (and the origin, which the DC rule sets
+// afterwards) point both offsets at the two zero slots that end row 0, so
+// every point runs the same branch-free code.
+struct Stencil {
+    unsigned o0, o1;
+    float g, w1;
+};
+
+// Stencil of Cartesian point (col, bs); bs signed.
+__device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a) {
+    Stencil st;
+    st.o0 = st.o1 = (unsigned)a.Mh * sizeof(float2);
+    st.g = st.w1 = 0.f;
+    if (col == 0 && bs == 0) return st;
     const double r = sqrt((double)(col * col + bs * bs)) * a.rscale;
-    if (r >= (double)a.Mh) return kCodeZero;
+    if (r >= (double)a.Mh) return st;
     const double mf = floor(r);
-    g_out = (float)(r - mf);
-    const unsigned m0 = (unsigned)mf;
+    const int m0 = (int)mf;
 
     // direction of the point on [0, pi): (x, y) with y >= 0
     const bool lower = bs < 0;
@@ -116,13 +140,14 @@ __device__ __forceinline__ unsigned point_code(int col, int bs, const GatherArgs
     } else if (f >= 1.f) {
         if (j0 < a.V - 1) { j0 += 1; f -= 1.f; } else { f = 1.f; }
     }
-    f_out = f;
+    // past theta_{V-1} the neighbour is theta_0 with the conjugation flipped
     const bool wrap = (j0 + 1 == a.V);
-    unsigned code = (unsigned)j0 | (m0 << 14);
-    if (lower) code |= kConj0;
-    if (lower != wrap) code |= kConj1;
-    if (wrap) code |= 1u << kWrapShift;
-    return code;
+    const bool conj1 = lower != wrap;
+    st.o0 = (unsigned)(j0 * a.S + m0) * sizeof(float2);
+    st.o1 = (unsigned)((wrap ? 0 : j0 + 1) * a.S + m0) * sizeof(float2);
+    st.g = (float)(r - mf);
+    st.w1 = conj1 ? -f : f;
+    return st;
 }
 
 template <int LOGG, int EV>
@@ -138,34 +163,36 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
     const int lblock = xcd_contiguous(blockIdx.x, gridDim.x);
     const int col = lblock * F + fid;
     const bool live = col < G / 2;
+    const FftTwiddles<LOGG, +1, E> tw(j, a.tw);
 
-    // Coordinates: computed in a rolled loop (one copy of the trigonometry in
+    // Stencils: computed in a rolled loop (one copy of the trigonometry in
     // registers), staged through the still unused transform LDS in chunks of
-    // 4 points, then held in registers for the whole chunk of slices.
-    constexpr int CH = 4;
-    unsigned code[E];
-    float fr[E], gr[E];
-    static_assert(C::F * C::STRIDE * 2 >= C::WG * CH * 3, "coordinate staging needs LDS");
-    unsigned* st_code = reinterpret_cast<unsigned*>(lds);
-    float* st_f = reinterpret_cast<float*>(lds) + C::WG * CH;
-    float* st_g = st_f + C::WG * CH;
+    // CH points, then held in registers for the whole chunk of slices.
+    constexpr int CH = E == 8 ? 2 : 4;
+    constexpr int NW = 4;  // words per stencil
+    Stencil pt[E];
+    static_assert(C::F * C::STRIDE * 2 >= C::WG * CH * NW, "stencil staging needs LDS");
+    unsigned* stage = reinterpret_cast<unsigned*>(lds);
 #pragma unroll
     for (int c0 = 0; c0 < E; c0 += CH) {
 #pragma unroll 1
         for (int h = 0; h < CH; ++h) {
             const int b = j + (c0 + h) * T;
             const int bs = b < G / 2 ? b : b - G;
-            float f = 0.f, g = 0.f;
-            const unsigned c = live ? point_code(col, bs, a, f, g) : kCodeZero;
-            st_code[h * C::WG + threadIdx.x] = c;
-            st_f[h * C::WG + threadIdx.x] = f;
-            st_g[h * C::WG + threadIdx.x] = g;
+            const Stencil st = point_stencil(live ? col : 0, live ? bs : 0, a);
+            unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
+            d[0] = st.o0;
+            d[C::WG] = st.o1;
+            d[2 * C::WG] = __float_as_uint(st.g);
+            d[3 * C::WG] = __float_as_uint(st.w1);
         }
 #pragma unroll
         for (int h = 0; h < CH; ++h) {
-            code[c0 + h] = st_code[h * C::WG + threadIdx.x];
-            fr[c0 + h] = st_f[h * C::WG + threadIdx.x];
-            gr[c0 + h] = st_g[h * C::WG + threadIdx.x];
+            const unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
+            pt[c0 + h].o0 = d[0];
+            pt[c0 + h].o1 = d[C::WG];
+            pt[c0 + h].g = __uint_as_float(d[2 * C::WG]);
+            pt[c0 + h].w1 = __uint_as_float(d[3 * C::WG]);
         }
     }
     __syncthreads();  // the transform reuses this LDS
@@ -173,9 +200,21 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
     const int s_begin = blockIdx.y * a.slices_per_block;
     const int s_end = min(a.batch, s_begin + a.slices_per_block);
     const int half_n = a.N >> 1;
-    const int S = a.S;
+    const int slice_bytes = a.V * a.S * (int)sizeof(float2);
     for (int s = s_begin; s < s_end; ++s) {
-        const float2* P = a.polar + (size_t)s * a.V * S;
+        // Re-derive the lane's row index each slice: otherwise every address
+        // that depends on it (LDS passes, grid stores) is hoisted out of the
+        // loop and held in registers, which spills.
+        int jv = j;
+        asm volatile("" : "+v"(jv));
+        const __amdgpu_buffer_rsrc_t P = polar_rsrc(a.polar + (size_t)s * a.V * a.S, slice_bytes);
+        // all 2E sample-pair loads are issued before any is used
+        Pair8 pa[E], pb[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            pa[e] = load_pair(P, pt[e].o0);
+            pb[e] = load_pair(P, pt[e].o1);
+        }
         float dcv = 0.f;
         if (lblock == 0) {
             float acc = 0.f;
@@ -185,35 +224,28 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
         float2 v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const unsigned c = code[e];
-            if (c < kCodeDc) {
-                const int j0 = c & 0x3FFF;
-                const int m0 = (c >> 14) & 0x1FFF;
-                const int o0 = j0 * S + m0;
-                const int o1 = ((c >> kWrapShift) & 1u) ? m0 : o0 + S;
-                // samples m0 and m0+1 of a row are adjacent: one 16-byte load each
-                const Pair8 pa = *reinterpret_cast<const Pair8*>(P + o0);
-                const Pair8 pb = *reinterpret_cast<const Pair8*>(P + o1);
-                const float g = gr[e], f = fr[e];
-                float2 u0 = make_float2(fmaf(g, pa.x1 - pa.x0, pa.x0), fmaf(g, pa.y1 - pa.y0, pa.y0));
-                float2 u1 = make_float2(fmaf(g, pb.x1 - pb.x0, pb.x0), fmaf(g, pb.y1 - pb.y0, pb.y0));
-                if (c & kConj0) u0.y = -u0.y;
-                if (c & kConj1) u1.y = -u1.y;
-                v[e] = make_float2(fmaf(f, u1.x - u0.x, u0.x), fmaf(f, u1.y - u0.y, u0.y));
-            } else if (c == kCodeDc) {
-                v[e] = make_float2(dcv, 0.f);
-            } else {
-                v[e] = make_float2(0.f, 0.f);
-            }
+            // rows b = j + e*T with e >= E/2 are the lower half-plane (b - G < 0)
+            const float g = pt[e].g, w1 = pt[e].w1;
+            const float a0 = 1.f - fabsf(w1);
+            const float w0 = 2 * e >= E ? -a0 : a0;
+            const float u0x = fmaf(g, pa[e].x1 - pa[e].x0, pa[e].x0);
+            const float u0y = fmaf(g, pa[e].y1 - pa[e].y0, pa[e].y0);
+            const float u1x = fmaf(g, pb[e].x1 - pb[e].x0, pb[e].x0);
+            const float u1y = fmaf(g, pb[e].y1 - pb[e].y0, pb[e].y0);
+            v[e] = make_float2(fmaf(fabsf(w1), u1x, a0 * u0x), fmaf(w1, u1y, w0 * u0y));
         }
+        // origin: column 0, row 0 is thread j = 0's first point
+        if (col == 0 && jv == 0) v[0] = make_float2(dcv, 0.f);
 
-        fft<LOGG, +1, E>(v, my, j, a.tw);
+        FftTwiddles<LOGG, +1, E> twl = tw;
+        twl.pin();
+        fft<LOGG, +1, E>(v, my, jv, twl);
 
         if (live) {
             float2* D = a.grid + (size_t)s * a.N * (G / 2);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int y = j + e * T;
+                const int y = jv + e * T;
                 const int p = (y + half_n) & (G - 1);
                 if (p < a.N) D[((size_t)(p >> 3) * (G / 2) + col) * 8 + (p & 7)] = v[e];
             }

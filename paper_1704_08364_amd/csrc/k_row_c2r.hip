@@ -47,38 +47,40 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     const float4* tile = reinterpret_cast<const float4*>(
         a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * (G / 2));
 
+    // all loads first, branch-free: k < G/2 reads k, k > G/2 reads G - k
+    // (Hermitian extension), k = G/2 reads k = 0 and is replaced by zero
+    float4 q[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int k = j + e * T;
+        const int kk = k < G / 2 ? k : (k == G / 2 ? 0 : G - k);
+        q[e] = tile[kk * 4 + (sub >> 1)];
+    }
+    float* o0 = (a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N) + (size_t)row0 * a.N;
+    float* o1 = o0 + a.N;
+
     float2 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int k = j + e * T;
-        float2 x0, x1;
-        if (k < G / 2) {
-            const float4 q = tile[k * 4 + (sub >> 1)];
-            x0 = make_float2(q.x, k == 0 ? 0.f : q.y);
-            x1 = make_float2(q.z, k == 0 ? 0.f : q.w);
-        } else if (k == G / 2) {
-            x0 = make_float2(0.f, 0.f);
-            x1 = x0;
-        } else {
-            const float4 q = tile[(G - k) * 4 + (sub >> 1)];
-            x0 = make_float2(q.x, -q.y);
-            x1 = make_float2(q.z, -q.w);
-        }
+        const bool mid = k == G / 2;
+        // imaginary parts: dropped at k = 0 (C2R convention), conjugated for k > G/2
+        const float sy = (k == 0 || mid) ? 0.f : (k < G / 2 ? 1.f : -1.f);
+        const float2 x0 = make_float2(mid ? 0.f : q[e].x, sy * q[e].y);
+        const float2 x1 = make_float2(mid ? 0.f : q[e].z, sy * q[e].w);
         v[e] = make_float2(x0.x - x1.y, x0.y + x1.x);
     }
 
     fft<LOGG, +1>(v, my, j, a.tw);
 
-    float* o0 = (a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N) + (size_t)row0 * a.N;
-    float* o1 = o0 + a.N;
     const int half_n = a.N >> 1;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int x = j + e * T;
-        const int q = (x + half_n) & (G - 1);
-        if (q < a.N) {
-            o0[q] = v[e].x * a.scale;
-            o1[q] = v[e].y * a.scale;
+        const int c = (x + half_n) & (G - 1);
+        if (c < a.N) {
+            o0[c] = v[e].x * a.scale;
+            o1[c] = v[e].y * a.scale;
         }
     }
 }

@@ -15,12 +15,9 @@
 #include "bst_internal.h"
 #include "fft_lds.h"
 
-// groups of projection pairs each block walks (software-pipelined loads)
+// waves per SIMD the register allocation must leave room for
 #ifndef BST_SPEC_WAVES
 #define BST_SPEC_WAVES 4
-#endif
-#ifndef BST_SPEC_PAIRS
-#define BST_SPEC_PAIRS 1
 #endif
 
 namespace bst {
@@ -35,106 +32,104 @@ struct SpecCfg {
 
 // LOGP = log2(P_r). Thread j's padded positions k = j + e*T hold data only for
 // e < E0 or e >= 16 - E0 (E0 = 8 / P_r): the middle of every line is padding,
-// known at compile time, so it is never loaded.
-template <int LOGM, int LOGP>
+// known at compile time, so it is never loaded. COUNTS: the input is raw
+// counts with per-slice flat and dark fields.
+template <int LOGM, int LOGP, bool COUNTS>
 __global__ void __launch_bounds__(SpecCfg<LOGM>::WG) __attribute__((amdgpu_waves_per_eu(BST_SPEC_WAVES, 8)))
 k_spectrum(SpecArgs a) {
     using C = SpecCfg<LOGM>;
     constexpr int M = C::M, T = C::T;
     constexpr int E0 = 8 >> LOGP;
+    constexpr int NQ = 2 * E0;  // data slots per thread
     __shared__ float2 lds[C::F * FftShape<LOGM>::LDS];
     const int fid = threadIdx.x / T;
     const int j = threadIdx.x - fid * T;
     float2* my = lds + fid * FftShape<LOGM>::LDS;
     const int s = blockIdx.y;
     const int h = a.n >> 1;
-    const bool counts = a.flat != nullptr;
-    const float* fl = counts ? a.flat + (size_t)s * a.n : nullptr;
-    const float* dkr = counts ? a.dark + (size_t)s * a.n : nullptr;
+    const int pair = blockIdx.x * C::F + fid;
+    const int ja = 2 * pair, jb = 2 * pair + 1;
+    const bool va = ja < a.V, vb = jb < a.V;
 
-    // detector bin of data slot q (q < 2*E0): positions e = q (q < E0) and
-    // e = 16 - 2*E0 + q (q >= E0)
+    // detector bin of data slot q: positions e = q (q < E0) and e = 16 - 2*E0 + q (q >= E0)
     auto bin_of = [&](int q) {
         const int e = q < E0 ? q : 16 - 2 * E0 + q;
         const int k = j + e * T;
         return k < h ? k + h : k - M + h;
     };
-    auto load = [&](int pair, float2 (&raw)[2 * E0]) {
-        const int ja = 2 * pair, jb = 2 * pair + 1;
-        const bool va = ja < a.V, vb = jb < a.V;
-        const float* base = a.sino_list ? a.sino_list[s] : a.sino + (size_t)s * a.V * a.n;
-        const float* ya = base + (size_t)(va ? ja : 0) * a.n;
-        const float* yb = base + (size_t)(vb ? jb : 0) * a.n;
+
+    // Every global read of the thread is issued up front with no branch in
+    // between (a missing second line of an odd V reads line 0 and is dropped
+    // by a select): both lines' data slots, the taper, flat and dark, the
+    // epilogue weights and the twiddle anchors.
+    const float* base = a.sino_list ? a.sino_list[s] : a.sino + (size_t)s * a.V * a.n;
+    const float* ya = base + (size_t)(va ? ja : 0) * a.n;
+    const float* yb = base + (size_t)(vb ? jb : 0) * a.n;
+    float ra[NQ], rb[NQ], w[NQ];
 #pragma unroll
-        for (int q = 0; q < 2 * E0; ++q) {
+    for (int q = 0; q < NQ; ++q) {
+        const int i = bin_of(q);
+        ra[q] = ya[i];
+        rb[q] = yb[i];
+        w[q] = a.taper[i];
+    }
+    float dk[COUNTS ? NQ : 1], fl[COUNTS ? NQ : 1];
+    if constexpr (COUNTS) {
+        const float* fs = a.flat + (size_t)s * a.n;
+        const float* ds = a.dark + (size_t)s * a.n;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
             const int i = bin_of(q);
-            raw[q] = make_float2(va ? ya[i] : 0.f, vb ? yb[i] : 0.f);
+            fl[q] = fs[i];
+            dk[q] = ds[i];
         }
-    };
-
-    // Each block walks BST_SPEC_PAIRS groups of F projection pairs; the next
-    // group's loads are issued before the current group's transform so that
-    // they are in flight while it computes.
-    constexpr int PAIRS = BST_SPEC_PAIRS;
-    const int group0 = blockIdx.x * PAIRS;
-    float2 cur[2 * E0];
-    load(group0 * C::F + fid, cur);
-#pragma unroll 1
-    for (int it = 0; it < PAIRS; ++it) {
-        const int pair = (group0 + it) * C::F + fid;
-        float2 nxt[2 * E0];
-        if (it + 1 < PAIRS) load(pair + C::F, nxt);
-        const int ja = 2 * pair, jb = 2 * pair + 1;
-        const bool va = ja < a.V, vb = jb < a.V;
-
-        float2 v[16];
+    }
+    float2 kc[8];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = make_float2(0.f, 0.f);
+    for (int e = 0; e < 8; ++e) kc[e] = a.kc[j + e * T];
+    const FftTwiddles<LOGM, -1, 16> tw(j, a.tw);
+
+    float2 v[16];
 #pragma unroll
-        for (int q = 0; q < 2 * E0; ++q) {
-            const int i = bin_of(q);
-            const float w = a.taper[i];
-            float ra = cur[q].x, rb = cur[q].y;
-            if (counts) {
-                // flat/dark normalisation, y = -log((I - D) / (I0 - D))
-                const float d = dkr[i], inv = 1.0f / (fl[i] - d);
-                ra = va ? -logf((ra - d) * inv) : 0.f;
-                rb = vb ? -logf((rb - d) * inv) : 0.f;
-            }
-            v[q < E0 ? q : 16 - 2 * E0 + q] = make_float2(w * ra, w * rb);
+    for (int e = 0; e < 16; ++e) v[e] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        float xa = ra[q], xb = rb[q];
+        if constexpr (COUNTS) {
+            // flat/dark normalisation, y = -log((I - D) / (I0 - D))
+            const float inv = 1.0f / (fl[q] - dk[q]);
+            xa = -logf((xa - dk[q]) * inv);
+            xb = -logf((xb - dk[q]) * inv);
         }
+        v[q < E0 ? q : 16 - 2 * E0 + q] = make_float2(va ? w[q] * xa : 0.f, vb ? w[q] * xb : 0.f);
+    }
 
-        fft<LOGM, -1>(v, my, j, a.tw);
+    fft<LOGM, -1>(v, my, j, tw);
 
 #pragma unroll
-        for (int e = 0; e < 16; ++e) my[lds_pad(j + e * T)] = v[e];
-        __syncthreads();
+    for (int e = 0; e < 16; ++e) my[lds_pad(j + e * T)] = v[e];
+    __syncthreads();
 
-        float2* pa = a.polar + ((size_t)s * a.V + ja) * a.S;
-        float2* pb = pa + a.S;
+    float2* pa = a.polar + ((size_t)s * a.V + ja) * a.S;
+    float2* pb = pa + a.S;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int m = j + e * T;  // 0 .. M/2-1
-            const float2 z = my[lds_pad(m)];
-            const float2 zc = my[lds_pad((M - m) & (M - 1))];
-            const float2 kc = a.kc[m];
-            const float2 ra = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc);
-            const float2 rb = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc);
-            if (va) pa[m] = ra;
-            if (vb) pb[m] = rb;
-        }
-        if (j < 2) {
-            if (va) pa[M / 2 + j] = make_float2(0.f, 0.f);
-            if (vb) pb[M / 2 + j] = make_float2(0.f, 0.f);
-        }
-        if (j == 0) {
-            const float2 z0 = my[0];
-            if (va) a.dc[(size_t)s * a.V + ja] = a.dt * z0.x;
-            if (vb) a.dc[(size_t)s * a.V + jb] = a.dt * z0.y;
-        }
-        __syncthreads();  // the next transform overwrites this LDS
-#pragma unroll
-        for (int q = 0; q < 2 * E0; ++q) cur[q] = nxt[q];
+    for (int e = 0; e < 8; ++e) {
+        const int m = j + e * T;  // 0 .. M/2-1
+        const float2 z = my[lds_pad(m)];
+        const float2 zc = my[lds_pad((M - m) & (M - 1))];
+        const float2 ya2 = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[e]);
+        const float2 yb2 = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[e]);
+        if (va) pa[m] = ya2;
+        if (vb) pb[m] = yb2;
+    }
+    if (j < 2) {
+        if (va) pa[M / 2 + j] = make_float2(0.f, 0.f);
+        if (vb) pb[M / 2 + j] = make_float2(0.f, 0.f);
+    }
+    if (j == 0) {
+        const float2 z0 = my[0];
+        if (va) a.dc[(size_t)s * a.V + ja] = a.dt * z0.x;
+        if (vb) a.dc[(size_t)s * a.V + jb] = a.dt * z0.y;
     }
 }
 
@@ -142,9 +137,11 @@ template <int LOGM, int LOGP>
 static hipError_t launch_spec_t(const SpecArgs& a, int batch, hipStream_t st) {
     using C = SpecCfg<LOGM>;
     const int pairs = (a.V + 1) / 2;
-    const int groups = (pairs + C::F - 1) / C::F;
-    dim3 grid((groups + BST_SPEC_PAIRS - 1) / BST_SPEC_PAIRS, batch);
-    hipLaunchKernelGGL((k_spectrum<LOGM, LOGP>), grid, dim3(C::WG), 0, st, a);
+    dim3 grid((pairs + C::F - 1) / C::F, batch);
+    if (a.flat != nullptr)
+        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, true>), grid, dim3(C::WG), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, false>), grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }
 

@@ -99,6 +99,7 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     ga.tw = p.tw_G;
     ga.V = p.V;
     ga.S = p.S;
+    ga.GT = p.GT;
     ga.N = p.N;
     ga.Mh = p.M / 2;
     ga.batch = batch;
@@ -109,7 +110,7 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     ga.dc_scale = p.dc_scale;
     e = bst::launch_gather_colifft(p, ga, st);
     if (e != hipSuccess) return e;
-    bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.out_scale};
+    bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.GT, p.out_scale};
     return bst::launch_row_c2r(p, ra, batch, st);
 }
 

@@ -11,6 +11,7 @@ struct bst_plan_s {
     int M, G;            // radial FFT length P_r*n, Cartesian grid side P_c*N
     int logM, logG;
     int S;               // row stride of a polar spectrum, complex values: M/2 + 2
+    int GT;              // columns per 8-row tile row of the half-transformed grid: G/2
     bool uniform;        // angles are j*pi/V
     double dt, dk;
     double rscale;       // P_r / P_c: Cartesian index radius -> radial sample index
@@ -48,6 +49,9 @@ void set_last_error(hipError_t e);
 struct WsLayout {
     size_t polar_off, dc_off, grid_off, total;
 };
+// Row stride of a polar spectrum and tile-row width of the grid (complex values).
+int polar_stride(int M);
+int grid_width(int G);
 WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch);
 
 struct ProjWsLayout {
@@ -75,6 +79,7 @@ struct GatherArgs {
     float2* grid;
     const float2* tw;
     int V, S, N, Mh;
+    int GT;                  // grid tile-row width (columns)
     int batch, slices_per_block;
     double rscale;
     float vpi_f;             // V / pi
@@ -88,6 +93,7 @@ struct RowArgs {
     float* const* img_list;     // or one pointer per slice (device array), if non-null
     const float2* tw;
     int N;
+    int GT;                     // grid tile-row width (columns)
     float scale;
 };
 

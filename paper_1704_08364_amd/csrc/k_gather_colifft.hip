@@ -20,7 +20,8 @@
 //   the small angle in FP32), so the fraction f carries no cancellation.
 // Per slice, the column is gathered straight into the registers the FFT
 // starts from, inverse-transformed along b, and only the N rows that survive
-// the crop are written, to a grid laid out [N/8][G/2][8] (complex): the 8 rows
+// the crop are written, to a grid laid out [N/8][GT][8] (complex, GT >= G/2
+// columns per tile row): the 8 rows
 // of a tile and neighbouring columns form contiguous runs, and the row kernel
 // reads each 8-row tile contiguously.
 //
@@ -70,7 +71,10 @@ struct GatherCfg {
     static constexpr int G = 1 << LOGG;
     static constexpr int E = EV;
     static constexpr int T = G / E;
-    static constexpr int MAXT = BST_GATHER_THREADS > T ? BST_GATHER_THREADS : T;
+    // 16 values per thread need about twice the registers: two waves per
+    // SIMD, so blocks of at most 512 threads
+    static constexpr int CAP = E == 8 ? BST_GATHER_THREADS : 512;
+    static constexpr int MAXT = CAP > T ? CAP : T;
     static constexpr int FL = 16384 / G;                 // LDS: about 140 KB of transforms
     static constexpr int F1 = FL < G / 2 ? FL : G / 2;   // no more columns than exist
     static constexpr int F2 = MAXT / T;
@@ -98,25 +102,26 @@ __device__ float block_sum(float x, float* red) {
 }
 
 // Interpolation stencil of one Cartesian point, fixed for all slices:
-//   o0, o1  byte offsets (inside one slice's polar block) of the sample pairs
-//           (j0, m0..m0+1) and (j1, m0..m0+1);
-//   g       radial fraction;
+//   o0      byte offset (inside one slice's polar block) of the sample pair
+//           (j0, m0..m0+1); the pair (j1, m0..m0+1) is one polar row further,
+//           or, when j1 wraps to angle 0, (V-1) rows back;
+//   g       radial fraction, its sign bit set when j1 wraps;
 //   w1      angular weight f of the j1 pair, negative when that pair is
 //           conjugated. The j0 pair has weight 1 - f and is conjugated
 //           exactly for the lower half-plane b < 0, which is known at compile
 //           time from the point's slot in the thread.
 // Points outside the radial data (and the origin, which the DC rule sets
-// afterwards) point both offsets at the two zero slots that end row 0, so
-// every point runs the same branch-free code.
+// afterwards) point at the two zero slots that end rows 0 and 1, so every
+// point runs the same branch-free code.
 struct Stencil {
-    unsigned o0, o1;
+    unsigned o0;
     float g, w1;
 };
 
 // Stencil of Cartesian point (col, bs); bs signed.
 __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a) {
     Stencil st;
-    st.o0 = st.o1 = (unsigned)a.Mh * sizeof(float2);
+    st.o0 = (unsigned)a.Mh * sizeof(float2);
     st.g = st.w1 = 0.f;
     if (col == 0 && bs == 0) return st;
     const double r = sqrt((double)(col * col + bs * bs)) * a.rscale;
@@ -144,8 +149,7 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
     const bool wrap = (j0 + 1 == a.V);
     const bool conj1 = lower != wrap;
     st.o0 = (unsigned)(j0 * a.S + m0) * sizeof(float2);
-    st.o1 = (unsigned)((wrap ? 0 : j0 + 1) * a.S + m0) * sizeof(float2);
-    st.g = (float)(r - mf);
+    st.g = __uint_as_float(__float_as_uint((float)(r - mf)) | ((unsigned)wrap << 31));
     st.w1 = conj1 ? -f : f;
     return st;
 }
@@ -169,7 +173,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
     // registers), staged through the still unused transform LDS in chunks of
     // CH points, then held in registers for the whole chunk of slices.
     constexpr int CH = E == 8 ? 2 : 4;
-    constexpr int NW = 4;  // words per stencil
+    constexpr int NW = 3;  // words per stencil
     Stencil pt[E];
     static_assert(C::F * C::STRIDE * 2 >= C::WG * CH * NW, "stencil staging needs LDS");
     unsigned* stage = reinterpret_cast<unsigned*>(lds);
@@ -182,17 +186,15 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
             const Stencil st = point_stencil(live ? col : 0, live ? bs : 0, a);
             unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
             d[0] = st.o0;
-            d[C::WG] = st.o1;
-            d[2 * C::WG] = __float_as_uint(st.g);
-            d[3 * C::WG] = __float_as_uint(st.w1);
+            d[C::WG] = __float_as_uint(st.g);
+            d[2 * C::WG] = __float_as_uint(st.w1);
         }
 #pragma unroll
         for (int h = 0; h < CH; ++h) {
             const unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
             pt[c0 + h].o0 = d[0];
-            pt[c0 + h].o1 = d[C::WG];
-            pt[c0 + h].g = __uint_as_float(d[2 * C::WG]);
-            pt[c0 + h].w1 = __uint_as_float(d[3 * C::WG]);
+            pt[c0 + h].g = __uint_as_float(d[C::WG]);
+            pt[c0 + h].w1 = __uint_as_float(d[2 * C::WG]);
         }
     }
     __syncthreads();  // the transform reuses this LDS
@@ -201,6 +203,8 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
     const int s_end = min(a.batch, s_begin + a.slices_per_block);
     const int half_n = a.N >> 1;
     const int slice_bytes = a.V * a.S * (int)sizeof(float2);
+    const unsigned row_bytes = (unsigned)a.S * sizeof(float2);
+    const unsigned wrap_bytes = 0u - (unsigned)(a.V - 1) * row_bytes;  // back to row 0
     for (int s = s_begin; s < s_end; ++s) {
         // Re-derive the lane's row index each slice: otherwise every address
         // that depends on it (LDS passes, grid stores) is hoisted out of the
@@ -212,8 +216,9 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
         Pair8 pa[E], pb[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
+            const bool wrap = __float_as_uint(pt[e].g) >> 31;
             pa[e] = load_pair(P, pt[e].o0);
-            pb[e] = load_pair(P, pt[e].o1);
+            pb[e] = load_pair(P, pt[e].o0 + (wrap ? wrap_bytes : row_bytes));
         }
         float dcv = 0.f;
         if (lblock == 0) {
@@ -225,7 +230,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             // rows b = j + e*T with e >= E/2 are the lower half-plane (b - G < 0)
-            const float g = pt[e].g, w1 = pt[e].w1;
+            const float g = fabsf(pt[e].g), w1 = pt[e].w1;
             const float a0 = 1.f - fabsf(w1);
             const float w0 = 2 * e >= E ? -a0 : a0;
             const float u0x = fmaf(g, pa[e].x1 - pa[e].x0, pa[e].x0);
@@ -242,12 +247,12 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
         fft<LOGG, +1, E>(v, my, jv, twl);
 
         if (live) {
-            float2* D = a.grid + (size_t)s * a.N * (G / 2);
+            float2* D = a.grid + (size_t)s * a.N * a.GT;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int y = jv + e * T;
                 const int p = (y + half_n) & (G - 1);
-                if (p < a.N) D[((size_t)(p >> 3) * (G / 2) + col) * 8 + (p & 7)] = v[e];
+                if (p < a.N) D[((size_t)(p >> 3) * a.GT + col) * 8 + (p & 7)] = v[e];
             }
         }
     }

@@ -51,12 +51,21 @@ __global__ void __launch_bounds__(ProjRowCfg<LOGG>::WG) k_proj_rows(ProjRowArgs 
     const float* r1 = r0 + a.N;
     const int half_n = a.N >> 1;
 
+    // loads first, branch-free: columns outside the crop read column 0 and
+    // are replaced by zero
+    float x0[16], x1[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int q = (j + e * T + half_n) & (G - 1);
+        const int qq = q < a.N ? q : 0;
+        x0[e] = r0[qq];
+        x1[e] = r1[qq];
+    }
     float2 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int x = j + e * T;
-        const int q = (x + half_n) & (G - 1);
-        v[e] = q < a.N ? make_float2(r0[q], r1[q]) : make_float2(0.f, 0.f);
+        const int q = (j + e * T + half_n) & (G - 1);
+        v[e] = q < a.N ? make_float2(x0[e], x1[e]) : make_float2(0.f, 0.f);
     }
     fft<LOGG, -1>(v, my, j, a.tw);
 #pragma unroll
@@ -99,12 +108,20 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
     const float2* D = a.grid + (size_t)s * a.N * (G / 2);
     const int half_n = a.N >> 1;
 
+    // loads first, branch-free: rows outside the crop (and columns past the
+    // last) read a valid element and are replaced by zero
+    const int cc = live ? col : 0;
     float2 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int y = j + e * T;
-        const int p = (y + half_n) & (G - 1);
-        v[e] = (live && p < a.N) ? D[((size_t)(p >> 3) * (G / 2) + col) * 8 + (p & 7)] : make_float2(0.f, 0.f);
+        const int p = (j + e * T + half_n) & (G - 1);
+        const int pp = p < a.N ? p : 0;
+        v[e] = D[((size_t)(pp >> 3) * (G / 2) + cc) * 8 + (pp & 7)];
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int p = (j + e * T + half_n) & (G - 1);
+        if (!(live && p < a.N)) v[e] = make_float2(0.f, 0.f);
     }
     fft<LOGG, -1>(v, my, j, a.tw);
     if (live) {
@@ -125,20 +142,24 @@ __global__ void __launch_bounds__(256) k_proj_gather(ProjGatherArgs a) {
 #pragma unroll
     for (int k = 0; k < kProjSlices; ++k) acc[k] = make_float2(0.f, 0.f);
     const int e1 = a.off[idx + 1];
+    const float2* base = a.cart + (size_t)s0 * a.cart_stride;
+    // slices past the batch re-read the last one (their sums are dropped), so
+    // that every load is unconditional and all of an entry's loads are in flight together
+    size_t soff[kProjSlices];
+#pragma unroll
+    for (int k = 0; k < kProjSlices; ++k) soff[k] = (size_t)(k < ns ? k : ns - 1) * a.cart_stride;
     for (int e = a.off[idx]; e < e1; ++e) {
         const uint2 en = a.ent[e];
         const size_t pidx = en.x & 0x7FFFFFFFu;
-        const bool cj = (en.x >> 31) != 0u;
         const float w = __uint_as_float(en.y);
-        const float2* src = a.cart + (size_t)s0 * a.cart_stride + pidx;
+        const float wy = (en.x >> 31) != 0u ? -w : w;  // conjugation folded into the weight
+        float2 v[kProjSlices];
+#pragma unroll
+        for (int k = 0; k < kProjSlices; ++k) v[k] = base[soff[k] + pidx];
 #pragma unroll
         for (int k = 0; k < kProjSlices; ++k) {
-            if (k < ns) {
-                float2 v = src[(size_t)k * a.cart_stride];
-                if (cj) v.y = -v.y;
-                acc[k].x = fmaf(w, v.x, acc[k].x);
-                acc[k].y = fmaf(w, v.y, acc[k].y);
-            }
+            acc[k].x = fmaf(w, v[k].x, acc[k].x);
+            acc[k].y = fmaf(wy, v[k].y, acc[k].y);
         }
     }
 #pragma unroll
@@ -170,23 +191,35 @@ __global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG) k_proj_polar(ProjPolar
     const float2* PB = a.polar + ((size_t)s * a.V + (vb ? jb : 0)) * (M / 2);
     const float dct = a.dc_dt * a.cart[(size_t)s * a.cart_stride].x;
 
+    // loads first, branch-free: sample m = |k| of both projections and its
+    // weight; k = M/2 reads m = 0 and is replaced by zero
+    float2 xa[16], xb[16], wk[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int k = j + e * T;
+        const int m = k < M / 2 ? k : (k == M / 2 ? 0 : M - k);
+        xa[e] = PA[m];
+        xb[e] = PB[m];
+        wk[e] = a.kc[m];
+    }
     float2 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int k = j + e * T;
-        float2 ha = make_float2(0.f, 0.f), hb = ha;
+        const bool up = k < M / 2;
+        float2 ha, hb;
         if (k == 0) {
-            const float k0 = a.kc[0].x;  // real: the phase is 1 at sigma = 0
-            if (va) ha.x = k0 * PA[0].x + dct;
-            if (vb) hb.x = k0 * PB[0].x + dct;
-        } else if (k != M / 2) {
-            const bool up = k < M / 2;
-            const int m = up ? k : M - k;
-            float2 w = a.kc[m];
-            w = make_float2(0.5f * w.x, -0.5f * w.y);  // conj(weight)/2
-            if (va) { const float2 x = cmul(PA[m], w); ha = up ? x : make_float2(x.x, -x.y); }
-            if (vb) { const float2 x = cmul(PB[m], w); hb = up ? x : make_float2(x.x, -x.y); }
+            // the weight is real at sigma = 0 (phase 1); the origin rule adds dct
+            ha = make_float2(wk[e].x * xa[e].x + dct, 0.f);
+            hb = make_float2(wk[e].x * xb[e].x + dct, 0.f);
+        } else {
+            const float2 w = make_float2(0.5f * wk[e].x, -0.5f * wk[e].y);  // conj(weight)/2
+            const float2 ya = cmul(xa[e], w), yb = cmul(xb[e], w);
+            ha = up ? ya : make_float2(ya.x, -ya.y);
+            hb = up ? yb : make_float2(yb.x, -yb.y);
         }
+        if (k == M / 2 || !va) ha = make_float2(0.f, 0.f);
+        if (k == M / 2 || !vb) hb = make_float2(0.f, 0.f);
         v[e] = make_float2(ha.x - hb.y, ha.y + hb.x);
     }
     fft<LOGM, +1>(v, my, j, a.tw);

@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     const int s = blockIdx.y;
     const int sub = row0 & 7;
     const float4* tile = reinterpret_cast<const float4*>(
-        a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * (G / 2));
+        a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * a.GT);
 
     // all loads first, branch-free: k < G/2 reads k, k > G/2 reads G - k
     // (Hermitian extension), k = G/2 reads k = 0 and is replaced by zero

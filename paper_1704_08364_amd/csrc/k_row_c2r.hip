@@ -15,6 +15,11 @@
 
 namespace bst {
 
+// extra float2 between the LDS regions of a block's row pairs
+#ifndef BST_ROW_PAD
+#define BST_ROW_PAD 8
+#endif
+
 // row pairs per block for G <= 4096 (one 8-row tile is 4 pairs)
 #ifndef BST_ROW_PAIRS
 #define BST_ROW_PAIRS 4
@@ -34,7 +39,7 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     constexpr int G = C::G, T = C::T;
     // regions 8 float2 (16 banks) apart, so interleaved lanes of different row
     // pairs fall on different banks
-    constexpr int STRIDE = FftShape<LOGG>::LDS + 8;
+    constexpr int STRIDE = FftShape<LOGG>::LDS + BST_ROW_PAD;
     __shared__ float2 lds[C::F * STRIDE];
     // thread t serves row pair t mod F: the lanes of a wave read F neighbouring
     // 16-byte pairs of each k, i.e. contiguous runs of the [G/2][8] tile

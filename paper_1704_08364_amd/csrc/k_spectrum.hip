@@ -19,8 +19,18 @@
 #ifndef BST_SPEC_WAVES
 #define BST_SPEC_WAVES 4
 #endif
+// projection-pair groups per block: the next group's detector data is read
+// while the current group is transformed
+#ifndef BST_SPEC_PAIRS
+#define BST_SPEC_PAIRS 2
+#endif
 
 namespace bst {
+
+// Groups per block: the prefetch needs registers for one more group's data
+// slots, which only the P_r >= 2 plain-input variants have to spare.
+template <int LOGP, bool COUNTS>
+constexpr int spec_pairs() { return (LOGP >= 1 && !COUNTS) ? BST_SPEC_PAIRS : 1; }
 
 template <int LOGM>
 struct SpecCfg {
@@ -47,9 +57,8 @@ k_spectrum(SpecArgs a) {
     float2* my = lds + fid * FftShape<LOGM>::LDS;
     const int s = blockIdx.y;
     const int h = a.n >> 1;
-    const int pair = blockIdx.x * C::F + fid;
-    const int ja = 2 * pair, jb = 2 * pair + 1;
-    const bool va = ja < a.V, vb = jb < a.V;
+    constexpr int PAIRS = spec_pairs<LOGP, COUNTS>();
+    const int npairs = (a.V + 1) >> 1;
 
     // detector bin of data slot q: positions e = q (q < E0) and e = 16 - 2*E0 + q (q >= E0)
     auto bin_of = [&](int q) {
@@ -59,20 +68,27 @@ k_spectrum(SpecArgs a) {
     };
 
     // Every global read of the thread is issued up front with no branch in
-    // between (a missing second line of an odd V reads line 0 and is dropped
-    // by a select): both lines' data slots, the taper, flat and dark, the
-    // epilogue weights and the twiddle anchors.
+    // between: the data slots of both lines of the first group (a missing
+    // line -- an odd V, or a group past the end -- reads line 0 and is
+    // dropped by a select), the taper, flat and dark, the epilogue weights and
+    // the twiddle anchors; these last are the same for every group.
     const float* base = a.sino_list ? a.sino_list[s] : a.sino + (size_t)s * a.V * a.n;
-    const float* ya = base + (size_t)(va ? ja : 0) * a.n;
-    const float* yb = base + (size_t)(vb ? jb : 0) * a.n;
-    float ra[NQ], rb[NQ], w[NQ];
+    auto load_lines = [&](int pair, float (&ra)[NQ], float (&rb)[NQ]) {
+        const int ja = 2 * pair, jb = 2 * pair + 1;
+        const float* ya = base + (size_t)(ja < a.V ? ja : 0) * a.n;
+        const float* yb = base + (size_t)(jb < a.V ? jb : 0) * a.n;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int i = bin_of(q);
-        ra[q] = ya[i];
-        rb[q] = yb[i];
-        w[q] = a.taper[i];
-    }
+        for (int q = 0; q < NQ; ++q) {
+            const int i = bin_of(q);
+            ra[q] = ya[i];
+            rb[q] = yb[i];
+        }
+    };
+    float ra[NQ], rb[NQ], w[NQ];
+    const int pair0 = blockIdx.x * PAIRS * C::F + fid;
+    load_lines(pair0 < npairs ? pair0 : 0, ra, rb);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) w[q] = a.taper[bin_of(q)];
     float dk[COUNTS ? NQ : 1], fl[COUNTS ? NQ : 1];
     if constexpr (COUNTS) {
         const float* fs = a.flat + (size_t)s * a.n;
@@ -89,47 +105,73 @@ k_spectrum(SpecArgs a) {
     for (int e = 0; e < 8; ++e) kc[e] = a.kc[j + e * T];
     const FftTwiddles<LOGM, -1, 16> tw(j, a.tw);
 
-    float2 v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        float xa = ra[q], xb = rb[q];
-        if constexpr (COUNTS) {
-            // flat/dark normalisation, y = -log((I - D) / (I0 - D))
-            const float inv = 1.0f / (fl[q] - dk[q]);
-            xa = -logf((xa - dk[q]) * inv);
-            xb = -logf((xb - dk[q]) * inv);
+    for (int it = 0; it < PAIRS; ++it) {
+        const int pair = pair0 + it * C::F;
+        const int ja = 2 * pair, jb = 2 * pair + 1;
+        const bool va = ja < a.V, vb = jb < a.V;
+        float na[NQ], nb[NQ];
+        if (it + 1 < PAIRS) {
+            const int nx = pair + C::F;
+            load_lines(nx < npairs ? nx : 0, na, nb);
         }
-        v[q < E0 ? q : 16 - 2 * E0 + q] = make_float2(va ? w[q] * xa : 0.f, vb ? w[q] * xb : 0.f);
-    }
 
-    fft<LOGM, -1>(v, my, j, tw);
+        float2 v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            float xa = ra[q], xb = rb[q];
+            if constexpr (COUNTS) {
+                // flat/dark normalisation, y = -log((I - D) / (I0 - D))
+                const float inv = 1.0f / (fl[q] - dk[q]);
+                xa = -logf((xa - dk[q]) * inv);
+                xb = -logf((xb - dk[q]) * inv);
+            }
+            v[q < E0 ? q : 16 - 2 * E0 + q] = make_float2(va ? w[q] * xa : 0.f, vb ? w[q] * xb : 0.f);
+        }
+
+        // fresh copies per group, so that nothing derived from them is
+        // computed once and held across both transforms (that spills)
+        FftTwiddles<LOGM, -1, 16> twl = tw;
+        twl.pin();
+        int jv = j;
+        asm volatile("" : "+v"(jv));
+        fft<LOGM, -1>(v, my, jv, twl);
 
 #pragma unroll
-    for (int e = 0; e < 16; ++e) my[lds_pad(j + e * T)] = v[e];
-    __syncthreads();
+        for (int e = 0; e < 16; ++e) my[lds_pad(jv + e * T)] = v[e];
+        __syncthreads();
 
-    float2* pa = a.polar + ((size_t)s * a.V + ja) * a.S;
-    float2* pb = pa + a.S;
+        float2* pa = a.polar + ((size_t)s * a.V + ja) * a.S;
+        float2* pb = pa + a.S;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int m = j + e * T;  // 0 .. M/2-1
-        const float2 z = my[lds_pad(m)];
-        const float2 zc = my[lds_pad((M - m) & (M - 1))];
-        const float2 ya2 = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[e]);
-        const float2 yb2 = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[e]);
-        if (va) pa[m] = ya2;
-        if (vb) pb[m] = yb2;
-    }
-    if (j < 2) {
-        if (va) pa[M / 2 + j] = make_float2(0.f, 0.f);
-        if (vb) pb[M / 2 + j] = make_float2(0.f, 0.f);
-    }
-    if (j == 0) {
-        const float2 z0 = my[0];
-        if (va) a.dc[(size_t)s * a.V + ja] = a.dt * z0.x;
-        if (vb) a.dc[(size_t)s * a.V + jb] = a.dt * z0.y;
+        for (int e = 0; e < 8; ++e) {
+            const int m = jv + e * T;  // 0 .. M/2-1
+            const float2 z = my[lds_pad(m)];
+            const float2 zc = my[lds_pad((M - m) & (M - 1))];
+            const float2 ya2 = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[e]);
+            const float2 yb2 = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[e]);
+            if (va) pa[m] = ya2;
+            if (vb) pb[m] = yb2;
+        }
+        if (jv < 2) {
+            if (va) pa[M / 2 + jv] = make_float2(0.f, 0.f);
+            if (vb) pb[M / 2 + jv] = make_float2(0.f, 0.f);
+        }
+        if (jv == 0) {
+            const float2 z0 = my[0];
+            if (va) a.dc[(size_t)s * a.V + ja] = a.dt * z0.x;
+            if (vb) a.dc[(size_t)s * a.V + jb] = a.dt * z0.y;
+        }
+        if (it + 1 < PAIRS) {
+            __syncthreads();  // the next transform overwrites this LDS
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                ra[q] = na[q];
+                rb[q] = nb[q];
+            }
+        }
     }
 }
 
@@ -137,11 +179,14 @@ template <int LOGM, int LOGP>
 static hipError_t launch_spec_t(const SpecArgs& a, int batch, hipStream_t st) {
     using C = SpecCfg<LOGM>;
     const int pairs = (a.V + 1) / 2;
-    dim3 grid((pairs + C::F - 1) / C::F, batch);
-    if (a.flat != nullptr)
-        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, true>), grid, dim3(C::WG), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, false>), grid, dim3(C::WG), 0, st, a);
+    const int groups = (pairs + C::F - 1) / C::F;
+    if (a.flat != nullptr) {
+        constexpr int P = spec_pairs<LOGP, true>();
+        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, true>), dim3((groups + P - 1) / P, batch), dim3(C::WG), 0, st, a);
+    } else {
+        constexpr int P = spec_pairs<LOGP, false>();
+        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, false>), dim3((groups + P - 1) / P, batch), dim3(C::WG), 0, st, a);
+    }
     return hipGetLastError();
 }
 

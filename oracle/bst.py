@@ -14,7 +14,9 @@ Discrete steps (readings where the paper is silent are listed beside each):
       signed-sigma transform on [0, pi) stand for sigma > 0 on [0, 2 pi).
   P1  taper w[i] in t. Default: 1/sinc^2(t_i dsigma), which undoes the roll-off
       of linear interpolation along the radius in P5 (the paper names a
-      Kaiser-Bessel window without parameters; 'kb' and 'none' are options).
+      Kaiser-Bessel window without parameters; 'kb' and 'none' are options;
+      'keys' is 1 / Khat(t_i dsigma), the de-apodiser of cubic radial
+      interpolation, Khat the Fourier transform of the Keys kernel).
   P2  zero pad each projection from n to M = P_r n samples, t = 0 at index 0:
       z[(i - n/2) mod M] = w[i] y[i].
   P3  Y_j[m] = dt * sum_k z_j[k] exp(-2 pi i k m / M), m = 0..M/2,
@@ -26,7 +28,11 @@ Discrete steps (readings where the paper is silent are listed beside each):
       a in [0, G/2], b in [-G/2, G/2), G = P_c N, dk = 1/(G d); points on
       the lower half (b < 0) read theta + pi via the conjugate; the angle
       neighbour past theta_{V-1} is theta_0 with sigma reversed (conjugate);
-      radial samples m >= M/2 are zero. The origin takes its own rule:
+      radial samples m >= M/2 are zero. The paper asks only for "an
+      interpolation"; the option interp='keys' replaces the linear radial
+      weights by the Keys cubic convolution kernel (a = -1/2) over samples
+      m0-1 .. m0+2 (sample -1 is conj Yh[1], since Yh(-sigma) = conj Yh(sigma)),
+      keeping linear interpolation in angle. The origin takes its own rule:
       RAMP: mean_j Y_j[0]; NONE: (kappa / dk) mean_j Y_j[0], kappa = 4 asinh(1),
       the average of 1/|k| over the origin cell times dk.
   P6  2D inverse DFT over the Hermitian plane: b = dk^2 sum_k C[k] e^{+2 pi i k.x / G}
@@ -46,6 +52,7 @@ KAPPA = 4.0 * np.arcsinh(1.0)
 
 
 APODIZATIONS = ("ramlak", "shepp", "hann", "cosine")
+INTERPS = ("linear", "keys")
 
 
 class Params:
@@ -53,14 +60,16 @@ class Params:
     radial weight (the filtering stage F of Section 3 is named "low-pass");
     `center_shift` is a known rotation-axis offset beta in detector bins: the
     measured sinogram is y(t - beta dt, theta) (Section 1, centering), undone in
-    P4 by the phase exp(+2 pi i sigma beta dt)."""
+    P4 by the phase exp(+2 pi i sigma beta dt). `interp` is the radial
+    interpolation of P5: 'linear' or 'keys' (cubic convolution)."""
 
     def __init__(self, pad_radial: int = 2, pad_cart: int = 2, filter: str = "ramp",
                  taper: str = "deapod", beta: float = 8.0, apod: str = "ramlak",
-                 center_shift: float = 0.0):
+                 center_shift: float = 0.0, interp: str = "linear"):
         assert filter in ("ramp", "none")
-        assert taper in ("deapod", "none", "kb")
+        assert taper in ("deapod", "none", "kb", "keys")
         assert apod in APODIZATIONS
+        assert interp in INTERPS
         self.P_r = int(pad_radial)
         self.P_c = int(pad_cart)
         self.filter = filter
@@ -68,6 +77,7 @@ class Params:
         self.beta = float(beta)
         self.apod = apod
         self.center_shift = float(center_shift)
+        self.interp = interp
 
 
 def sizes(geom: Geometry, prm: Params):
@@ -78,12 +88,40 @@ def sizes(geom: Geometry, prm: Params):
     return M, G, dsig, dk
 
 
+# Keys cubic convolution kernel, a = -1/2 (Keys 1981): the interpolant
+# sum_k c_k W(x - k) passes through the samples and reproduces quadratics.
+KEYS_A = -0.5
+
+
+def keys_kernel(x: np.ndarray) -> np.ndarray:
+    a = KEYS_A
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    inner = (a + 2.0) * x ** 3 - (a + 3.0) * x ** 2 + 1.0
+    outer = a * x ** 3 - 5.0 * a * x ** 2 + 8.0 * a * x - 4.0 * a
+    return np.where(x <= 1.0, inner, np.where(x < 2.0, outer, 0.0))
+
+
+def keys_weights(frac: np.ndarray):
+    """Weights of samples m0-1, m0, m0+1, m0+2 for a point at m0 + frac."""
+    return (keys_kernel(1.0 + frac), keys_kernel(frac), keys_kernel(1.0 - frac), keys_kernel(2.0 - frac))
+
+
+def keys_ft(nu: np.ndarray) -> np.ndarray:
+    """Khat(nu) = int W(x) exp(-2 pi i nu x) dx for a = -1/2, in closed form:
+    sinc^3(nu) (3 sinc(nu) - 2 cos(pi nu)), sinc(nu) = sin(pi nu) / (pi nu)."""
+    nu = np.asarray(nu, dtype=np.float64)
+    s = np.sinc(nu)
+    return s ** 3 * (3.0 * s - 2.0 * np.cos(np.pi * nu))
+
+
 # P1 ---------------------------------------------------------------------------
 def taper(geom: Geometry, prm: Params) -> np.ndarray:
     M, _, dsig, _ = sizes(geom, prm)
     t = geom.t()
     if prm.taper == "deapod":
         return 1.0 / np.sinc(t * dsig) ** 2  # np.sinc(x) = sin(pi x) / (pi x)
+    if prm.taper == "keys":
+        return 1.0 / keys_ft(t * dsig)
     if prm.taper == "none":
         return np.ones_like(t)
     return bessel_i0(prm.beta * np.sqrt(np.clip(1.0 - t * t, 0.0, None))) / bessel_i0(prm.beta)
@@ -175,11 +213,19 @@ def gather(Yh: np.ndarray, Y0: np.ndarray, geom: Geometry, prm: Params) -> np.nd
     m1 = m0 + 1
 
     def S(j, m, conj):
-        v = ext[j, m]
-        return np.where(conj, np.conj(v), v)
+        # a sample at m < 0 is the conjugate of -m (the spectrum of a real line)
+        neg = m < 0
+        v = ext[j, np.where(neg, -m, m)]
+        return np.where(conj ^ neg, np.conj(v), v)
 
-    C = ((1 - f) * (1 - g) * S(j0, m0, c0) + (1 - f) * g * S(j0, m1, c0)
-         + f * (1 - g) * S(j1, m0, c1) + f * g * S(j1, m1, c1))
+    if prm.interp == "linear":
+        C = ((1 - f) * (1 - g) * S(j0, m0, c0) + (1 - f) * g * S(j0, m1, c0)
+             + f * (1 - g) * S(j1, m0, c1) + f * g * S(j1, m1, c1))
+    else:
+        C = np.zeros(r.shape, dtype=np.complex128)
+        for off, wr in zip((-1, 0, 1, 2), keys_weights(g)):
+            mm = np.minimum(m0 + off, M + 2)
+            C += wr * ((1 - f) * S(j0, mm, c0) + f * S(j1, mm, c1))
     mean0 = np.mean(Y0)
     if prm.filter == "ramp":
         C[0, 0] = mean0
@@ -289,6 +335,8 @@ def project(img: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndarray:
     prm = prm or Params()
     if not geom.uniform:
         raise NotImplementedError("the BST oracle takes uniform angles theta_j = j pi / V")
+    if prm.interp != "linear":
+        raise NotImplementedError("the projector is the transpose of the linear-interpolation BST")
     f = np.asarray(img, dtype=np.float64)
     assert f.shape == (geom.N, geom.N)
     M, G, _, dk = sizes(geom, prm)

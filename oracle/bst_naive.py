@@ -24,11 +24,23 @@ def _taper(t: float, dsig: float, kind: str) -> float:
         return 1.0
     x = math.pi * t * dsig
     s = 1.0 if x == 0.0 else math.sin(x) / x
+    if kind == "keys":
+        return 1.0 / (s ** 3 * (3.0 * s - 2.0 * math.cos(x)))
     return 1.0 / (s * s)
 
 
+def _keys(x: float) -> float:
+    """Keys cubic convolution weight at distance x, a = -1/2."""
+    x = abs(x)
+    if x <= 1.0:
+        return 1.5 * x ** 3 - 2.5 * x ** 2 + 1.0
+    if x < 2.0:
+        return -0.5 * x ** 3 + 2.5 * x ** 2 - 4.0 * x + 2.0
+    return 0.0
+
+
 def backproject(sino, geom: Geometry, P_r: int = 2, P_c: int = 2,
-                filter: str = "ramp", taper: str = "deapod") -> np.ndarray:
+                filter: str = "ramp", taper: str = "deapod", interp: str = "linear") -> np.ndarray:
     y = np.asarray(sino, dtype=np.float64)
     V, n, N = geom.V, geom.n, geom.N
     dt, d = geom.dt, geom.d
@@ -57,6 +69,8 @@ def backproject(sino, geom: Geometry, P_r: int = 2, P_c: int = 2,
             Yh[j][m] = w * acc
 
     def sample(j: int, m: int, conj: bool) -> complex:
+        if m < 0:  # the spectrum of a real line: Yh(-sigma) = conj Yh(sigma)
+            m, conj = -m, not conj
         if m >= half:
             return 0j
         v = Yh[j][m]
@@ -87,10 +101,17 @@ def backproject(sino, geom: Geometry, P_r: int = 2, P_c: int = 2,
                 j1, conj1 = 0, not conj
             m0 = int(math.floor(r))
             g = r - m0
-            C[bi][a] = ((1 - f) * (1 - g) * sample(j0, m0, conj)
-                        + (1 - f) * g * sample(j0, m0 + 1, conj)
-                        + f * (1 - g) * sample(j1, m0, conj1)
-                        + f * g * sample(j1, m0 + 1, conj1))
+            if interp == "linear":
+                C[bi][a] = ((1 - f) * (1 - g) * sample(j0, m0, conj)
+                            + (1 - f) * g * sample(j0, m0 + 1, conj)
+                            + f * (1 - g) * sample(j1, m0, conj1)
+                            + f * g * sample(j1, m0 + 1, conj1))
+            else:
+                acc = 0j
+                for mm in range(m0 - 1, m0 + 3):
+                    wr = _keys(r - mm)
+                    acc += wr * ((1 - f) * sample(j0, mm, conj) + f * sample(j1, mm, conj1))
+                C[bi][a] = acc
 
     # P6-P8: explicit real-linear inverse sum, evaluated only on the output pixels
     out = np.zeros((N, N))

@@ -34,7 +34,8 @@ Discrete steps (readings where the paper is silent are listed beside each):
       m0-1 .. m0+2 (sample -1 is conj Yh[1], since Yh(-sigma) = conj Yh(sigma)),
       keeping linear interpolation in angle. The origin takes its own rule:
       RAMP: mean_j Y_j[0]; NONE: (kappa / dk) mean_j Y_j[0], kappa = 4 asinh(1),
-      the average of 1/|k| over the origin cell times dk.
+      the average of 1/|k| over the origin cell times dk. The Nyquist column
+      a = G/2 is set to zero (like the radial Nyquist sample in P4).
   P6  2D inverse DFT over the Hermitian plane: b = dk^2 sum_k C[k] e^{+2 pi i k.x / G}
       (the C2R convention drops the imaginary parts of self-conjugate columns).
   P7  fftshift and P8 restriction to the N x N output grid:
@@ -231,6 +232,10 @@ def gather(Yh: np.ndarray, Y0: np.ndarray, geom: Geometry, prm: Params) -> np.nd
         C[0, 0] = mean0
     else:
         C[0, 0] = (KAPPA / dk) * mean0
+    # The Cartesian Nyquist column |k_x| = G/2 dk is dropped, as P4 drops the
+    # radial Nyquist sample. With linear radial taps it is zero anyway (its
+    # points lie at r >= M/2); the cubic taps reach one sample further in.
+    C[:, G // 2] = 0.0
     return C
 
 

@@ -81,6 +81,8 @@ def backproject(sino, geom: Geometry, P_r: int = 2, P_c: int = 2,
     for bi in range(G):
         b = bi if bi < G // 2 else bi - G
         for a in range(G // 2 + 1):
+            if a == G // 2:  # the Cartesian Nyquist column is dropped
+                continue
             if a == 0 and b == 0:
                 mean0 = sum(Y0) / V
                 C[bi][a] = mean0 if filter == "ramp" else (4.0 * math.asinh(1.0) / dk) * mean0

@@ -113,3 +113,23 @@ def test_projector_refuses_keys():
     g = Geometry(16, 8, 16)
     with pytest.raises(NotImplementedError):
         bst.project(np.zeros((16, 16)), g, bst.Params(interp="keys"))
+
+
+@pytest.mark.parametrize("interp", ["linear", "keys"])
+def test_cartesian_nyquist_column_is_zero(interp):
+    """The column |k_x| = G/2 dk is dropped (like the radial Nyquist sample):
+    with linear taps all its points already lie at r >= M/2 (P_r = P_c)."""
+    N, V = 16, 12
+    g = Geometry(N, V, N)
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((V, N))
+    prm = bst.Params(2, 2, "ramp", "none", interp=interp)
+    Yh, Y0 = bst.spectrum(y, g, prm)
+    C = bst.gather(Yh, Y0, g, prm)
+    M, G, _, _ = bst.sizes(g, prm)
+    assert np.all(C[:, G // 2] == 0)
+    if interp == "linear":
+        a = G // 2
+        b = np.arange(G)
+        b = np.where(b < G // 2, b, b - G)
+        assert np.all(np.hypot(a, b) * prm.P_r / prm.P_c >= M // 2)

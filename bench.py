@@ -75,7 +75,7 @@ def measured_traffic(kernel: str, config_key: str):
         return None
 
 
-def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices):
+def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear"):
     """FP64 oracle on `slices` slices of the same batch, single thread."""
     import numpy as np
 
@@ -83,8 +83,9 @@ def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices):
     from oracle.geometry import Geometry
 
     geom = Geometry(n, V, N)
+    prm = obst.Params(taper="keys", interp="keys") if interp == "keys" else obst.Params()
     t0 = time.perf_counter()
-    refs = [obst.backproject(sino_cpu[i], geom, obst.Params()) for i in range(slices)]
+    refs = [obst.backproject(sino_cpu[i], geom, prm) for i in range(slices)]
     dt = time.perf_counter() - t0
     errs = [float(np.linalg.norm(out_gpu_cpu[i] - refs[i]) / np.linalg.norm(refs[i])) for i in range(slices)]
     return slices / dt, dt, errs
@@ -237,6 +238,8 @@ def main():
                     help="batch: 64 x 2048^2 FBP (default); volume: the full 2048^3 volume; "
                          "ls: 32 x 1024^2 least squares by gradient descent")
     ap.add_argument("--slices", type=int, default=2048)
+    ap.add_argument("--interp", choices=("linear", "keys"), default="linear",
+                    help="radial interpolation of the gather (keys: cubic, narrower gap to brute force)")
     ap.add_argument("--input", choices=("phantom", "random"), default="phantom",
                     help="random: N(0,1) sinograms (for hardware-counter runs, where generating "
                          "phantoms with thousands of small kernels is slow)")
@@ -280,7 +283,8 @@ def main():
         sino = torch.randn(B, V, n, device=dev, generator=gen)
     else:
         sino = synth.batch_sinograms(B, n, V, seed=170408366, device=dev)
-    plan = P.Plan(n, V, max_batch=B)
+    interp_kw = dict(taper="keys", interp="keys") if args.interp == "keys" else {}
+    plan = P.Plan(n, V, max_batch=B, **interp_kw)
     M, G = plan.M, plan.G
     ws = plan.workspace(B)
     img = torch.empty(B, N, N, dtype=torch.float32, device=dev)
@@ -342,7 +346,7 @@ def main():
         sino_cpu = sino[:s].double().cpu().numpy()
         img_cpu = img[:s].double().cpu().numpy()
         log(f"timing the FP64 oracle on {s} slices ...")
-        rate, dt, errs = cpu_baseline(sino_cpu, img_cpu, n, V, N, s)
+        rate, dt, errs = cpu_baseline(sino_cpu, img_cpu, n, V, N, s, args.interp)
         cpu = {"value": round(rate, 4), "unit": "slices/s", "cores": 1, "kind": "oracle",
                "sample": f"{s} of the {B} slices ({V}x{n} -> {N}^2), FP64 NumPy BST, "
                          f"single thread, {dt:.1f} s"}
@@ -364,9 +368,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"FBP of {B} slices x {V} angles x {n} bins -> {B} x {N}x{N}, "
-                        f"random 5-20 ellipse phantoms + 1% noise, P_r=P_c=2, de-apodising taper",
+                        f"random 5-20 ellipse phantoms + 1% noise, P_r=P_c=2, "
+                        + ("cubic (Keys) radial interpolation + its de-apodiser" if args.interp == "keys"
+                           else "de-apodising taper"),
             "batch": B, "n_det": n, "n_angles": V, "n_out": N, "pad_radial": 2, "pad_cart": 2,
-            "filter": "ramp", "input": args.input,
+            "filter": "ramp", "input": args.input, "interp": args.interp,
         },
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -69,8 +69,19 @@ typedef enum {
 typedef enum {
     BST_TAPER_DEAPOD = 0,   /* 1/sinc^2(t dsigma): undoes radial linear interpolation */
     BST_TAPER_NONE = 1,
-    BST_TAPER_KAISER = 2    /* Kaiser-Bessel I0(beta sqrt(1-t^2)) / I0(beta)          */
+    BST_TAPER_KAISER = 2,   /* Kaiser-Bessel I0(beta sqrt(1-t^2)) / I0(beta)          */
+    BST_TAPER_KEYS = 3      /* 1/Khat(t dsigma), Khat(v) = sinc^3(v) (3 sinc(v) - 2 cos(pi v)):
+                               undoes radial cubic (Keys) interpolation                */
 } bst_taper;
+
+/* Radial interpolation of step P5 (the paper asks for "an interpolation"; the
+ * angle direction is always linear). */
+typedef enum {
+    BST_INTERP_LINEAR = 0,  /* samples m0, m0+1                                       */
+    BST_INTERP_KEYS = 1     /* Keys cubic convolution (a = -1/2), samples m0-1 .. m0+2,
+                               sample -1 = conj of sample 1; narrows the gap to brute
+                               force (pair it with BST_TAPER_KEYS). Not with adjoint. */
+} bst_interp;
 
 typedef struct {
     int32_t n_det;          /* n: detector bins; power of two in [16, 4096]            */
@@ -95,6 +106,8 @@ typedef struct {
     double center_shift;    /* known rotation-axis offset beta, detector bins: the data
                                are y(t - beta*dt, theta) (Section 1, "Centering"); P4
                                multiplies by exp(+2 pi i sigma beta dt). |beta| < n/4    */
+    int32_t interp;         /* bst_interp (step P5); BST_INTERP_KEYS with adjoint set
+                               is BST_E_UNSUPPORTED                                      */
 } bst_params;
 
 typedef enum {
@@ -104,15 +117,17 @@ typedef enum {
     BST_APOD_COSINE = 3     /* cos(pi x/2)                            */
 } bst_apodization;
 
-/* Fill *p with the defaults: P_r = P_c = 2, RAMP, de-apodising taper, max_batch 1. */
+/* Fill *p with the defaults: P_r = P_c = 2, RAMP, de-apodising taper, linear
+ * radial interpolation, max_batch 1. */
 void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t n_out);
 
 /* Host-only validation of *p (no device call). */
 bst_status bst_validate(const bst_params* p);
 
 /* Workspace bytes for `batch` slices (host only, no plan needed).
- * bst_backproject: polar spectra [batch][V][M/2+2] complex64, per-projection DC
- * terms [batch][V] float32 and the half-transformed grid [batch][N][G/2]
+ * bst_backproject: polar spectra [batch][V][M/2+2] complex64 ([batch][V][M/2+5]
+ * with BST_INTERP_KEYS: one leading and two more trailing slots), per-projection
+ * DC terms [batch][V] float32 and the half-transformed grid [batch][N][G/2]
  * complex64. With p->adjoint set, the size also covers bst_project: the grid,
  * the full Cartesian half-plane spectrum [batch][G/2][G] and the polar adjoint
  * [batch][V][M/2] (complex64); the larger of the two needs is returned. */

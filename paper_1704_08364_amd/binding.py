@@ -23,7 +23,8 @@ STATUS_NAMES = {
     9: "BST_E_BATCH", 10: "BST_E_ALIAS",
 }
 FILTERS = {"none": 0, "ramp": 1}
-TAPERS = {"deapod": 0, "none": 1, "kaiser": 2, "kb": 2}
+TAPERS = {"deapod": 0, "none": 1, "kaiser": 2, "kb": 2, "keys": 3}
+INTERPS = {"linear": 0, "keys": 1}
 APODIZATIONS = {"ramlak": 0, "shepp": 1, "hann": 2, "cosine": 3}
 
 # Every symbol include/bst.h declares, with its ctypes signature.
@@ -40,6 +41,7 @@ class bst_params(C.Structure):
         ("filter", C.c_int32), ("taper", C.c_int32), ("taper_beta", C.c_double),
         ("max_batch", C.c_int32), ("device", C.c_int32), ("adjoint", C.c_int32),
         ("apodization", C.c_int32), ("center_shift", C.c_double),
+        ("interp", C.c_int32),
     ]
 
 
@@ -115,8 +117,9 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
                 pad_cart: int = 2, filter: str = "ramp", taper: str = "deapod",
                 taper_beta: float = 8.0, max_batch: int = 1, device: int = 0,
                 angles: Optional[Sequence[float]] = None, adjoint: bool = False,
-                apodization: str = "ramlak", center_shift: float = 0.0):
-    """bst_params plus the ctypes array that backs `angles` (keep both alive)."""
+                apodization: str = "ramlak", center_shift: float = 0.0, interp: str = "linear"):
+    """bst_params plus the ctypes array that backs `angles` (keep both alive).
+    interp='keys' (cubic radial interpolation) pairs with taper='keys'."""
     p = bst_params()
     lib().bst_params_default(C.byref(p), n_det, n_angles, n_det if n_out is None else n_out)
     p.pad_radial = pad_radial
@@ -129,6 +132,7 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
     p.adjoint = 1 if adjoint else 0
     p.apodization = APODIZATIONS[apodization] if isinstance(apodization, str) else int(apodization)
     p.center_shift = center_shift
+    p.interp = INTERPS[interp] if isinstance(interp, str) else int(interp)
     keep = None
     if angles is not None:
         arr = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))

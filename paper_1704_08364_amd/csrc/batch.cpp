@@ -83,13 +83,13 @@ void release(bst_batch_s* b) {
 hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStream_t st) {
     const bst_plan_s& p = *c.plan;
     const int batch = (int)c.members.size();
-    const bst::WsLayout L = bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch);
+    const bst::WsLayout L = bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch, p.prm.interp);
     unsigned char* w = static_cast<unsigned char*>(ws) + c.ws_off;
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
     float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
     bst::SpecArgs sa{nullptr, b->d_sino_list + c.list_base, nullptr, nullptr, polar, dc, p.taper, p.kc,
-                     p.tw_M, p.n, p.V, p.S, (float)p.dt};
+                     p.tw_M, p.n, p.V, p.S, p.lead, p.S - p.lead - p.M / 2, (float)p.dt};
     hipError_t e = bst::launch_spectrum(p, sa, batch, st);
     if (e != hipSuccess) return e;
     bst::GatherArgs ga{};
@@ -102,6 +102,7 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     ga.GT = p.GT;
     ga.N = p.N;
     ga.Mh = p.M / 2;
+    ga.zero_slot = p.M / 2 + p.lead;
     ga.batch = batch;
     ga.slices_per_block = p.gather_slices;
     ga.rscale = p.rscale;

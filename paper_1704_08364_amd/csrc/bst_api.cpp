@@ -83,16 +83,17 @@ void set_last_error(hipError_t e) { g_last_error = hipGetErrorString(e); }
 // to odd multiples of 256 bytes (to spread rows over memory channels) was
 // measured on MI355X: it speeds the spectrum kernel by 7% but slows the
 // gather by 4%, a net loss, so both stay unpadded.
-int polar_stride(int M) { return M / 2 + 2; }
+// Keys rows: [conj Yh[1], Yh[0 .. M/2-1], four zeros], linear rows: [Yh[0 .. M/2-1], two zeros]
+int polar_stride(int M, int interp) { return M / 2 + (interp == BST_INTERP_KEYS ? 5 : 2); }
 int grid_width(int G) { return G / 2; }
 
-WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch) {
+WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp) {
     (void)n;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     WsLayout L{};
     const size_t B = (size_t)batch;
     L.polar_off = 0;
-    const size_t polar = B * (size_t)V * (size_t)polar_stride(M) * sizeof(float2);
+    const size_t polar = B * (size_t)V * (size_t)polar_stride(M, interp) * sizeof(float2);
     L.dc_off = up(L.polar_off + polar);
     const size_t dc = B * (size_t)V * sizeof(float);
     L.grid_off = up(L.dc_off + dc);
@@ -112,9 +113,9 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
     return L;
 }
 
-size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint) {
+size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp) {
     if (batch == 0) return 0;
-    size_t need = workspace_layout(n, V, N, M, G, batch).total;
+    size_t need = workspace_layout(n, V, N, M, G, batch, interp).total;
     if (adjoint) {
         const size_t pj = project_workspace_layout(V, N, M, G, batch).total;
         if (pj > need) need = pj;
@@ -143,6 +144,7 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
     p->adjoint = 0;
     p->apodization = BST_APOD_RAMLAK;
     p->center_shift = 0.0;
+    p->interp = BST_INTERP_LINEAR;
 }
 
 bst_status bst_validate(const bst_params* p) {
@@ -154,8 +156,12 @@ bst_status bst_validate(const bst_params* p) {
     if (!(pr == 1 || pr == 2 || pr == 4) || !(pc == 1 || pc == 2 || pc == 4)) return BST_E_PARAM;
     if ((int64_t)pr * p->n_det > 8192 || (int64_t)pc * p->n_out > 8192) return BST_E_SHAPE;
     if (p->filter != BST_FILTER_NONE && p->filter != BST_FILTER_RAMP) return BST_E_PARAM;
-    if (p->taper != BST_TAPER_DEAPOD && p->taper != BST_TAPER_NONE && p->taper != BST_TAPER_KAISER)
+    if (p->taper != BST_TAPER_DEAPOD && p->taper != BST_TAPER_NONE && p->taper != BST_TAPER_KAISER &&
+        p->taper != BST_TAPER_KEYS)
         return BST_E_PARAM;
+    if (p->interp != BST_INTERP_LINEAR && p->interp != BST_INTERP_KEYS) return BST_E_PARAM;
+    // the projector is the transpose of the linear-interpolation gather only
+    if (p->interp == BST_INTERP_KEYS && p->adjoint != 0) return BST_E_UNSUPPORTED;
     if (p->taper == BST_TAPER_KAISER && !(std::isfinite(p->taper_beta) && p->taper_beta >= 0.0 &&
                                           p->taper_beta <= 700.0))
         return BST_E_PARAM;
@@ -182,7 +188,7 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
-                                  p->adjoint != 0 && p->angles == nullptr);
+                                  p->adjoint != 0 && p->angles == nullptr, p->interp);
     return BST_OK;
 }
 
@@ -205,7 +211,9 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->G = pl->prm.pad_cart * pl->N;
     pl->logM = ilog2(pl->M);
     pl->logG = ilog2(pl->G);
-    pl->S = bst::polar_stride(pl->M);
+    pl->S = bst::polar_stride(pl->M, p->interp);
+    pl->lead = (p->interp == BST_INTERP_KEYS) ? 1 : 0;
+    pl->taps = (p->interp == BST_INTERP_KEYS) ? 4 : 2;
     pl->GT = bst::grid_width(pl->G);
     pl->uniform = (p->angles == nullptr);
     pl->dt = 2.0 / pl->n;
@@ -238,6 +246,12 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
             const double x = M_PI * t * dsig;
             const double sc = (x == 0.0) ? 1.0 : std::sin(x) / x;
             w = 1.0 / (sc * sc);
+        } else if (p->taper == BST_TAPER_KEYS) {
+            // transform of the Keys kernel (a = -1/2): sinc^3 (3 sinc - 2 cos), by
+            // integrating its two cubic pieces against cos(2 pi v x)
+            const double x = M_PI * t * dsig;
+            const double sc = (x == 0.0) ? 1.0 : std::sin(x) / x;
+            w = 1.0 / (sc * sc * sc * (3.0 * sc - 2.0 * std::cos(x)));
         } else if (p->taper == BST_TAPER_KAISER) {
             const double arg = 1.0 - t * t;
             w = bessel_i0(p->taper_beta * std::sqrt(arg > 0.0 ? arg : 0.0)) / bessel_i0(p->taper_beta);
@@ -371,7 +385,8 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
 bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
     if (!plan || !bytes) return BST_E_NULL;
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
-    *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint);
+    *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint,
+                                  plan->prm.interp);
     return BST_OK;
 }
 
@@ -386,7 +401,7 @@ bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const vo
     if (batch == 0) return BST_OK;
     if (!in || !out) return BST_E_NULL;
     if (need_ws) {
-        *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch).total;
+        *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp).total;
         if (!ws) return BST_E_NULL;
         if (ws_bytes < *need) return BST_E_WORKSPACE;
     }
@@ -424,7 +439,8 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     DeviceGuard guard(plan->device);
     if (guard.err != hipSuccess) return device_fail(guard.err);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bst::WsLayout L = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch);
+    const bst::WsLayout L =
+        bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp);
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
@@ -435,8 +451,9 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         e = hipEventRecord(static_cast<hipEvent_t>(ev[0]), s);
         if (e != hipSuccess) return device_fail(e);
     }
-    bst::SpecArgs sa{sino, sino_list, flat, dark, polar, dc, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
-                     plan->S, (float)plan->dt};
+    bst::SpecArgs sa{sino,   sino_list, flat,    dark,       polar,          dc,
+                     plan->taper, plan->kc, plan->tw_M, plan->n, plan->V, plan->S,
+                     plan->lead,  plan->S - plan->lead - plan->M / 2, (float)plan->dt};
     e = bst::launch_spectrum(*plan, sa, batch, s);
     if (e != hipSuccess) return device_fail(e);
     if (ev && ev[1]) {
@@ -444,7 +461,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         if (e != hipSuccess) return device_fail(e);
     }
     if (spectrum_only) {
-        e = hipMemcpy2DAsync(spec_out, (plan->M / 2) * sizeof(float2), polar, plan->S * sizeof(float2),
+        e = hipMemcpy2DAsync(spec_out, (plan->M / 2) * sizeof(float2), polar + plan->lead, plan->S * sizeof(float2),
                              (plan->M / 2) * sizeof(float2), (size_t)batch * plan->V, hipMemcpyDeviceToDevice,
                              s);
         if (e != hipSuccess) return device_fail(e);
@@ -462,6 +479,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.GT = plan->GT;
     ga.N = plan->N;
     ga.Mh = plan->M / 2;
+    ga.zero_slot = plan->M / 2 + plan->lead;
     ga.batch = batch;
     ga.slices_per_block = plan->gather_slices;
     ga.rscale = plan->rscale;

@@ -10,7 +10,9 @@ struct bst_plan_s {
     int n, V, N;         // detector bins, projections, output side
     int M, G;            // radial FFT length P_r*n, Cartesian grid side P_c*N
     int logM, logG;
-    int S;               // row stride of a polar spectrum, complex values: M/2 + 2
+    int S;               // row stride of a polar spectrum, complex values: M/2 + 2 (+3 for Keys)
+    int lead;            // slots before sample 0 in a polar row: 1 (conj of sample 1) for Keys, else 0
+    int taps;            // radial taps of the gather: 2 (linear) or 4 (Keys)
     int GT;              // columns per 8-row tile row of the half-transformed grid: G/2
     bool uniform;        // angles are j*pi/V
     double dt, dk;
@@ -50,9 +52,9 @@ struct WsLayout {
     size_t polar_off, dc_off, grid_off, total;
 };
 // Row stride of a polar spectrum and tile-row width of the grid (complex values).
-int polar_stride(int M);
+int polar_stride(int M, int interp);
 int grid_width(int G);
-WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch);
+WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp);
 
 struct ProjWsLayout {
     size_t grid_off, cart_off, polar_off, total;
@@ -70,6 +72,8 @@ struct SpecArgs {
     const float2* kc;
     const float2* tw;
     int n, V, S;
+    int lead;               // slots before sample 0 (1: conj of sample 1 there)
+    int tail;               // zero slots after sample M/2 - 1
     float dt;
 };
 
@@ -80,6 +84,8 @@ struct GatherArgs {
     const float2* tw;
     int V, S, N, Mh;
     int GT;                  // grid tile-row width (columns)
+    int zero_slot;           // first of the zero slots of a row; also the radius cut-off:
+                             // points with r >= zero_slot read only zeros
     int batch, slices_per_block;
     double rscale;
     float vpi_f;             // V / pi

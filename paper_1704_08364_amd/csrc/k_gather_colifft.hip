@@ -121,11 +121,11 @@ struct Stencil {
 // Stencil of Cartesian point (col, bs); bs signed.
 __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a) {
     Stencil st;
-    st.o0 = (unsigned)a.Mh * sizeof(float2);
+    st.o0 = (unsigned)a.zero_slot * sizeof(float2);
     st.g = st.w1 = 0.f;
     if (col == 0 && bs == 0) return st;
     const double r = sqrt((double)(col * col + bs * bs)) * a.rscale;
-    if (r >= (double)a.Mh) return st;
+    if (r >= (double)a.zero_slot) return st;
     const double mf = floor(r);
     const int m0 = (int)mf;
 
@@ -154,7 +154,31 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
     return st;
 }
 
-template <int LOGG, int EV>
+// Radial value of one row from its two (linear) or four (cubic) samples.
+__device__ __forceinline__ float2 radial2(const Pair8& p, float g) {
+    return make_float2(fmaf(g, p.x1 - p.x0, p.x0), fmaf(g, p.y1 - p.y0, p.y0));
+}
+// Keys cubic convolution (a = -1/2) over samples m0-1 .. m0+2 at fraction g:
+// the Catmull-Rom weights.
+__device__ __forceinline__ float2 radial4(const Pair8& p, const Pair8& q, float g) {
+    const float g2 = g * g, g3 = g2 * g;
+    const float wm = 0.5f * (-g3 + 2.f * g2 - g);
+    const float w0 = 0.5f * (3.f * g3 - 5.f * g2 + 2.f);
+    const float w1 = 0.5f * (-3.f * g3 + 4.f * g2 + g);
+    const float w2 = 0.5f * (g3 - g2);
+    return make_float2(fmaf(w2, q.x1, fmaf(w1, q.x0, fmaf(w0, p.x1, wm * p.x0))),
+                       fmaf(w2, q.y1, fmaf(w1, q.y0, fmaf(w0, p.y1, wm * p.y0))));
+}
+// Angular (linear) combination of the two rows' radial values: weight
+// 1 - |w1| for the j0 row, conjugated in the lower half-plane, and w1 (sign =
+// conjugation) for the j1 row.
+__device__ __forceinline__ float2 angular(float2 u0, float2 u1, float w1, bool lower) {
+    const float a0 = 1.f - fabsf(w1);
+    const float w0 = lower ? -a0 : a0;
+    return make_float2(fmaf(fabsf(w1), u1.x, a0 * u0.x), fmaf(w1, u1.y, w0 * u0.y));
+}
+
+template <int LOGG, int EV, int TAPS>
 __global__ void __launch_bounds__((GatherCfg<LOGG, EV>::WG))
 __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather_colifft(GatherArgs a) {
     using C = GatherCfg<LOGG, EV>;
@@ -212,32 +236,57 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
         int jv = j;
         asm volatile("" : "+v"(jv));
         const __amdgpu_buffer_rsrc_t P = polar_rsrc(a.polar + (size_t)s * a.V * a.S, slice_bytes);
-        // all 2E sample-pair loads are issued before any is used
-        Pair8 pa[E], pb[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const bool wrap = __float_as_uint(pt[e].g) >> 31;
-            pa[e] = load_pair(P, pt[e].o0);
-            pb[e] = load_pair(P, pt[e].o0 + (wrap ? wrap_bytes : row_bytes));
-        }
-        float dcv = 0.f;
-        if (lblock == 0) {
-            float acc = 0.f;
-            for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)s * a.V + i];
-            dcv = block_sum<C::WG>(acc, red) * a.dc_scale;
-        }
         float2 v[E];
+        float dcv = 0.f;
+        // rows b = j + e*T with e >= E/2 are the lower half-plane (b - G < 0)
+        if constexpr (TAPS == 2) {
+            // all 2E sample-pair loads are issued before any is used
+            Pair8 pa[E], pb[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            // rows b = j + e*T with e >= E/2 are the lower half-plane (b - G < 0)
-            const float g = fabsf(pt[e].g), w1 = pt[e].w1;
-            const float a0 = 1.f - fabsf(w1);
-            const float w0 = 2 * e >= E ? -a0 : a0;
-            const float u0x = fmaf(g, pa[e].x1 - pa[e].x0, pa[e].x0);
-            const float u0y = fmaf(g, pa[e].y1 - pa[e].y0, pa[e].y0);
-            const float u1x = fmaf(g, pb[e].x1 - pb[e].x0, pb[e].x0);
-            const float u1y = fmaf(g, pb[e].y1 - pb[e].y0, pb[e].y0);
-            v[e] = make_float2(fmaf(fabsf(w1), u1x, a0 * u0x), fmaf(w1, u1y, w0 * u0y));
+            for (int e = 0; e < E; ++e) {
+                const bool wrap = __float_as_uint(pt[e].g) >> 31;
+                pa[e] = load_pair(P, pt[e].o0);
+                pb[e] = load_pair(P, pt[e].o0 + (wrap ? wrap_bytes : row_bytes));
+            }
+            if (lblock == 0) {
+                float acc = 0.f;
+                for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)s * a.V + i];
+                dcv = block_sum<C::WG>(acc, red) * a.dc_scale;
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const float g = fabsf(pt[e].g);
+                v[e] = angular(radial2(pa[e], g), radial2(pb[e], g), pt[e].w1, 2 * e >= E);
+            }
+        } else {
+            if (lblock == 0) {
+                float acc = 0.f;
+                for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)s * a.V + i];
+                dcv = block_sum<C::WG>(acc, red) * a.dc_scale;
+            }
+            // four 16-byte reads per point (samples m0-1 .. m0+2 of both rows),
+            // issued half the points at a time to bound the registers in flight
+            constexpr int H = E / 2;
+#pragma unroll
+            for (int h0 = 0; h0 < E; h0 += H) {
+                Pair8 pa[H], qa[H], pb[H], qb[H];
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    const Stencil& st = pt[h0 + i];
+                    const unsigned o1 = st.o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes);
+                    pa[i] = load_pair(P, st.o0);
+                    qa[i] = load_pair(P, st.o0 + 16u);
+                    pb[i] = load_pair(P, o1);
+                    qb[i] = load_pair(P, o1 + 16u);
+                }
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    const int e = h0 + i;
+                    const float g = fabsf(pt[e].g);
+                    v[e] = angular(radial4(pa[i], qa[i], g), radial4(pb[i], qb[i], g), pt[e].w1, 2 * e >= E);
+                }
+                asm volatile("" ::: "memory");
+            }
         }
         // origin: column 0, row 0 is thread j = 0's first point
         if (col == 0 && jv == 0) v[0] = make_float2(dcv, 0.f);
@@ -258,35 +307,37 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
     }
 }
 
-template <int LOGG, int EV>
+template <int LOGG, int EV, int TAPS>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
     using C = GatherCfg<LOGG, EV>;
     const int cols = C::G / 2;
     const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
     dim3 grid((cols + C::F - 1) / C::F, chunks);
-    hipLaunchKernelGGL((k_gather_colifft<LOGG, EV>), grid, dim3(C::WG), 0, st, a);
+    hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS>), grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }
 
+// values per thread e (8 or 16) for linear radial taps; cubic taps use 8
 template <int LOGG>
-static hipError_t launch_gather_e(const GatherArgs& a, int e, hipStream_t st) {
-    if (e == 16) return launch_gather_t<LOGG, 16>(a, st);
-    return launch_gather_t<LOGG, 8>(a, st);
+static hipError_t launch_gather_e(const GatherArgs& a, int e, int taps, hipStream_t st) {
+    if (taps == 4) return launch_gather_t<LOGG, 8, 4>(a, st);
+    if (e == 16) return launch_gather_t<LOGG, 16, 2>(a, st);
+    return launch_gather_t<LOGG, 8, 2>(a, st);
 }
 
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st) {
-    const int e = p.gather_e;
+    const int e = p.gather_e, t = p.taps;
     switch (p.logG) {
-        case 4: return launch_gather_e<4>(a, e, st);
-        case 5: return launch_gather_e<5>(a, e, st);
-        case 6: return launch_gather_e<6>(a, e, st);
-        case 7: return launch_gather_e<7>(a, e, st);
-        case 8: return launch_gather_e<8>(a, e, st);
-        case 9: return launch_gather_e<9>(a, e, st);
-        case 10: return launch_gather_e<10>(a, e, st);
-        case 11: return launch_gather_e<11>(a, e, st);
-        case 12: return launch_gather_e<12>(a, e, st);
-        case 13: return launch_gather_e<13>(a, e, st);
+        case 4: return launch_gather_e<4>(a, e, t, st);
+        case 5: return launch_gather_e<5>(a, e, t, st);
+        case 6: return launch_gather_e<6>(a, e, t, st);
+        case 7: return launch_gather_e<7>(a, e, t, st);
+        case 8: return launch_gather_e<8>(a, e, t, st);
+        case 9: return launch_gather_e<9>(a, e, t, st);
+        case 10: return launch_gather_e<10>(a, e, t, st);
+        case 11: return launch_gather_e<11>(a, e, t, st);
+        case 12: return launch_gather_e<12>(a, e, t, st);
+        case 13: return launch_gather_e<13>(a, e, t, st);
         default: return hipErrorInvalidValue;
     }
 }

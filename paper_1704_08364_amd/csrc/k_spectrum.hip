@@ -9,8 +9,11 @@
 // and each is multiplied by the complex weight dt*K[m]*A(sigma_m)*exp(2 pi i
 // sigma_m beta dt) (K = 1/sigma for plain B, 1 for FBP, 0 at m = M/2; A the
 // apodising window; beta a known rotation-axis offset). With raw counts the
-// load forms y = -log((I - D)/(I0 - D)) first (flat/dark normalisation). Output rows hold m = 0..M/2-1 plus two zero slots (row stride
-// S = M/2 + 2) so the gather may read samples m0 and m0+1 without a bound test.
+// load forms y = -log((I - D)/(I0 - D)) first (flat/dark normalisation).
+// Output rows hold m = 0..M/2-1 followed by zero slots, so the gather may read
+// past the last sample without a bound test: two for linear radial
+// interpolation (samples m0, m0+1), four plus a leading conj Yh[1] (the
+// sample at m = -1) for cubic interpolation (samples m0-1 .. m0+2).
 // The unweighted DC values dt*Y_j[0] go to a separate array for the origin rule.
 #include "bst_internal.h"
 #include "fft_lds.h"
@@ -152,12 +155,17 @@ k_spectrum(SpecArgs a) {
             const float2 zc = my[lds_pad((M - m) & (M - 1))];
             const float2 ya2 = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[e]);
             const float2 yb2 = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[e]);
-            if (va) pa[m] = ya2;
-            if (vb) pb[m] = yb2;
+            if (va) pa[a.lead + m] = ya2;
+            if (vb) pb[a.lead + m] = yb2;
+            // the sample before 0 (cubic radial taps): Yh(-sigma) = conj Yh(sigma)
+            if (a.lead && m == 1) {
+                if (va) pa[0] = make_float2(ya2.x, -ya2.y);
+                if (vb) pb[0] = make_float2(yb2.x, -yb2.y);
+            }
         }
-        if (jv < 2) {
-            if (va) pa[M / 2 + jv] = make_float2(0.f, 0.f);
-            if (vb) pb[M / 2 + jv] = make_float2(0.f, 0.f);
+        for (int z = jv; z < a.tail; z += T) {
+            if (va) pa[a.lead + M / 2 + z] = make_float2(0.f, 0.f);
+            if (vb) pb[a.lead + M / 2 + z] = make_float2(0.f, 0.f);
         }
         if (jv == 0) {
             const float2 z0 = my[0];

@@ -46,7 +46,7 @@ def test_defaults_validate():
     ("n_det", 100, 2), ("n_det", 8, 2), ("n_det", 8192, 2), ("n_out", 128, 2),
     ("n_angles", 1, 2), ("n_angles", 20000, 2),
     ("pad_radial", 3, 4), ("pad_cart", 8, 4), ("filter", 2, 4), ("taper", 7, 4),
-    ("max_batch", 0, 9), ("device", -1, 4),
+    ("max_batch", 0, 9), ("device", -1, 4), ("interp", 2, 4), ("interp", -1, 4),
 ])
 def test_validation_codes(field, value, code):
     p, _ = _params()
@@ -155,3 +155,16 @@ def test_batch_create_validates_before_device_work():
     assert L.bst_batch_create(C.byref(p), 3, n, v, C.byref(h)) == 2  # 100 is not a power of two
     assert h.value is None
     assert L.bst_batch_destroy(None) == 0
+
+
+def test_keys_interpolation_validates_and_sizes_its_rows():
+    p, _ = _params(n=2048, V=2048, max_batch=4, taper="keys", interp="keys")
+    assert _validate(p) == 0
+    # keys rows: one leading slot and four trailing zeros, [V][M/2 + 5]
+    per = 2048 * (2048 + 5) * 8 + 2048 * 4 + 2048 * 2048 * 8
+    assert abs(P.query_workspace(p, 1) - per) < 3 * 256
+    lin, _ = _params(n=2048, V=2048, max_batch=4)
+    assert P.query_workspace(p, 4) > P.query_workspace(lin, 4)
+    # the projector is the transpose of the linear gather only
+    p.adjoint = 1
+    assert _validate(p) == 8

@@ -36,6 +36,10 @@ Discrete steps (readings where the paper is silent are listed beside each):
       RAMP: mean_j Y_j[0]; NONE: (kappa / dk) mean_j Y_j[0], kappa = 4 asinh(1),
       the average of 1/|k| over the origin cell times dk. The Nyquist column
       a = G/2 is set to zero (like the radial Nyquist sample in P4).
+      Non-uniform angles (strictly increasing in [0, pi)): the angle sequence
+      is continued with period pi (theta_{j+V} = theta_j + pi, conjugated
+      sample), j0 is the last angle <= theta in it and f the fraction of the
+      bracketing gap, so below theta_0 the j0 neighbour is theta_{V-1} - pi.
   P6  2D inverse DFT over the Hermitian plane: b = dk^2 sum_k C[k] e^{+2 pi i k.x / G}
       (the C2R convention drops the imaginary parts of self-conjugate columns).
   P7  fftshift and P8 restriction to the N x N output grid:
@@ -178,10 +182,39 @@ def normalize(counts: np.ndarray, flat: np.ndarray, dark: np.ndarray) -> np.ndar
 
 
 # P5 ---------------------------------------------------------------------------
+def angle_bracket(theta: np.ndarray, geom: Geometry):
+    """For directions theta in [0, pi): (j0, j1, f, flip0, flip1): the bracketing
+    angle indices in the period-pi continuation of the angle sequence, the
+    fraction of the gap and whether each neighbour is a conjugated image
+    (theta_j - pi below the first angle, theta_j + pi past the last)."""
+    V = geom.V
+    if geom.uniform:
+        q = theta * (V / np.pi)
+        j0 = np.floor(q)
+        f = q - j0
+        j0 = j0.astype(np.int64)
+        over = j0 >= V  # rounding guard: theta == pi
+        j0 = np.where(over, V - 1, j0)
+        f = np.where(over, 1.0, f)
+        flip0 = np.zeros(theta.shape, dtype=bool)
+    else:
+        th = geom.theta
+        k = np.searchsorted(th, theta, side="right") - 1  # last theta_j <= theta, -1 below theta_0
+        flip0 = k < 0
+        j0 = np.where(flip0, V - 1, k)
+        lo = np.where(flip0, th[V - 1] - np.pi, th[j0])
+        hi = np.where(j0 + 1 < V, th[np.minimum(j0 + 1, V - 1)], th[0] + np.pi)
+        hi = np.where(flip0, th[0], hi)
+        f = (theta - lo) / (hi - lo)
+    j1 = j0 + 1
+    wrap = j1 == V
+    j1 = np.where(wrap, 0, j1)
+    flip1 = wrap & ~flip0
+    return j0, j1, f, flip0, flip1
+
+
 def gather(Yh: np.ndarray, Y0: np.ndarray, geom: Geometry, prm: Params) -> np.ndarray:
     """Cartesian half-plane spectrum C[b][a], b in FFT order over G rows, a in [0, G/2]."""
-    if not geom.uniform:
-        raise NotImplementedError("the BST oracle takes uniform angles theta_j = j pi / V")
     M, G, _, dk = sizes(geom, prm)
     V = geom.V
     # radial samples past the data are zero: extend with zeros to cover |k| up to the corner
@@ -196,18 +229,9 @@ def gather(Yh: np.ndarray, Y0: np.ndarray, geom: Geometry, prm: Params) -> np.nd
     phi = np.arctan2(b, a) + 0.0 * a  # in [-pi/2, pi/2]
     lower = phi < 0.0
     theta = np.where(lower, phi + np.pi, phi)
-    q = theta * (V / np.pi)
-    j0 = np.floor(q)
-    f = q - j0
-    j0 = j0.astype(np.int64)
-    over = j0 >= V  # rounding guard: theta == pi
-    j0 = np.where(over, V - 1, j0)
-    f = np.where(over, 1.0, f)
-    j1 = j0 + 1
-    wrap = j1 == V
-    j1 = np.where(wrap, 0, j1)
-    c0 = lower
-    c1 = lower ^ wrap
+    j0, j1, f, flip0, flip1 = angle_bracket(theta, geom)
+    c0 = lower ^ flip0
+    c1 = lower ^ flip1
     m0 = np.floor(r)
     g = r - m0
     m0 = np.minimum(m0.astype(np.int64), M + 2)

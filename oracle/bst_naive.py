@@ -93,26 +93,44 @@ def backproject(sino, geom: Geometry, P_r: int = 2, P_c: int = 2,
                 theta, conj = phi, False
             else:
                 theta, conj = phi + math.pi, True
-            q = theta * V / math.pi
-            j0 = int(math.floor(q))
-            f = q - j0
-            if j0 >= V:
-                j0, f = V - 1, 1.0
+            conj0 = conj
+            if geom.uniform:
+                q = theta * V / math.pi
+                j0 = int(math.floor(q))
+                f = q - j0
+                if j0 >= V:
+                    j0, f = V - 1, 1.0
+            else:
+                # the period-pi continuation: scan for the last angle <= theta
+                th = list(geom.theta)
+                j0 = -1
+                for jj in range(V):
+                    if th[jj] <= theta:
+                        j0 = jj
+                if j0 < 0:  # below theta_0: the neighbour is theta_{V-1} - pi, conjugated
+                    lo, hi = th[V - 1] - math.pi, th[0]
+                    j0, conj0 = V - 1, not conj
+                else:
+                    lo = th[j0]
+                    hi = th[j0 + 1] if j0 + 1 < V else th[0] + math.pi
+                f = (theta - lo) / (hi - lo)
             j1, conj1 = j0 + 1, conj
             if j1 == V:
-                j1, conj1 = 0, not conj
+                j1 = 0
+                if conj0 == conj:  # theta_0 + pi, conjugated (not when j0 is already the image)
+                    conj1 = not conj
             m0 = int(math.floor(r))
             g = r - m0
             if interp == "linear":
-                C[bi][a] = ((1 - f) * (1 - g) * sample(j0, m0, conj)
-                            + (1 - f) * g * sample(j0, m0 + 1, conj)
+                C[bi][a] = ((1 - f) * (1 - g) * sample(j0, m0, conj0)
+                            + (1 - f) * g * sample(j0, m0 + 1, conj0)
                             + f * (1 - g) * sample(j1, m0, conj1)
                             + f * g * sample(j1, m0 + 1, conj1))
             else:
                 acc = 0j
                 for mm in range(m0 - 1, m0 + 3):
                     wr = _keys(r - mm)
-                    acc += wr * ((1 - f) * sample(j0, mm, conj) + f * sample(j1, mm, conj1))
+                    acc += wr * ((1 - f) * sample(j0, mm, conj0) + f * sample(j1, mm, conj1))
                 C[bi][a] = acc
 
     # P6-P8: explicit real-linear inverse sum, evaluated only on the output pixels

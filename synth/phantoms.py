@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
+from typing import Optional
 from typing import List, Sequence
 
 import numpy as np
@@ -30,6 +31,7 @@ class Geometry:
     n_det: int
     n_angles: int
     n_out: int
+    angles: Optional[tuple] = None   # non-uniform theta_j (increasing, in [0, pi)), else j pi / V
 
     @property
     def dt(self) -> float:
@@ -44,6 +46,8 @@ class Geometry:
                 - self.n_det // 2) * self.dt
 
     def theta(self, device="cpu") -> torch.Tensor:
+        if self.angles is not None:
+            return torch.tensor(self.angles, dtype=torch.float64, device=device)
         return torch.arange(self.n_angles, dtype=torch.float64,
                             device=device) * (math.pi / self.n_angles)
 

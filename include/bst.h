@@ -87,9 +87,10 @@ typedef struct {
     int32_t n_det;          /* n: detector bins; power of two in [16, 4096]            */
     int32_t n_angles;       /* V: projections; [2, 16384]                               */
     int32_t n_out;          /* N: output side; must equal n_det in this version         */
-    const double* angles;   /* host, V values; NULL = uniform j*pi/V. Non-uniform
-                               angles are validated, then rejected with
-                               BST_E_UNSUPPORTED by the FFT path                        */
+    const double* angles;   /* host, V values, strictly increasing in [0, pi); NULL =
+                               uniform j*pi/V. Step P5 brackets each direction in the
+                               period-pi continuation of the angle sequence. With
+                               adjoint set, non-uniform angles are BST_E_UNSUPPORTED    */
     int32_t pad_radial;     /* P_r in {1,2,4}: FFT length M = P_r*n <= 8192 (P2); 0 -> 2 */
     int32_t pad_cart;       /* P_c in {1,2,4}: Cartesian grid G = P_c*N <= 8192; 0 -> 2  */
     int32_t filter;         /* bst_filter                                                */

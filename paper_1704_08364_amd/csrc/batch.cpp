@@ -103,6 +103,8 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     ga.N = p.N;
     ga.Mh = p.M / 2;
     ga.zero_slot = p.M / 2 + p.lead;
+    ga.inv_gap = p.inv_gap;
+    ga.uniform = p.uniform ? 1 : 0;
     ga.batch = batch;
     ga.slices_per_block = p.gather_slices;
     ga.rscale = p.rscale;

@@ -162,6 +162,8 @@ bst_status bst_validate(const bst_params* p) {
     if (p->interp != BST_INTERP_LINEAR && p->interp != BST_INTERP_KEYS) return BST_E_PARAM;
     // the projector is the transpose of the linear-interpolation gather only
     if (p->interp == BST_INTERP_KEYS && p->adjoint != 0) return BST_E_UNSUPPORTED;
+    // ... and of the uniform-angle gather only
+    if (p->angles != nullptr && p->adjoint != 0) return BST_E_UNSUPPORTED;
     if (p->taper == BST_TAPER_KAISER && !(std::isfinite(p->taper_beta) && p->taper_beta >= 0.0 &&
                                           p->taper_beta <= 700.0))
         return BST_E_PARAM;
@@ -239,6 +241,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::vector<float2> twM(M), twG(G);
     std::vector<double> bf_c(V), bf_s(V), theta(V);
     std::vector<double2> ang(V);
+    std::vector<float> inv_gap(V);
     for (int i = 0; i < n; ++i) {
         const double t = (i - n / 2) * pl->dt;
         double w = 1.0;
@@ -282,6 +285,11 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     for (int j = 0; j < V; ++j) theta[j] = p->angles ? p->angles[j] : (double)j * M_PI / (double)V;
     const double ratio = d / pl->dt;
     for (int j = 0; j < V; ++j) ang[j] = make_double2(std::cos(theta[j]), std::sin(theta[j]));
+    // 1 / (theta_{j+1} - theta_j) in the period-pi continuation (the last gap wraps to theta_0 + pi)
+    for (int j = 0; j < V; ++j) {
+        const double next = (j == V - 1) ? theta[0] + M_PI : theta[j + 1];
+        inv_gap[j] = (float)(1.0 / (next - theta[j]));
+    }
     for (int j = 0; j < V; ++j) {
         bf_c[j] = std::cos(theta[j]) * ratio;
         bf_s[j] = std::sin(theta[j]) * ratio;
@@ -307,6 +315,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     const size_t o_s = off;     off = up(off + V * sizeof(double));
     const size_t o_w = off;     off = up(off + V * sizeof(float));
     const size_t o_ang = off;   off = up(off + V * sizeof(double2));
+    const size_t o_gap = off;   off = up(off + V * sizeof(float));
     const size_t total = off;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
@@ -317,6 +326,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::memcpy(host.data() + o_s, bf_s.data(), V * sizeof(double));
     std::memcpy(host.data() + o_w, bf_w.data(), V * sizeof(float));
     std::memcpy(host.data() + o_ang, ang.data(), V * sizeof(double2));
+    std::memcpy(host.data() + o_gap, inv_gap.data(), V * sizeof(float));
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -378,6 +388,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->bf_s = reinterpret_cast<double*>(base + o_s);
     pl->bf_w = reinterpret_cast<float*>(base + o_w);
     pl->ang = reinterpret_cast<double2*>(base + o_ang);
+    pl->inv_gap = reinterpret_cast<float*>(base + o_gap);
     *out = pl;
     return BST_OK;
 }
@@ -434,7 +445,6 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         st = check_call(plan, sino, in_bytes, img, out_bytes, batch, ws, ws_bytes, true, &need);
     }
     if (st != BST_OK || batch == 0) return st;
-    if (!plan->uniform) return BST_E_UNSUPPORTED;
 
     DeviceGuard guard(plan->device);
     if (guard.err != hipSuccess) return device_fail(guard.err);
@@ -485,6 +495,8 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.rscale = plan->rscale;
     ga.vpi_f = (float)plan->vpi;
     ga.ang = plan->ang;
+    ga.inv_gap = plan->inv_gap;
+    ga.uniform = plan->uniform ? 1 : 0;
     ga.dc_scale = plan->dc_scale;
     e = bst::launch_gather_colifft(*plan, ga, s);
     if (e != hipSuccess) return device_fail(e);

@@ -31,6 +31,7 @@ struct bst_plan_s {
     double* bf_s;        // [V]          sin(theta_j) * d/dt
     float* bf_w;         // [V]          w_j
     double2* ang;        // [V]          (cos theta_j, sin theta_j), gather angle residuals
+    float* inv_gap;      // [V]          1 / (theta_{j+1} - theta_j), last gap to theta_0 + pi
     // adjoint (bst_project): transposed gather as CSR lists per polar sample
     bool adjoint;
     void* adj_block;
@@ -91,6 +92,8 @@ struct GatherArgs {
     float vpi_f;             // V / pi
     float dc_scale;
     const double2* ang;      // [V] (cos theta_j, sin theta_j)
+    const float* inv_gap;    // [V] 1 / angle gap (non-uniform angles)
+    int uniform;             // angles are j pi / V
 };
 
 struct RowArgs {

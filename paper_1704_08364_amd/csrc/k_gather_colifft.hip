@@ -104,12 +104,14 @@ __device__ float block_sum(float x, float* red) {
 // Interpolation stencil of one Cartesian point, fixed for all slices:
 //   o0      byte offset (inside one slice's polar block) of the sample pair
 //           (j0, m0..m0+1); the pair (j1, m0..m0+1) is one polar row further,
-//           or, when j1 wraps to angle 0, (V-1) rows back;
+//           or, when j1 wraps to angle 0, (V-1) rows back. Bit 31 flips the
+//           conjugation of the j0 pair (non-uniform angles, below theta_0,
+//           where the j0 neighbour is the image theta_{V-1} - pi);
 //   g       radial fraction, its sign bit set when j1 wraps;
 //   w1      angular weight f of the j1 pair, negative when that pair is
-//           conjugated. The j0 pair has weight 1 - f and is conjugated
-//           exactly for the lower half-plane b < 0, which is known at compile
-//           time from the point's slot in the thread.
+//           conjugated. The j0 pair has weight 1 - f and is conjugated for
+//           the lower half-plane b < 0 (known at compile time from the
+//           point's slot in the thread), unless bit 31 of o0 flips it.
 // Points outside the radial data (and the origin, which the DC rule sets
 // afterwards) point at the two zero slots that end rows 0 and 1, so every
 // point runs the same branch-free code.
@@ -117,8 +119,17 @@ struct Stencil {
     unsigned o0;
     float g, w1;
 };
+constexpr unsigned kOffsetMask = 0x7FFFFFFFu;
 
-// Stencil of Cartesian point (col, bs); bs signed.
+// conjugation of the j0 pair: the lower half-plane, flipped by bit 31 of o0
+template <bool NU>
+__device__ __forceinline__ bool lower_j0(const Stencil& st, bool lower) {
+    if constexpr (NU) return lower != ((st.o0 >> 31) != 0u);
+    return lower;
+}
+
+// Stencil of Cartesian point (col, bs); bs signed. NU: non-uniform angles.
+template <bool NU>
 __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a) {
     Stencil st;
     st.o0 = (unsigned)a.zero_slot * sizeof(float2);
@@ -133,22 +144,54 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
     const bool lower = bs < 0;
     const int x = lower ? -col : col;
     const int y = lower ? -bs : bs;
-    const float th = atan2f((float)y, (float)x);
-    int j0 = (int)floorf(th * a.vpi_f);
-    j0 = j0 < 0 ? 0 : (j0 >= a.V ? a.V - 1 : j0);
-    const double2 cs = a.ang[j0];
-    const double cross = (double)y * cs.x - (double)x * cs.y;
-    const double dot = (double)x * cs.x + (double)y * cs.y;
-    float f = atan2f((float)cross, (float)dot) * a.vpi_f;
-    if (f < 0.f) {
-        if (j0 > 0) { j0 -= 1; f += 1.f; } else { f = 0.f; }
-    } else if (f >= 1.f) {
-        if (j0 < a.V - 1) { j0 += 1; f -= 1.f; } else { f = 1.f; }
+    int j0;
+    float f;
+    bool flip0 = false;
+    if constexpr (!NU) {
+        const float th = atan2f((float)y, (float)x);
+        j0 = (int)floorf(th * a.vpi_f);
+        j0 = j0 < 0 ? 0 : (j0 >= a.V ? a.V - 1 : j0);
+        const double2 cs = a.ang[j0];
+        const double cross = (double)y * cs.x - (double)x * cs.y;
+        const double dot = (double)x * cs.x + (double)y * cs.y;
+        f = atan2f((float)cross, (float)dot) * a.vpi_f;
+        if (f < 0.f) {
+            if (j0 > 0) { j0 -= 1; f += 1.f; } else { f = 0.f; }
+        } else if (f >= 1.f) {
+            if (j0 < a.V - 1) { j0 += 1; f -= 1.f; } else { f = 1.f; }
+        }
+    } else {
+        // theta_j <= theta exactly when the cross product e_j x u is >= 0 (both
+        // directions in [0, pi)): binary search for the last such j
+        auto at_or_before = [&](int jj) {
+            const double2 e = a.ang[jj];
+            return (double)y * e.x - (double)x * e.y >= 0.0;
+        };
+        double ex, ey;  // direction of the lower neighbour
+        if (!at_or_before(0)) {
+            j0 = a.V - 1;  // below theta_0: the image theta_{V-1} - pi, conjugated
+            flip0 = true;
+            ex = -a.ang[j0].x;
+            ey = -a.ang[j0].y;
+        } else {
+            int lo = 0, hi = a.V;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (at_or_before(mid)) lo = mid; else hi = mid;
+            }
+            j0 = lo;
+            ex = a.ang[j0].x;
+            ey = a.ang[j0].y;
+        }
+        const double cross = (double)y * ex - (double)x * ey;
+        const double dot = (double)x * ex + (double)y * ey;
+        f = fminf(fmaxf(atan2f((float)cross, (float)dot) * a.inv_gap[j0], 0.f), 1.f);
     }
-    // past theta_{V-1} the neighbour is theta_0 with the conjugation flipped
+    // past theta_{V-1} the neighbour is theta_0 + pi: conjugated (both
+    // neighbours of a point below theta_0 are already in place)
     const bool wrap = (j0 + 1 == a.V);
-    const bool conj1 = lower != wrap;
-    st.o0 = (unsigned)(j0 * a.S + m0) * sizeof(float2);
+    const bool conj1 = lower != (wrap && !flip0);
+    st.o0 = ((unsigned)(j0 * a.S + m0) * sizeof(float2)) | ((unsigned)flip0 << 31);
     st.g = __uint_as_float(__float_as_uint((float)(r - mf)) | ((unsigned)wrap << 31));
     st.w1 = conj1 ? -f : f;
     return st;
@@ -178,7 +221,7 @@ __device__ __forceinline__ float2 angular(float2 u0, float2 u1, float w1, bool l
     return make_float2(fmaf(fabsf(w1), u1.x, a0 * u0.x), fmaf(w1, u1.y, w0 * u0.y));
 }
 
-template <int LOGG, int EV, int TAPS>
+template <int LOGG, int EV, int TAPS, bool NU>
 __global__ void __launch_bounds__((GatherCfg<LOGG, EV>::WG))
 __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather_colifft(GatherArgs a) {
     using C = GatherCfg<LOGG, EV>;
@@ -207,7 +250,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
         for (int h = 0; h < CH; ++h) {
             const int b = j + (c0 + h) * T;
             const int bs = b < G / 2 ? b : b - G;
-            const Stencil st = point_stencil(live ? col : 0, live ? bs : 0, a);
+            const Stencil st = point_stencil<NU>(live ? col : 0, live ? bs : 0, a);
             unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
             d[0] = st.o0;
             d[C::WG] = __float_as_uint(st.g);
@@ -245,8 +288,9 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const bool wrap = __float_as_uint(pt[e].g) >> 31;
-                pa[e] = load_pair(P, pt[e].o0);
-                pb[e] = load_pair(P, pt[e].o0 + (wrap ? wrap_bytes : row_bytes));
+                const unsigned o0 = NU ? (pt[e].o0 & kOffsetMask) : pt[e].o0;
+                pa[e] = load_pair(P, o0);
+                pb[e] = load_pair(P, o0 + (wrap ? wrap_bytes : row_bytes));
             }
             if (lblock == 0) {
                 float acc = 0.f;
@@ -256,7 +300,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float g = fabsf(pt[e].g);
-                v[e] = angular(radial2(pa[e], g), radial2(pb[e], g), pt[e].w1, 2 * e >= E);
+                v[e] = angular(radial2(pa[e], g), radial2(pb[e], g), pt[e].w1, lower_j0<NU>(pt[e], 2 * e >= E));
             }
         } else {
             if (lblock == 0) {
@@ -273,9 +317,10 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
                 for (int i = 0; i < H; ++i) {
                     const Stencil& st = pt[h0 + i];
-                    const unsigned o1 = st.o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes);
-                    pa[i] = load_pair(P, st.o0);
-                    qa[i] = load_pair(P, st.o0 + 16u);
+                    const unsigned o0 = NU ? (st.o0 & kOffsetMask) : st.o0;
+                    const unsigned o1 = o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes);
+                    pa[i] = load_pair(P, o0);
+                    qa[i] = load_pair(P, o0 + 16u);
                     pb[i] = load_pair(P, o1);
                     qb[i] = load_pair(P, o1 + 16u);
                 }
@@ -283,7 +328,8 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
                 for (int i = 0; i < H; ++i) {
                     const int e = h0 + i;
                     const float g = fabsf(pt[e].g);
-                    v[e] = angular(radial4(pa[i], qa[i], g), radial4(pb[i], qb[i], g), pt[e].w1, 2 * e >= E);
+                    v[e] = angular(radial4(pa[i], qa[i], g), radial4(pb[i], qb[i], g), pt[e].w1,
+                                   lower_j0<NU>(pt[e], 2 * e >= E));
                 }
                 asm volatile("" ::: "memory");
             }
@@ -313,7 +359,10 @@ static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
     const int cols = C::G / 2;
     const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
     dim3 grid((cols + C::F - 1) / C::F, chunks);
-    hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS>), grid, dim3(C::WG), 0, st, a);
+    if (a.uniform)
+        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, false>), grid, dim3(C::WG), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, true>), grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }
 

@@ -168,3 +168,11 @@ def test_keys_interpolation_validates_and_sizes_its_rows():
     # the projector is the transpose of the linear gather only
     p.adjoint = 1
     assert _validate(p) == 8
+
+
+def test_adjoint_needs_uniform_angles():
+    import numpy as np
+    p, keep = _params(n=64, V=8, angles=np.linspace(0.1, 3.0, 8))
+    assert _validate(p) == 0
+    p.adjoint = 1
+    assert _validate(p) == 8

@@ -306,8 +306,8 @@ def backproject_batch(sinos: np.ndarray, geom: Geometry, prm: Params = None) -> 
 # Adjoint: the exact real-linear transpose of steps P1..P8, stage by stage.
 #
 # With the weighted inner products <f, f'> = d^2 sum f f' (images) and
-# <g, g'> = dt sum_j w_j sum_i g g' (sinograms, uniform w = pi/V), the
-# projector R = (d^2 / (dt w)) B^T satisfies <R f, g> = <f, B g> exactly,
+# <g, g'> = dt sum_j w_j sum_i g g' (sinograms, w_j = pi/V for uniform angles),
+# the projector R = (d^2 / dt) diag(1/w_j) B^T satisfies <R f, g> = <f, B g> exactly,
 # mirroring B = R* of Section 1. With a plain-B plan R approximates the Radon
 # transform (Eq. 1) through the Fourier-slice theorem: the Cartesian density
 # of the transposed gather (~sigma) cancels the 1/sigma weight of P4.
@@ -323,10 +323,12 @@ def backproject_batch(sinos: np.ndarray, geom: Geometry, prm: Params = None) -> 
 #   pad             -> crop;  taper -> taper
 # ----------------------------------------------------------------------------
 def _gather_stencil(geom: Geometry, prm: Params):
-    """Per Cartesian point (b, a) of the half plane: the four (j, m, weight,
-    conjugate) entries of P5, as flat arrays (origin excluded)."""
+    """Per Cartesian point (b, a) of the half plane: the (j, m, weight,
+    conjugate) entries of P5 (two radial taps per angle neighbour, or four for
+    the cubic option), as flat arrays; the origin and the Nyquist column
+    (which have their own rules) and samples past the data are excluded, and
+    a tap at m < 0 becomes the conjugated tap at -m."""
     M, G, _, _ = sizes(geom, prm)
-    V = geom.V
     a = np.arange(G // 2 + 1, dtype=np.float64)[None, :]
     b = np.arange(G, dtype=np.float64)
     b = np.where(b < G // 2, b, b - G)[:, None]
@@ -334,38 +336,31 @@ def _gather_stencil(geom: Geometry, prm: Params):
     phi = np.arctan2(b, a) + 0.0 * a
     lower = phi < 0.0
     theta = np.where(lower, phi + np.pi, phi)
-    q = theta * (V / np.pi)
-    j0 = np.floor(q)
-    f = q - j0
-    j0 = j0.astype(np.int64)
-    over = j0 >= V
-    j0 = np.where(over, V - 1, j0)
-    f = np.where(over, 1.0, f)
-    j1 = j0 + 1
-    wrap = j1 == V
-    j1 = np.where(wrap, 0, j1)
+    j0, j1, f, flip0, flip1 = angle_bracket(theta, geom)
     m0 = np.floor(r)
     g = r - m0
     m0 = m0.astype(np.int64)
     bb, aa = np.meshgrid(np.arange(G), np.arange(G // 2 + 1), indexing="ij")
-    keep = ~((bb == 0) & (aa == 0))
+    keep = ~((bb == 0) & (aa == 0)) & (aa < G // 2)
+    if prm.interp == "linear":
+        radial = ((0, 1 - g), (1, g))
+    else:
+        radial = tuple(zip((-1, 0, 1, 2), keys_weights(g)))
     entries = []
-    for jj, mm, ww, cc in ((j0, m0, (1 - f) * (1 - g), lower),
-                           (j0, m0 + 1, (1 - f) * g, lower),
-                           (j1, m0, f * (1 - g), lower ^ wrap),
-                           (j1, m0 + 1, f * g, lower ^ wrap)):
-        ok = keep & (mm < M // 2)
-        entries.append((bb[ok], aa[ok], jj[ok], mm[ok], ww[ok], cc[ok]))
+    for jj, wa, cc in ((j0, 1 - f, lower ^ flip0), (j1, f, lower ^ flip1)):
+        for off, wr in radial:
+            mm = m0 + off
+            neg = mm < 0
+            mm = np.where(neg, -mm, mm)
+            ok = keep & (mm < M // 2)
+            entries.append((bb[ok], aa[ok], jj[ok], mm[ok], (wa * wr)[ok], (cc ^ neg)[ok]))
     return entries
 
 
 def project(img: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndarray:
-    """R f = (d^2 / (dt w)) B^T f for one image [N][N] -> sinogram [V][n], FP64."""
+    """R f = (d^2 / dt) diag(1 / w_j) B^T f for one image [N][N] -> sinogram
+    [V][n], FP64 (w_j = pi/V for uniform angles, else half the neighbour gap)."""
     prm = prm or Params()
-    if not geom.uniform:
-        raise NotImplementedError("the BST oracle takes uniform angles theta_j = j pi / V")
-    if prm.interp != "linear":
-        raise NotImplementedError("the projector is the transpose of the linear-interpolation BST")
     f = np.asarray(img, dtype=np.float64)
     assert f.shape == (geom.N, geom.N)
     M, G, _, dk = sizes(geom, prm)
@@ -398,5 +393,4 @@ def project(img: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndarray:
     z_t = geom.dt * M * np.fft.ifft(X, axis=-1).real
     # P2 transpose (crop) and P1 (taper)
     y_t = z_t[:, (np.arange(n) - n // 2) % M] * taper(geom, prm)[None, :]
-    w = np.pi / V
-    return (geom.d ** 2 / (geom.dt * w)) * y_t
+    return (geom.d ** 2 / geom.dt) * y_t / geom.w[:, None]

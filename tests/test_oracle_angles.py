@@ -96,3 +96,32 @@ def test_jittered_angles_keep_the_gap():
     disk = np.hypot(u[None, :], u[:, None]) <= (N / 2 - 2) * g.d
     gap = _rel(bst.backproject(y, g, bst.Params())[disk], bf[disk])
     assert gap < 0.035
+
+
+@pytest.mark.parametrize("interp", ["linear", "keys"])
+@pytest.mark.parametrize("first", [0.0, 0.4])
+def test_nonuniform_project_is_the_adjoint(interp, first):
+    N, V = 32, 27
+    g = Geometry(N, V, N, _irregular(V, 21, first))
+    prm = bst.Params(2, 2, "ramp", "keys" if interp == "keys" else "deapod", interp=interp)
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal((N, N))
+    y = rng.standard_normal((V, N))
+    lhs = bruteforce.inner_sino(bst.project(f, g, prm), y, g)
+    rhs = bruteforce.inner_image(f, bst.backproject(y, g, prm), g)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+def test_nonuniform_project_equals_transpose_of_literal_backprojection():
+    N, V = 8, 6
+    g = Geometry(N, V, N, np.array([0.15, 0.6, 1.1, 1.3, 2.2, 2.9]))
+    cols = []
+    for k in range(V * N):
+        e = np.zeros(V * N)
+        e[k] = 1.0
+        cols.append(bst_naive.backproject(e.reshape(V, N), g, 2, 2, "none").ravel())
+    Bmat = np.stack(cols, axis=1)
+    f = np.random.default_rng(12).standard_normal((N, N))
+    expect = (g.d ** 2 / g.dt) * (Bmat.T @ f.ravel()).reshape(V, N) / g.w[:, None]
+    got = bst.project(f, g, bst.Params(2, 2, "none"))
+    assert np.max(np.abs(got - expect)) <= 1e-12 * np.max(np.abs(expect))

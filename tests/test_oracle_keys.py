@@ -109,10 +109,33 @@ def test_keys_narrows_the_gap_to_bruteforce():
     assert cub < 0.025
 
 
-def test_projector_refuses_keys():
-    g = Geometry(16, 8, 16)
-    with pytest.raises(NotImplementedError):
-        bst.project(np.zeros((16, 16)), g, bst.Params(interp="keys"))
+@pytest.mark.parametrize("N,V,P_r,P_c,filt", [(16, 12, 2, 2, "ramp"), (32, 21, 1, 2, "none"),
+                                              (64, 50, 2, 1, "ramp"), (32, 24, 4, 2, "none")])
+def test_keys_project_is_the_adjoint(N, V, P_r, P_c, filt):
+    rng = np.random.default_rng(N + V + 7 * P_r)
+    g = Geometry(N, V, N)
+    prm = bst.Params(P_r, P_c, filt, "keys", interp="keys")
+    f = rng.standard_normal((N, N))
+    y = rng.standard_normal((V, N))
+    lhs = bruteforce.inner_sino(bst.project(f, g, prm), y, g)
+    rhs = bruteforce.inner_image(f, bst.backproject(y, g, prm), g)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+@pytest.mark.parametrize("filt", ["ramp", "none"])
+def test_keys_project_equals_transpose_of_literal_backprojection(filt):
+    N, V = 8, 6
+    g = Geometry(N, V, N)
+    cols = []
+    for k in range(V * N):
+        e = np.zeros(V * N)
+        e[k] = 1.0
+        cols.append(bst_naive.backproject(e.reshape(V, N), g, 2, 2, filt, taper="keys", interp="keys").ravel())
+    Bmat = np.stack(cols, axis=1)
+    f = np.random.default_rng(9).standard_normal((N, N))
+    expect = (g.d ** 2 / (g.dt * np.pi / V)) * (Bmat.T @ f.ravel()).reshape(V, N)
+    got = bst.project(f, g, bst.Params(2, 2, filt, "keys", interp="keys"))
+    assert np.max(np.abs(got - expect)) <= 1e-12 * np.max(np.abs(expect))
 
 
 @pytest.mark.parametrize("interp", ["linear", "keys"])

@@ -80,7 +80,7 @@ typedef enum {
     BST_INTERP_LINEAR = 0,  /* samples m0, m0+1                                       */
     BST_INTERP_KEYS = 1     /* Keys cubic convolution (a = -1/2), samples m0-1 .. m0+2,
                                sample -1 = conj of sample 1; narrows the gap to brute
-                               force (pair it with BST_TAPER_KEYS). Not with adjoint. */
+                               force (pair it with BST_TAPER_KEYS)                    */
 } bst_interp;
 
 typedef struct {
@@ -89,8 +89,7 @@ typedef struct {
     int32_t n_out;          /* N: output side; must equal n_det in this version         */
     const double* angles;   /* host, V values, strictly increasing in [0, pi); NULL =
                                uniform j*pi/V. Step P5 brackets each direction in the
-                               period-pi continuation of the angle sequence. With
-                               adjoint set, non-uniform angles are BST_E_UNSUPPORTED    */
+                               period-pi continuation of the angle sequence            */
     int32_t pad_radial;     /* P_r in {1,2,4}: FFT length M = P_r*n <= 8192 (P2); 0 -> 2 */
     int32_t pad_cart;       /* P_c in {1,2,4}: Cartesian grid G = P_c*N <= 8192; 0 -> 2  */
     int32_t filter;         /* bst_filter                                                */
@@ -107,8 +106,7 @@ typedef struct {
     double center_shift;    /* known rotation-axis offset beta, detector bins: the data
                                are y(t - beta*dt, theta) (Section 1, "Centering"); P4
                                multiplies by exp(+2 pi i sigma beta dt). |beta| < n/4    */
-    int32_t interp;         /* bst_interp (step P5); BST_INTERP_KEYS with adjoint set
-                               is BST_E_UNSUPPORTED                                      */
+    int32_t interp;         /* bst_interp (step P5)                                      */
 } bst_params;
 
 typedef enum {
@@ -174,9 +172,10 @@ bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float*
 
 /* Projector R, the exact adjoint of bst_backproject: steps P8..P1 of Section 2
  * transposed one by one (crop -> zero-embed, C2R inverse FFT -> forward FFT,
- * bilinear gather -> the same weights scattered back, 1D FFT -> its transpose,
- * pad -> crop, taper -> taper), scaled so that under the weighted inner products
- * <f,f'> = d^2 sum f f' and <g,g'> = dt sum_j (pi/V) sum_i g g'
+ * gather (linear or cubic radial taps, any angle set) -> the same weights
+ * scattered back, 1D FFT -> its transpose, pad -> crop, taper -> taper), scaled
+ * so that under the weighted inner products <f,f'> = d^2 sum f f' and
+ * <g,g'> = dt sum_j w_j sum_i g g' (w_j = pi/V, or half the neighbour gap)
  *     <R f, g> = <f, B g>   (B = R* as in Section 1).
  * With a BST_FILTER_NONE plan R is a Fourier-slice (Eq. 1) projector; its
  * transposed gridding is exact as an adjoint but, where polar samples are denser

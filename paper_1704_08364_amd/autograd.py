@@ -18,6 +18,10 @@ from .binding import Plan
 
 
 def adjoint_scale(plan: Plan) -> float:
+    """c with R = c B^T; a single scalar only for uniform angles (for others the
+    library's R carries the factor d^2 / (dt w_j) per angle)."""
+    if plan._angles_keep is not None:
+        raise ValueError("the autograd wrappers take plans with uniform angles")
     d = 2.0 / plan.N
     dt = 2.0 / plan.n
     return d * d / (dt * math.pi / plan.V)

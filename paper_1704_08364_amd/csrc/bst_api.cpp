@@ -20,7 +20,8 @@
 #endif
 
 namespace bst {
-bool build_adjoint_tables(int V, int M, int G, double rscale, std::vector<int>& off, std::vector<uint2>& ent);
+bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<double>& theta, bool uniform,
+                          int taps, std::vector<int>& off, std::vector<uint2>& ent);
 }
 
 namespace {
@@ -160,10 +161,7 @@ bst_status bst_validate(const bst_params* p) {
         p->taper != BST_TAPER_KEYS)
         return BST_E_PARAM;
     if (p->interp != BST_INTERP_LINEAR && p->interp != BST_INTERP_KEYS) return BST_E_PARAM;
-    // the projector is the transpose of the linear-interpolation gather only
-    if (p->interp == BST_INTERP_KEYS && p->adjoint != 0) return BST_E_UNSUPPORTED;
-    // ... and of the uniform-angle gather only
-    if (p->angles != nullptr && p->adjoint != 0) return BST_E_UNSUPPORTED;
+
     if (p->taper == BST_TAPER_KAISER && !(std::isfinite(p->taper_beta) && p->taper_beta >= 0.0 &&
                                           p->taper_beta <= 700.0))
         return BST_E_PARAM;
@@ -190,7 +188,7 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
-                                  p->adjoint != 0 && p->angles == nullptr, p->interp);
+                                  p->adjoint != 0, p->interp);
     return BST_OK;
 }
 
@@ -228,8 +226,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->dc_scale = (float)(dc_rule / pl->V);
     pl->out_scale = (float)(pl->dk * pl->dk);
     pl->device = p->device;
-    pl->adjoint = (p->adjoint != 0) && pl->uniform;
-    pl->proj_scale = (float)(d * d / (pl->dt * (M_PI / pl->V)));
+    pl->adjoint = (p->adjoint != 0);
     pl->gather_slices = BST_GATHER_SLICES;
     pl->gather_e = BST_GATHER_E;
 
@@ -241,7 +238,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::vector<float2> twM(M), twG(G);
     std::vector<double> bf_c(V), bf_s(V), theta(V);
     std::vector<double2> ang(V);
-    std::vector<float> inv_gap(V);
+    std::vector<float> inv_gap(V), proj_row(V);
     for (int i = 0; i < n; ++i) {
         const double t = (i - n / 2) * pl->dt;
         double w = 1.0;
@@ -302,6 +299,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
             w = 0.5 * (next - prev);
         }
         bf_w[j] = (float)w;
+        proj_row[j] = (float)(d * d / (pl->dt * w));
     }
 
     // ---- one device block ----
@@ -316,6 +314,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     const size_t o_w = off;     off = up(off + V * sizeof(float));
     const size_t o_ang = off;   off = up(off + V * sizeof(double2));
     const size_t o_gap = off;   off = up(off + V * sizeof(float));
+    const size_t o_prow = off;  off = up(off + V * sizeof(float));
     const size_t total = off;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
@@ -327,6 +326,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::memcpy(host.data() + o_w, bf_w.data(), V * sizeof(float));
     std::memcpy(host.data() + o_ang, ang.data(), V * sizeof(double2));
     std::memcpy(host.data() + o_gap, inv_gap.data(), V * sizeof(float));
+    std::memcpy(host.data() + o_prow, proj_row.data(), V * sizeof(float));
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -355,7 +355,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     if (pl->adjoint) {
         std::vector<int> off;
         std::vector<uint2> ent;
-        bst::build_adjoint_tables(V, M, G, pl->rscale, off, ent);
+        bst::build_adjoint_tables(V, M, G, pl->rscale, theta, pl->uniform, pl->taps, off, ent);
         pl->n_entries = ent.size();
         const size_t o_ent = up(off.size() * sizeof(int));
         const size_t adj_total = o_ent + std::max<size_t>(ent.size(), 1) * sizeof(uint2);
@@ -389,6 +389,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->bf_w = reinterpret_cast<float*>(base + o_w);
     pl->ang = reinterpret_cast<double2*>(base + o_ang);
     pl->inv_gap = reinterpret_cast<float*>(base + o_gap);
+    pl->proj_row = reinterpret_cast<float*>(base + o_prow);
     *out = pl;
     return BST_OK;
 }
@@ -602,7 +603,7 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     e = bst::launch_proj_gather(*plan, ga, s);
     if (e != hipSuccess) return device_fail(e);
     bst::ProjPolarArgs pa{polar, cart, sino, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
-                          cart_stride, (float)(plan->dt * plan->dc_scale), plan->proj_scale};
+                          cart_stride, (float)(plan->dt * plan->dc_scale), plan->proj_row};
     e = bst::launch_proj_polar(*plan, pa, batch, s);
     if (e != hipSuccess) return device_fail(e);
     return BST_OK;

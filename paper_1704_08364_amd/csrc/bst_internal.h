@@ -38,7 +38,7 @@ struct bst_plan_s {
     int* csr_off;        // [V*M/2 + 1]  entry range of polar sample j*M/2 + m
     uint2* csr_ent;      // [entries]    (point index a*G + b | conj << 31, weight bits)
     size_t n_entries;
-    float proj_scale;    // d^2 / (dt * pi/V): makes R the weighted adjoint of B
+    float* proj_row;     // [V]          d^2 / (dt w_j): makes R the weighted adjoint of B
     int gather_slices;   // slices per gather block (coordinates reused across them)
     int gather_e;        // values per thread of the column transform, 8 or 16: fewer
                          // values mean less per-thread state and more resident waves
@@ -147,7 +147,7 @@ struct ProjPolarArgs {     // polar^T rows -> sinogram rows
     const float2* tw;      // length M
     int n, V, cart_stride;
     float dc_dt;           // dt * dc_scale
-    float scale;           // proj_scale
+    const float* row_scale;  // [V] d^2 / (dt w_j)
 };
 
 hipError_t launch_proj_rows(const bst_plan_s& p, const ProjRowArgs& a, int batch, hipStream_t st);

@@ -21,7 +21,8 @@
 //                  on m = 0), the transpose of the real DFT as the inverse FFT
 //                  of the Hermitian extension (two projections per complex
 //                  FFT), crop of the zero padding, taper, and the factor
-//                  d^2 / (dt pi/V) that makes R the weighted-inner-product
+//                  d^2 / (dt w_j) (w_j = pi/V for uniform angles, else half
+//                  the neighbour gap) that makes R the weighted-inner-product
 //                  adjoint of B.
 #include "bst_internal.h"
 #include "fft_lds.h"
@@ -227,14 +228,15 @@ __global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG) k_proj_polar(ProjPolar
     const int h = a.n >> 1;
     float* oa = a.sino + ((size_t)s * a.V + ja) * a.n;
     float* ob = oa + a.n;
+    const float sa = a.row_scale[va ? ja : 0], sb = a.row_scale[vb ? jb : 0];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int x = j + e * T;
         const int i = (x < h) ? x + h : ((x >= M - h) ? x - M + h : -1);
         if (i >= 0) {
-            const float w = a.taper[i] * a.scale;
-            if (va) oa[i] = w * v[e].x;
-            if (vb) ob[i] = w * v[e].y;
+            const float w = a.taper[i];
+            if (va) oa[i] = (w * sa) * v[e].x;
+            if (vb) ob[i] = (w * sb) * v[e].y;
         }
     }
 }

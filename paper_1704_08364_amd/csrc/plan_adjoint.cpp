@@ -1,13 +1,18 @@
 // plan_adjoint.cpp -- host construction of the transposed gather used by
 // bst_project: for every polar sample (j, m), m < M/2, the list of Cartesian
-// half-plane points (a, b) whose bilinear stencil (step P5 of Section 2)
-// reads it, with the stencil weight and the conjugation flag. Coordinates are
-// formed in FP64 with the same rules as the forward gather: radius index
-// r = |(a,b)| P_r/P_c, angle index q = theta V/pi with theta = atan2(b, a)
-// (plus pi and conjugation below the k_x axis), neighbour past theta_{V-1} =
-// theta_0 with the conjugation flipped, samples m >= M/2 zero, the origin
-// excluded (it has its own rule). Lists are filled in increasing point order,
-// so the device sum has a fixed order.
+// half-plane points (a, b) whose stencil (step P5 of Section 2) reads it,
+// with the stencil weight and the conjugation flag. Coordinates are formed in
+// FP64 with the same rules as the forward gather: radius index
+// r = |(a,b)| P_r/P_c; direction theta = atan2(b, a) (plus pi and conjugation
+// below the k_x axis), bracketed in the period-pi continuation of the angle
+// sequence (uniform: q = theta V/pi; otherwise the last angle <= theta, the
+// image theta_{V-1} - pi below theta_0, theta_0 + pi past theta_{V-1}, images
+// conjugated); radial taps m0, m0+1 (linear) or m0-1 .. m0+2 with the Keys
+// weights (a = -1/2), a tap at m < 0 read as the conjugate of -m; samples
+// m >= M/2 zero; the origin and the Nyquist column k_x = G/2 excluded (they
+// have their own rules). Lists are filled in increasing point order, so the
+// device sum has a fixed order.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -23,45 +28,85 @@ struct StencilEntry {
     float w;
 };
 
-bool build_adjoint_tables(int V, int M, int G, double rscale, std::vector<int>& off,
-                          std::vector<uint2>& ent) {
+namespace {
+
+// Keys cubic convolution weight (a = -1/2) at distance x
+double keys_weight(double x) {
+    x = std::fabs(x);
+    if (x <= 1.0) return (1.5 * x - 2.5) * x * x + 1.0;
+    if (x < 2.0) return ((-0.5 * x + 2.5) * x - 4.0) * x + 2.0;
+    return 0.0;
+}
+
+}  // namespace
+
+bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<double>& theta, bool uniform,
+                          int taps, std::vector<int>& off, std::vector<uint2>& ent) {
     const int Mh = M / 2;
     const size_t samples = (size_t)V * Mh;
     off.assign(samples + 1, 0);
     std::vector<StencilEntry> tmp;
-    tmp.reserve((size_t)G * G);  // ~ 4 entries x (G/2 x G) x pi/4
+    tmp.reserve((size_t)G * G * (taps / 2));  // ~ 2*taps entries x (G/2 x G) x pi/4
     for (int a = 0; a < G / 2; ++a) {
         for (int bi = 0; bi < G; ++bi) {
             const int b = bi < G / 2 ? bi : bi - G;
             if (a == 0 && b == 0) continue;
             const double r = std::sqrt((double)a * a + (double)b * b) * rscale;
-            if (r >= (double)Mh) continue;
+            if (r >= (double)Mh + (taps == 4 ? 1.0 : 0.0)) continue;
             const double phi = std::atan2((double)b, (double)a);
             const bool lower = phi < 0.0;
             const double th = lower ? phi + M_PI : phi;
-            const double q = th * ((double)V / M_PI);
-            double qf = std::floor(q);
-            double f = q - qf;
-            int j0 = (int)qf;
-            if (j0 >= V) { j0 = V - 1; f = 1.0; }
+            int j0;
+            double f;
+            bool flip0 = false;
+            if (uniform) {
+                const double q = th * ((double)V / M_PI);
+                const double qf = std::floor(q);
+                f = q - qf;
+                j0 = (int)qf;
+                if (j0 >= V) { j0 = V - 1; f = 1.0; }
+            } else {
+                // last theta_j <= th; below theta_0 the image theta_{V-1} - pi
+                const int k = (int)(std::upper_bound(theta.begin(), theta.end(), th) - theta.begin()) - 1;
+                double lo, hi;
+                if (k < 0) {
+                    j0 = V - 1;
+                    flip0 = true;
+                    lo = theta[V - 1] - M_PI;
+                    hi = theta[0];
+                } else {
+                    j0 = k;
+                    lo = theta[k];
+                    hi = (k + 1 < V) ? theta[k + 1] : theta[0] + M_PI;
+                }
+                f = (th - lo) / (hi - lo);
+            }
             int j1 = j0 + 1;
             const bool wrap = (j1 == V);
             if (wrap) j1 = 0;
+            const bool c0 = lower != flip0;
+            const bool c1 = lower != (wrap && !flip0);
             const double mf = std::floor(r);
             const double g = r - mf;
             const int m0 = (int)mf;
             const uint32_t pt = (uint32_t)a * (uint32_t)G + (uint32_t)bi;
-            const struct { int j, m; double w; bool c; } e4[4] = {
-                {j0, m0, (1 - f) * (1 - g), lower},
-                {j0, m0 + 1, (1 - f) * g, lower},
-                {j1, m0, f * (1 - g), lower != wrap},
-                {j1, m0 + 1, f * g, lower != wrap},
-            };
-            for (const auto& e : e4) {
-                if (e.m >= Mh || e.w == 0.0) continue;
-                const int smp = e.j * Mh + e.m;
-                tmp.push_back({smp, pt | (e.c ? 0x80000000u : 0u), (float)e.w});
-                off[smp + 1]++;
+            const int first = (taps == 4) ? -1 : 0;
+            for (int side = 0; side < 2; ++side) {
+                const int j = side ? j1 : j0;
+                const double wa = side ? f : 1.0 - f;
+                const bool c = side ? c1 : c0;
+                for (int t = 0; t < taps; ++t) {
+                    const int off_m = first + t;
+                    const double wr = (taps == 4) ? keys_weight(g - off_m) : (off_m == 0 ? 1.0 - g : g);
+                    int m = m0 + off_m;
+                    bool cc = c;
+                    if (m < 0) { m = -m; cc = !cc; }
+                    const double w = wa * wr;
+                    if (m >= Mh || w == 0.0) continue;
+                    const int smp = j * Mh + m;
+                    tmp.push_back({smp, pt | (cc ? 0x80000000u : 0u), (float)w});
+                    off[smp + 1]++;
+                }
             }
         }
     }

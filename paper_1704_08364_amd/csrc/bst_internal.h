@@ -104,6 +104,7 @@ struct RowArgs {
     int N;
     int GT;                     // grid tile-row width (columns)
     float scale;
+    int tiles;                  // row-pair groups per block (set by the launcher)
 };
 
 struct BfArgs {

@@ -15,6 +15,11 @@
 
 namespace bst {
 
+// most row-pair groups (8-row tiles) a block walks, for G <= 4096
+#ifndef BST_ROW_TILES
+#define BST_ROW_TILES 16
+#endif
+
 // extra float2 between the LDS regions of a block's row pairs
 #ifndef BST_ROW_PAD
 #define BST_ROW_PAD 8
@@ -31,6 +36,8 @@ struct RowCfg {
     static constexpr int T = G / 16;
     static constexpr int F = G <= 4096 ? BST_ROW_PAIRS : (G == 8192 ? 2 : 1);  // row pairs per block
     static constexpr int WG = F * T;
+    static constexpr int MAX_TILES = G <= 4096 ? BST_ROW_TILES : 1;  // row-pair groups per block, at most
+    static_assert(T * 16 == G, "16 values per thread");
 };
 
 template <int LOGG>
@@ -40,60 +47,93 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     // regions 8 float2 (16 banks) apart, so interleaved lanes of different row
     // pairs fall on different banks
     constexpr int STRIDE = FftShape<LOGG>::LDS + BST_ROW_PAD;
-    __shared__ float2 lds[C::F * STRIDE];
+    __shared__ __attribute__((aligned(16))) float2 lds[C::F * STRIDE];
     // thread t serves row pair t mod F: the lanes of a wave read F neighbouring
     // 16-byte pairs of each k, i.e. contiguous runs of the [G/2][8] tile
     const int fid = threadIdx.x % C::F;
     const int j = threadIdx.x / C::F;
     float2* my = lds + fid * STRIDE;
-    const int row0 = blockIdx.x * (2 * C::F) + 2 * fid;
     const int s = blockIdx.y;
-    const int sub = row0 & 7;
-    const float4* tile = reinterpret_cast<const float4*>(
-        a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * a.GT);
+    const int groups = a.N / (2 * C::F);             // row-pair groups (tiles) per slice
+    const int g0 = blockIdx.x * a.tiles;
+    float* const img_s = a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N;
+    const FftTwiddles<LOGG, +1, 16> tw(j, a.tw);
 
-    // all loads first, branch-free: k < G/2 reads k, k > G/2 reads G - k
-    // (Hermitian extension), k = G/2 reads k = 0 and is replaced by zero
-    float4 q[16];
+    // Thread j's slots e < 8 are k = j + e*T < G/2: the block reads every
+    // stored column once (all loads first, no branch between them) and puts
+    // it in LDS, where the Hermitian extension k > G/2 (the conjugate of
+    // column G - k) is read back; k = G/2 is zero. A block walks TILES
+    // groups, the next group's reads in flight during the current group's
+    // transform.
+    auto load = [&](int grp, float4 (&q)[8]) {
+        const int row0 = (grp < groups ? grp : 0) * (2 * C::F) + 2 * fid;
+        const float4* tile = reinterpret_cast<const float4*>(
+            a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * a.GT);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int k = j + e * T;
-        const int kk = k < G / 2 ? k : (k == G / 2 ? 0 : G - k);
-        q[e] = tile[kk * 4 + (sub >> 1)];
-    }
-    float* o0 = (a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N) + (size_t)row0 * a.N;
-    float* o1 = o0 + a.N;
-
-    float2 v[16];
+        for (int e = 0; e < 8; ++e) q[e] = tile[(j + e * T) * 4 + ((row0 & 7) >> 1)];
+    };
+    float4 q[8];
+    load(g0, q);
+#pragma unroll 1
+    for (int it = 0; it < a.tiles; ++it) {
+        const int grp = g0 + it;
+        int jv = j;
+        asm volatile("" : "+v"(jv));
+        float4* stage = reinterpret_cast<float4*>(lds);  // [G/2][F] of the group's row pairs
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int k = j + e * T;
-        const bool mid = k == G / 2;
-        // imaginary parts: dropped at k = 0 (C2R convention), conjugated for k > G/2
-        const float sy = (k == 0 || mid) ? 0.f : (k < G / 2 ? 1.f : -1.f);
-        const float2 x0 = make_float2(mid ? 0.f : q[e].x, sy * q[e].y);
-        const float2 x1 = make_float2(mid ? 0.f : q[e].z, sy * q[e].w);
-        v[e] = make_float2(x0.x - x1.y, x0.y + x1.x);
-    }
+        for (int e = 0; e < 8; ++e) stage[(jv + e * T) * C::F + fid] = q[e];
+        __syncthreads();
 
-    fft<LOGG, +1>(v, my, j, a.tw);
-
-    const int half_n = a.N >> 1;
+        float2 v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int x = j + e * T;
-        const int c = (x + half_n) & (G - 1);
-        if (c < a.N) {
-            o0[c] = v[e].x * a.scale;
-            o1[c] = v[e].y * a.scale;
+        for (int e = 0; e < 16; ++e) {
+            const int k = jv + e * T;
+            const bool lo = e < 8;
+            const int kk = G - k;                     // mirrored column for k > G/2
+            const float4 m = lo ? q[e] : stage[(kk & (G / 2 - 1)) * C::F + fid];
+            const bool mid = k == G / 2;
+            // imaginary parts: dropped at k = 0 (C2R convention), conjugated for k > G/2
+            const float sy = (k == 0 || mid) ? 0.f : (lo ? 1.f : -1.f);
+            const float2 x0 = make_float2(mid ? 0.f : m.x, sy * m.y);
+            const float2 x1 = make_float2(mid ? 0.f : m.z, sy * m.w);
+            v[e] = make_float2(x0.x - x1.y, x0.y + x1.x);
+        }
+        __syncthreads();  // the transform overwrites the staged columns
+        if (it + 1 < a.tiles) load(grp + 1, q);
+
+        FftTwiddles<LOGG, +1, 16> twl = tw;
+        twl.pin();
+        fft<LOGG, +1>(v, my, jv, twl);
+
+        if (grp < groups) {
+            const int row0 = grp * (2 * C::F) + 2 * fid;
+            float* o0 = img_s + (size_t)row0 * a.N;
+            float* o1 = o0 + a.N;
+            const int half_n = a.N >> 1;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int x = jv + e * T;
+                const int c = (x + half_n) & (G - 1);
+                if (c < a.N) {
+                    o0[c] = v[e].x * a.scale;
+                    o1[c] = v[e].y * a.scale;
+                }
+            }
         }
     }
 }
 
 template <int LOGG>
-static hipError_t launch_row_t(const RowArgs& a, int batch, hipStream_t st) {
+static hipError_t launch_row_t(const RowArgs& a0, int batch, hipStream_t st) {
     using C = RowCfg<LOGG>;
-    dim3 grid(a.N / (2 * C::F), batch);
+    RowArgs a = a0;
+    const int groups = a.N / (2 * C::F);
+    // as many groups per block as keep about four blocks per compute unit
+    constexpr int kTargetBlocks = 1024;
+    int tiles = (int)(((long long)groups * batch) / kTargetBlocks);
+    tiles = tiles < 1 ? 1 : (tiles > C::MAX_TILES ? C::MAX_TILES : tiles);
+    a.tiles = tiles;
+    dim3 grid((groups + tiles - 1) / tiles, batch);
     hipLaunchKernelGGL(k_row_c2r<LOGG>, grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }

@@ -307,6 +307,7 @@ bst_status bst_batch_tune(bst_batch_t b, const float* sinos, const int64_t* sino
 
 bst_status bst_batch_backproject(bst_batch_t b, const float* sinos, const int64_t* sino_off, float* imgs,
                                  const int64_t* img_off, void* ws, size_t ws_bytes, void* stream) {
+    bst::TraceRange trace("bst_batch_backproject");
     Guard guard(b ? b->device : 0);
     if (guard.err != hipSuccess) return fail(guard.err);
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -449,6 +449,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
 
     DeviceGuard guard(plan->device);
     if (guard.err != hipSuccess) return device_fail(guard.err);
+    bst::TraceRange trace(spectrum_only ? "bst_debug_spectrum" : "bst_backproject");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bst::WsLayout L =
         bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp);
@@ -465,7 +466,10 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     bst::SpecArgs sa{sino,   sino_list, flat,    dark,       polar,          dc,
                      plan->taper, plan->kc, plan->tw_M, plan->n, plan->V, plan->S,
                      plan->lead,  plan->S - plan->lead - plan->M / 2, (float)plan->dt};
-    e = bst::launch_spectrum(*plan, sa, batch, s);
+    {
+        bst::TraceRange tr("bst P1-P4 spectrum");
+        e = bst::launch_spectrum(*plan, sa, batch, s);
+    }
     if (e != hipSuccess) return device_fail(e);
     if (ev && ev[1]) {
         e = hipEventRecord(static_cast<hipEvent_t>(ev[1]), s);
@@ -499,14 +503,20 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.inv_gap = plan->inv_gap;
     ga.uniform = plan->uniform ? 1 : 0;
     ga.dc_scale = plan->dc_scale;
-    e = bst::launch_gather_colifft(*plan, ga, s);
+    {
+        bst::TraceRange tr("bst P5-P6 gather + column IFFT");
+        e = bst::launch_gather_colifft(*plan, ga, s);
+    }
     if (e != hipSuccess) return device_fail(e);
     if (ev && ev[2]) {
         e = hipEventRecord(static_cast<hipEvent_t>(ev[2]), s);
         if (e != hipSuccess) return device_fail(e);
     }
     bst::RowArgs ra{grid, img, img_list, plan->tw_G, plan->N, plan->GT, plan->out_scale};
-    e = bst::launch_row_c2r(*plan, ra, batch, s);
+    {
+        bst::TraceRange tr("bst P6-P8 row C2R + crop");
+        e = bst::launch_row_c2r(*plan, ra, batch, s);
+    }
     if (e != hipSuccess) return device_fail(e);
     if (ev && ev[3]) {
         e = hipEventRecord(static_cast<hipEvent_t>(ev[3]), s);
@@ -562,6 +572,7 @@ bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float*
     DeviceGuard guard(plan->device);
     if (guard.err != hipSuccess) return device_fail(guard.err);
     bst::BfArgs a{sino, img, plan->bf_c, plan->bf_s, plan->bf_w, plan->n, plan->V, plan->N};
+    bst::TraceRange tr("bst_backproject_bruteforce");
     const hipError_t e = bst::launch_bruteforce(*plan, a, batch, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_fail(e);
     return BST_OK;
@@ -593,6 +604,7 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     const int cart_stride = (plan->G / 2) * plan->G;
 
     bst::ProjRowArgs ra{img, grid, plan->tw_G, plan->N, plan->out_scale};
+    bst::TraceRange tr("bst_project");
     hipError_t e = bst::launch_proj_rows(*plan, ra, batch, s);
     if (e != hipSuccess) return device_fail(e);
     bst::ProjColArgs ca{grid, cart, plan->tw_G, plan->N};

@@ -2,8 +2,20 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "bst.h"
+
+namespace bst {
+// Host-side trace range (roctx): shows each entry point and pipeline stage as
+// a named range in rocprofv3 --marker-trace; a cheap call when no profiler runs.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+}  // namespace bst
 
 struct bst_plan_s {
     bst_params prm;      // copy of the caller's parameters (angles pointer cleared)

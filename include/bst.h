@@ -222,8 +222,9 @@ bst_status bst_batch_destroy(bst_batch_t b);
 /* Free the plan's device tables and the plan. NULL is accepted. */
 bst_status bst_destroy(bst_plan_t plan);
 
-/* Static text for a status code. */
-const char* bst_status_string(bst_status s);
+/* Static text for a status code (a bst_status value; any other integer gives
+   "unknown status"). */
+const char* bst_status_string(int32_t status);
 
 /* Text of the last HIP error seen by this thread ("" if none). */
 const char* bst_last_error_string(void);

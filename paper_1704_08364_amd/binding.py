@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbst.so")
+# BST_LIBRARY selects another build of the same library (for instance the
+# host-sanitizer build of `python -m paper_1704_08364_amd.build --host-sanitize`).
+LIB_PATH = os.environ.get("BST_LIBRARY") or os.path.join(_HERE, "libbst.so")
 
 BST_OK = 0
 STATUS_NAMES = {

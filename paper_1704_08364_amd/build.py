@@ -1,6 +1,14 @@
 """Build the HIP library libbst.so in-tree for gfx950 with hipcc.
 
 Usage: python -m paper_1704_08364_amd.build   (or call build())
+
+`--host-sanitize` (or build(host_sanitize=True)) builds a second library,
+_build_hostsan/libbst_hostsan.so: the host sources (C ABI, argument checks,
+workspace arithmetic, plan tables, batch graphs) instrumented with
+AddressSanitizer and UndefinedBehaviorSanitizer on the host side only, linked
+with the ordinary kernel objects (device code is never instrumented). Load it
+with BST_LIBRARY=<path> and LD_PRELOAD=<clang ASan runtime> (see
+host_sanitizer_runtime()).
 """
 from __future__ import annotations
 
@@ -16,6 +24,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbst.so")
+SAN_DIR = os.path.join(HERE, "_build_hostsan")
+SAN_LIB = os.path.join(SAN_DIR, "libbst_hostsan.so")
 
 SOURCES = ["bst_api.cpp", "plan_adjoint.cpp", "batch.cpp", "k_spectrum.hip", "k_gather_colifft.hip", "k_row_c2r.hip",
            "k_bruteforce.hip", "k_project.hip"]
@@ -28,35 +38,75 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+# -fsanitize= goes to the host compilation only (-Xarch_host before each).
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SAN_COMPILE = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "--offload-host-only",
+               f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"] + SAN_FLAGS
+HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]
+
+
+def _stale(obj: str, src: str) -> bool:
+    """True when obj is missing or older than its source or any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")] + [
+        os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE)]
+    return os.path.getmtime(obj) < max(os.path.getmtime(d) for d in deps)
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    obj = os.path.join(SAN_DIR if sanitize else OBJDIR, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    flags = SAN_COMPILE if sanitize else COMMON
+    cmd = [HIPCC] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def host_sanitizer_runtime() -> str:
+    """Path of the clang ASan runtime (with the UBSan handlers) that matches hipcc."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("clang ASan runtime not found next to hipcc")
+    return path
+
+
+def build(verbose: bool = False, host_sanitize: bool = False) -> str:
     if shutil.which(HIPCC) is None and not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
-    os.makedirs(OBJDIR, exist_ok=True)
+    out = SAN_LIB if host_sanitize else LIB
+    os.makedirs(SAN_DIR if host_sanitize else OBJDIR, exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
-    with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+    if host_sanitize:
+        # instrumented host sources + the ordinary kernel objects (rebuilt only when stale)
+        os.makedirs(OBJDIR, exist_ok=True)
+        kern = [s for s in SOURCES if s not in HOST_SOURCES]
+        todo = [s for s in kern if _stale(os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o"), s)]
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            list(ex.map(_compile, todo))
+            objs = list(ex.map(lambda src: _compile(src, True), HOST_SOURCES))
+        objs += [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in kern]
+    else:
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            objs = list(ex.map(_compile, SOURCES))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + [
         f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
+    if host_sanitize:
+        cmd += SAN_FLAGS + ["-shared-libsan"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {out}")
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, host_sanitize="--host-sanitize" in sys.argv[1:])
     sys.exit(0)

@@ -639,8 +639,9 @@ bst_status bst_destroy(bst_plan_t plan) {
     return st;
 }
 
-const char* bst_status_string(bst_status s) {
-    switch (s) {
+const char* bst_status_string(int32_t status) {
+    // switch on the integer: a value outside the enumerators is not a valid bst_status in C++
+    switch (status) {
         case BST_OK: return "ok";
         case BST_E_NULL: return "null pointer argument";
         case BST_E_SHAPE: return "unsupported or inconsistent sizes";

@@ -4,11 +4,11 @@ Usage: python -m paper_1704_08364_amd.build   (or call build())
 
 `--host-sanitize` (or build(host_sanitize=True)) builds a second library,
 _build_hostsan/libbst_hostsan.so: the host sources (C ABI, argument checks,
-workspace arithmetic, plan tables, batch graphs) instrumented with
-AddressSanitizer and UndefinedBehaviorSanitizer on the host side only, linked
-with the ordinary kernel objects (device code is never instrumented). Load it
-with BST_LIBRARY=<path> and LD_PRELOAD=<clang ASan runtime> (see
-host_sanitizer_runtime()).
+workspace arithmetic, plan tables, batch graphs) compiled by g++ with
+AddressSanitizer and UndefinedBehaviorSanitizer, linked with the ordinary
+kernel objects (device code is never instrumented). GCC's ASan runtime leaves
+the HSA allocator alone, so the library also runs kernels on a GPU. Load it
+in a process started with the variables of host_sanitizer_env().
 """
 from __future__ import annotations
 
@@ -37,11 +37,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"]
 
-
-# -fsanitize= goes to the host compilation only (-Xarch_host before each).
-SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
-SAN_COMPILE = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "--offload-host-only",
+# host sources only, compiled by g++ (no .hip file on these lines)
+GXX = os.environ.get("BST_HOST_CXX", "g++")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
+SAN_COMPILE = ["-O1", "-g", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
                f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function"] + SAN_FLAGS
 HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]
 
@@ -57,22 +56,53 @@ def _stale(obj: str, src: str) -> bool:
 
 def _compile(src: str, sanitize: bool = False) -> str:
     obj = os.path.join(SAN_DIR if sanitize else OBJDIR, os.path.splitext(src)[0] + ".o")
-    lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    flags = SAN_COMPILE if sanitize else COMMON
-    cmd = [HIPCC] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if sanitize:
+        cmd = [GXX] + SAN_COMPILE + ["-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        raise RuntimeError(f"compile failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def host_sanitizer_runtime() -> str:
-    """Path of the clang ASan runtime (with the UBSan handlers) that matches hipcc."""
-    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
-    path = r.stdout.strip()
-    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
-        raise RuntimeError("clang ASan runtime not found next to hipcc")
-    return path
+def host_sanitizer_preload() -> str:
+    """LD_PRELOAD value for a process that loads the host-sanitizer library: the
+    ASan runtime of the g++ that built it, then libstdc++ (ASan resolves its
+    C++ exception interceptor at start-up, and Python does not load libstdc++
+    itself)."""
+    paths = []
+    for name in ("libasan.so", "libstdc++.so.6"):
+        r = subprocess.run([GXX, f"-print-file-name={name}"], capture_output=True, text=True)
+        path = r.stdout.strip()
+        if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+            raise RuntimeError(f"{name} of {GXX} not found")
+        paths.append(path)
+    return " ".join(paths)
+
+
+def host_sanitizer_env(log_dir: str | None = None) -> dict:
+    """Environment additions for a process that runs the host-sanitizer library.
+
+    Besides BST_LIBRARY and LD_PRELOAD: torch's lib directory goes on
+    LD_LIBRARY_PATH, because under ASan's dlopen interceptor torch's own
+    $ORIGIN-relative dlopen calls (its runtime-compiler stub) no longer find
+    their files; leak checking is off (Python is not instrumented and keeps its
+    arenas to the end); every report ends the process with status 86 (ASan) or
+    a non-zero status (UBSan), written to log_dir when given."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    torch_lib = os.path.join(os.path.dirname(spec.origin), "lib") if spec and spec.origin else ""
+    asan = "detect_leaks=0:exitcode=86"
+    ubsan = "print_stacktrace=1:halt_on_error=1"
+    if log_dir:
+        asan += f":log_path={os.path.join(log_dir, 'asan')}"
+        ubsan += f":log_path={os.path.join(log_dir, 'ubsan')}"
+    ld = os.environ.get("LD_LIBRARY_PATH", "")
+    return {"BST_LIBRARY": SAN_LIB, "LD_PRELOAD": host_sanitizer_preload(),
+            "LD_LIBRARY_PATH": ":".join(x for x in (torch_lib, ld) if x),
+            "ASAN_OPTIONS": asan, "UBSAN_OPTIONS": ubsan}
 
 
 def build(verbose: bool = False, host_sanitize: bool = False) -> str:
@@ -94,10 +124,11 @@ def build(verbose: bool = False, host_sanitize: bool = False) -> str:
         with ThreadPoolExecutor(max_workers=jobs) as ex:
             objs = list(ex.map(_compile, SOURCES))
     tmp = out + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + [
-        f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
+    libs = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
     if host_sanitize:
-        cmd += SAN_FLAGS + ["-shared-libsan"]
+        cmd = [GXX, "-shared", "-fPIC", "-o", tmp] + objs + libs + ["-lamdhip64"] + SAN_FLAGS
+    else:
+        cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + libs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

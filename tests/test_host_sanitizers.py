@@ -2,9 +2,9 @@
 status strings) under AddressSanitizer and UndefinedBehaviorSanitizer.
 
 Builds the host-instrumented library (`build(host_sanitize=True)`: host
-sources with -fsanitize=address,undefined on the host pass only, ordinary
-kernel objects) and runs the ABI tests against it in a child process with the
-clang ASan runtime preloaded. Any sanitizer report ends the child with a
+sources compiled by g++ with -fsanitize=address,undefined, ordinary kernel
+objects) and runs the ABI tests against it in a child process with the
+ASan runtime preloaded. Any sanitizer report ends the child with a
 non-zero status (UBSan is built with -fno-sanitize-recover). CPU only."""
 import os
 import shutil
@@ -19,25 +19,21 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _runtime_or_skip():
+    """Skip where hipcc or g++'s sanitizer runtimes are missing."""
     if shutil.which(B.HIPCC) is None and not os.path.exists(B.HIPCC):
         pytest.skip("hipcc not available")
     try:
-        return B.host_sanitizer_runtime()
+        return B.host_sanitizer_preload()
     except RuntimeError as e:
         pytest.skip(str(e))
 
 
 def test_abi_tests_pass_under_asan_and_ubsan(tmp_path):
-    rt = _runtime_or_skip()
+    _runtime_or_skip()
     lib = B.build(host_sanitize=True)
+    assert lib == B.SAN_LIB
     env = dict(os.environ)
-    env.update({
-        "BST_LIBRARY": lib,
-        "LD_PRELOAD": rt,
-        # Python itself is not instrumented and keeps its arenas to the end
-        "ASAN_OPTIONS": "detect_leaks=0:abort_on_error=0:exitcode=86",
-        "UBSAN_OPTIONS": "print_stacktrace=1:halt_on_error=1",
-    })
+    env.update(B.host_sanitizer_env())
     log = tmp_path / "abi_sanitized.log"
     with open(log, "w") as f:
         r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_abi.py"), "-x", "-q",

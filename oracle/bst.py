@@ -45,11 +45,23 @@ Discrete steps (readings where the paper is silent are listed beside each):
   P7  fftshift and P8 restriction to the N x N output grid:
       out[p][q] = b[(p - N/2) mod G][(q - N/2) mod G]. Because n dt = N d = 2
       the inverse-DFT pitch equals the pixel pitch, so P8 needs no resampling.
+
+Monopole subtraction (option of plain B, for the origin artifacts that Section 2
+attributes to the sinogram not vanishing at t = 0): B y has a slowly decaying
+tail ~ (mass)/|x| whose periodic images on the G-point grid the origin rule can
+only approximate. With phi(t) the unit-mass Gaussian of width s centred on the
+rotation axis (t = beta dt) and m = mean_j sum_i y[j][i] / sum_i phi(t_i),
+  B y = B (y - m phi) + m b_phi,   b_phi(u) = int_0^pi phi(u . xi_theta) dtheta
+                                             = (pi / (sqrt(2 pi) s)) e^{-rho} I0(rho),
+rho = |u|^2 / (4 s^2) (from int_0^pi exp(-a cos^2 theta) dtheta = pi e^{-a/2} I0(a/2)).
+The BST steps run on the residual y - m phi, whose mean projection mass is
+zero, and m b_phi is added to the image in closed form.
 """
 from __future__ import annotations
 
 import numpy as np
 from scipy.special import i0 as bessel_i0
+from scipy.special import i0e as bessel_i0e
 
 from .geometry import Geometry
 
@@ -66,12 +78,15 @@ class Params:
     `center_shift` is a known rotation-axis offset beta in detector bins: the
     measured sinogram is y(t - beta dt, theta) (Section 1, centering), undone in
     P4 by the phase exp(+2 pi i sigma beta dt). `interp` is the radial
-    interpolation of P5: 'linear' or 'keys' (cubic convolution)."""
+    interpolation of P5: 'linear' or 'keys' (cubic convolution). `monopole` is
+    the width s of the subtracted Gaussian (plain B only; 0 = off), in the
+    units of t (the detector spans [-1, 1))."""
 
     def __init__(self, pad_radial: int = 2, pad_cart: int = 2, filter: str = "ramp",
                  taper: str = "deapod", beta: float = 8.0, apod: str = "ramlak",
-                 center_shift: float = 0.0, interp: str = "linear"):
+                 center_shift: float = 0.0, interp: str = "linear", monopole: float = 0.0):
         assert filter in ("ramp", "none")
+        assert monopole >= 0.0 and (monopole == 0.0 or filter == "none")
         assert taper in ("deapod", "none", "kb", "keys")
         assert apod in APODIZATIONS
         assert interp in INTERPS
@@ -83,6 +98,7 @@ class Params:
         self.apod = apod
         self.center_shift = float(center_shift)
         self.interp = interp
+        self.monopole = float(monopole)
 
 
 def sizes(geom: Geometry, prm: Params):
@@ -289,13 +305,42 @@ def spectrum(sino: np.ndarray, geom: Geometry, prm: Params):
     return Yh, Y[:, 0].real.copy()
 
 
+# Monopole subtraction (plain B) ------------------------------------------------
+def monopole_profile(geom: Geometry, prm: Params) -> np.ndarray:
+    """phi(t_i - beta dt): the unit-mass Gaussian of width s on the rotation axis."""
+    s = prm.monopole
+    t = geom.t() - prm.center_shift * geom.dt
+    return np.exp(-t * t / (2.0 * s * s)) / (np.sqrt(2.0 * np.pi) * s)
+
+
+def monopole_mass(sino: np.ndarray, geom: Geometry, prm: Params) -> float:
+    """m = mean_j sum_i y[j][i] / sum_i phi(t_i - beta dt)."""
+    y = np.asarray(sino, dtype=np.float64)
+    return float(np.mean(y.sum(axis=1)) / monopole_profile(geom, prm).sum())
+
+
+def monopole_image(geom: Geometry, prm: Params) -> np.ndarray:
+    """b_phi on the output grid: (pi / (sqrt(2 pi) s)) e^{-rho} I0(rho), rho = |u|^2 / (4 s^2)."""
+    s = prm.monopole
+    u = geom.u()
+    rho = (u[None, :] ** 2 + u[:, None] ** 2) / (4.0 * s * s)
+    return (np.pi / (np.sqrt(2.0 * np.pi) * s)) * bessel_i0e(rho)
+
+
 def backproject(sino: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndarray:
     """BST backprojection of one sinogram [V][n] -> image [N][N], FP64."""
     prm = prm or Params()
     M, G, _, dk = sizes(geom, prm)
-    Yh, Y0 = spectrum(sino, geom, prm)
+    y = np.asarray(sino, dtype=np.float64)
+    if prm.monopole > 0.0:
+        m = monopole_mass(y, geom, prm)
+        y = y - m * monopole_profile(geom, prm)[None, :]
+    Yh, Y0 = spectrum(y, geom, prm)
     C = gather(Yh, Y0, geom, prm)
-    return shift_crop(inverse(C, G, dk), geom.N)
+    img = shift_crop(inverse(C, G, dk), geom.N)
+    if prm.monopole > 0.0:
+        img = img + m * monopole_image(geom, prm)
+    return img
 
 
 def backproject_batch(sinos: np.ndarray, geom: Geometry, prm: Params = None) -> np.ndarray:

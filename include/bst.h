@@ -107,6 +107,17 @@ typedef struct {
                                are y(t - beta*dt, theta) (Section 1, "Centering"); P4
                                multiplies by exp(+2 pi i sigma beta dt). |beta| < n/4    */
     int32_t interp;         /* bst_interp (step P5)                                      */
+    double monopole_width;  /* BST_FILTER_NONE only; 0 = off. Width s (units of t: the
+                               detector spans [-1, 1)) of a unit-mass Gaussian phi on the
+                               rotation axis. Against the origin artifacts of Section 2,
+                               m phi, m = mean_j sum_i y_ji / sum_i phi(t_i - beta dt), is
+                               subtracted from every projection before P1 and its
+                               backprojection m (pi/(sqrt(2 pi) s)) e^-rho I0(rho),
+                               rho = |u|^2/(4 s^2), added to the image. The 1/|x| mass
+                               tail of B y then no longer wraps around the FFT grid.
+                               4 dt <= s <= 2; not with adjoint (the result is no longer
+                               the transpose of bst_project). Adds a reduction kernel
+                               and a [batch][64] float32 workspace array.                */
 } bst_params;
 
 typedef enum {
@@ -126,8 +137,9 @@ bst_status bst_validate(const bst_params* p);
 /* Workspace bytes for `batch` slices (host only, no plan needed).
  * bst_backproject: polar spectra [batch][V][M/2+2] complex64 ([batch][V][M/2+5]
  * with BST_INTERP_KEYS: one leading and two more trailing slots), per-projection
- * DC terms [batch][V] float32 and the half-transformed grid [batch][N][G/2]
- * complex64. With p->adjoint set, the size also covers bst_project: the grid,
+ * DC terms [batch][V] float32, the half-transformed grid [batch][N][G/2]
+ * complex64 and, with a monopole width, partial sinogram sums [batch][64]
+ * float32. With p->adjoint set, the size also covers bst_project: the grid,
  * the full Cartesian half-plane spectrum [batch][G/2][G] and the polar adjoint
  * [batch][V][M/2] (complex64); the larger of the two needs is returned. */
 bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes);
@@ -145,7 +157,8 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes);
  *   (a constant sinogram c gives pi*c).
  * sino: device float32 [batch][V][n]; img: device float32 [batch][N][N];
  * ws: device workspace of ws_bytes >= bst_workspace_size(plan, batch).
- * batch == 0 is a no-op. Three kernels are enqueued on `stream`. */
+ * batch == 0 is a no-op. Three kernels are enqueued on `stream` (four with a
+ * monopole width: a sinogram-sum kernel first). */
 bst_status bst_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch,
                            void* ws, size_t ws_bytes, void* stream);
 

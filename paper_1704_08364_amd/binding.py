@@ -43,7 +43,7 @@ class bst_params(C.Structure):
         ("filter", C.c_int32), ("taper", C.c_int32), ("taper_beta", C.c_double),
         ("max_batch", C.c_int32), ("device", C.c_int32), ("adjoint", C.c_int32),
         ("apodization", C.c_int32), ("center_shift", C.c_double),
-        ("interp", C.c_int32),
+        ("interp", C.c_int32), ("monopole_width", C.c_double),
     ]
 
 
@@ -119,9 +119,12 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
                 pad_cart: int = 2, filter: str = "ramp", taper: str = "deapod",
                 taper_beta: float = 8.0, max_batch: int = 1, device: int = 0,
                 angles: Optional[Sequence[float]] = None, adjoint: bool = False,
-                apodization: str = "ramlak", center_shift: float = 0.0, interp: str = "linear"):
+                apodization: str = "ramlak", center_shift: float = 0.0, interp: str = "linear",
+                monopole_width: float = 0.0):
     """bst_params plus the ctypes array that backs `angles` (keep both alive).
-    interp='keys' (cubic radial interpolation) pairs with taper='keys'."""
+    interp='keys' (cubic radial interpolation) pairs with taper='keys';
+    monopole_width > 0 (filter='none' only) subtracts a Gaussian monopole of that
+    width (units of t, detector in [-1, 1)) and adds its backprojection back."""
     p = bst_params()
     lib().bst_params_default(C.byref(p), n_det, n_angles, n_det if n_out is None else n_out)
     p.pad_radial = pad_radial
@@ -135,6 +138,7 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
     p.apodization = APODIZATIONS[apodization] if isinstance(apodization, str) else int(apodization)
     p.center_shift = center_shift
     p.interp = INTERPS[interp] if isinstance(interp, str) else int(interp)
+    p.monopole_width = monopole_width
     keep = None
     if angles is not None:
         arr = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))

@@ -83,14 +83,22 @@ void release(bst_batch_s* b) {
 hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStream_t st) {
     const bst_plan_s& p = *c.plan;
     const int batch = (int)c.members.size();
-    const bst::WsLayout L = bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch, p.prm.interp);
+    const bst::WsLayout L = bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch, p.prm.interp, p.monopole);
     unsigned char* w = static_cast<unsigned char*>(ws) + c.ws_off;
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
     float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
+    float* mass = p.monopole ? reinterpret_cast<float*>(w + L.mass_off) : nullptr;
+    hipError_t e;
+    if (p.monopole) {
+        const bst::MassArgs ma{nullptr, b->d_sino_list + c.list_base, nullptr, nullptr, mass, p.n, p.V};
+        e = bst::launch_mass(p, ma, batch, st);
+        if (e != hipSuccess) return e;
+    }
     bst::SpecArgs sa{nullptr, b->d_sino_list + c.list_base, nullptr, nullptr, polar, dc, p.taper, p.kc,
-                     p.tw_M, p.n, p.V, p.S, p.lead, p.S - p.lead - p.M / 2, (float)p.dt};
-    hipError_t e = bst::launch_spectrum(p, sa, batch, st);
+                     p.tw_M, p.n, p.V, p.S, p.lead, p.S - p.lead - p.M / 2, (float)p.dt,
+                     mass, p.mono_phi, p.mono_inv};
+    e = bst::launch_spectrum(p, sa, batch, st);
     if (e != hipSuccess) return e;
     bst::GatherArgs ga{};
     ga.polar = polar;
@@ -113,7 +121,8 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     ga.dc_scale = p.dc_scale;
     e = bst::launch_gather_colifft(p, ga, st);
     if (e != hipSuccess) return e;
-    bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.GT, p.out_scale};
+    bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.GT, p.out_scale, 0,
+                    mass, p.mono_inv, p.mono_amp, p.mono_rho_px};
     return bst::launch_row_c2r(p, ra, batch, st);
 }
 

@@ -88,7 +88,7 @@ void set_last_error(hipError_t e) { g_last_error = hipGetErrorString(e); }
 int polar_stride(int M, int interp) { return M / 2 + (interp == BST_INTERP_KEYS ? 5 : 2); }
 int grid_width(int G) { return G / 2; }
 
-WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp) {
+WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole) {
     (void)n;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     WsLayout L{};
@@ -99,7 +99,9 @@ WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int inte
     const size_t dc = B * (size_t)V * sizeof(float);
     L.grid_off = up(L.dc_off + dc);
     const size_t grid = B * (size_t)N * (size_t)grid_width(G) * sizeof(float2);
-    L.total = up(L.grid_off + grid);
+    L.mass_off = up(L.grid_off + grid);
+    const size_t mass = monopole ? B * (size_t)kMassChunks * sizeof(float) : 0;
+    L.total = up(L.mass_off + mass);
     return L;
 }
 
@@ -114,9 +116,9 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
     return L;
 }
 
-size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp) {
+size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp, bool monopole) {
     if (batch == 0) return 0;
-    size_t need = workspace_layout(n, V, N, M, G, batch, interp).total;
+    size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole).total;
     if (adjoint) {
         const size_t pj = project_workspace_layout(V, N, M, G, batch).total;
         if (pj > need) need = pj;
@@ -146,6 +148,7 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
     p->apodization = BST_APOD_RAMLAK;
     p->center_shift = 0.0;
     p->interp = BST_INTERP_LINEAR;
+    p->monopole_width = 0.0;
 }
 
 bst_status bst_validate(const bst_params* p) {
@@ -167,6 +170,12 @@ bst_status bst_validate(const bst_params* p) {
         return BST_E_PARAM;
     if (p->apodization < BST_APOD_RAMLAK || p->apodization > BST_APOD_COSINE) return BST_E_PARAM;
     if (!std::isfinite(p->center_shift) || std::fabs(p->center_shift) >= 0.25 * p->n_det) return BST_E_PARAM;
+    if (p->monopole_width != 0.0) {
+        // plain B only, not with the adjoint, and a Gaussian the detector resolves
+        const double s = p->monopole_width, dt = 2.0 / p->n_det;
+        if (!std::isfinite(s) || s < 4.0 * dt || s > 2.0) return BST_E_PARAM;
+        if (p->filter != BST_FILTER_NONE || p->adjoint) return BST_E_PARAM;
+    }
     if (p->max_batch < 1) return BST_E_BATCH;
     if (p->device < 0) return BST_E_PARAM;
     if (p->angles) {
@@ -188,7 +197,7 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
-                                  p->adjoint != 0, p->interp);
+                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0);
     return BST_OK;
 }
 
@@ -229,6 +238,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->adjoint = (p->adjoint != 0);
     pl->gather_slices = BST_GATHER_SLICES;
     pl->gather_e = BST_GATHER_E;
+    pl->monopole = (p->monopole_width != 0.0);
 
     // ---- FP64 tables ----
     const int n = pl->n, M = pl->M, G = pl->G, V = pl->V;
@@ -302,6 +312,23 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
         proj_row[j] = (float)(d * d / (pl->dt * w));
     }
 
+    // monopole: phi(t_i - beta dt) = exp(-(t_i - beta dt)^2 / (2 s^2)) / (sqrt(2 pi) s); the
+    // add-back m (pi / (sqrt(2 pi) s)) e^-rho I0(rho), rho = |u|^2 / (4 s^2) = rho_px * pixels^2
+    std::vector<float> mono_phi(n, 0.0f);
+    if (pl->monopole) {
+        const double ms = p->monopole_width;
+        double sum = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double t = (i - n / 2) * pl->dt - p->center_shift * pl->dt;
+            const double ph = std::exp(-t * t / (2.0 * ms * ms)) / (std::sqrt(2.0 * M_PI) * ms);
+            mono_phi[i] = (float)ph;
+            sum += ph;
+        }
+        pl->mono_inv = (float)(1.0 / ((double)V * sum));
+        pl->mono_amp = (float)(M_PI / (std::sqrt(2.0 * M_PI) * ms));
+        pl->mono_rho_px = (float)(d * d / (4.0 * ms * ms));
+    }
+
     // ---- one device block ----
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
@@ -315,6 +342,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     const size_t o_ang = off;   off = up(off + V * sizeof(double2));
     const size_t o_gap = off;   off = up(off + V * sizeof(float));
     const size_t o_prow = off;  off = up(off + V * sizeof(float));
+    const size_t o_mphi = off;  off = up(off + n * sizeof(float));
     const size_t total = off;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
@@ -327,6 +355,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::memcpy(host.data() + o_ang, ang.data(), V * sizeof(double2));
     std::memcpy(host.data() + o_gap, inv_gap.data(), V * sizeof(float));
     std::memcpy(host.data() + o_prow, proj_row.data(), V * sizeof(float));
+    std::memcpy(host.data() + o_mphi, mono_phi.data(), n * sizeof(float));
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -390,6 +419,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->ang = reinterpret_cast<double2*>(base + o_ang);
     pl->inv_gap = reinterpret_cast<float*>(base + o_gap);
     pl->proj_row = reinterpret_cast<float*>(base + o_prow);
+    pl->mono_phi = reinterpret_cast<float*>(base + o_mphi);
     *out = pl;
     return BST_OK;
 }
@@ -398,7 +428,7 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
     if (!plan || !bytes) return BST_E_NULL;
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
     *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint,
-                                  plan->prm.interp);
+                                  plan->prm.interp, plan->monopole);
     return BST_OK;
 }
 
@@ -413,7 +443,9 @@ bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const vo
     if (batch == 0) return BST_OK;
     if (!in || !out) return BST_E_NULL;
     if (need_ws) {
-        *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp).total;
+        *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp,
+                                      plan->monopole)
+                    .total;
         if (!ws) return BST_E_NULL;
         if (ws_bytes < *need) return BST_E_WORKSPACE;
     }
@@ -451,21 +483,29 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     if (guard.err != hipSuccess) return device_fail(guard.err);
     bst::TraceRange trace(spectrum_only ? "bst_debug_spectrum" : "bst_backproject");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bst::WsLayout L =
-        bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp);
+    const bst::WsLayout L = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch,
+                                                  plan->prm.interp, plan->monopole);
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
     float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
+    float* mass = plan->monopole ? reinterpret_cast<float*>(w + L.mass_off) : nullptr;
     hipError_t e;
 
     if (ev && ev[0]) {
         e = hipEventRecord(static_cast<hipEvent_t>(ev[0]), s);
         if (e != hipSuccess) return device_fail(e);
     }
+    if (plan->monopole) {
+        bst::TraceRange tr("bst monopole mass");
+        const bst::MassArgs ma{sino, sino_list, flat, dark, mass, plan->n, plan->V};
+        e = bst::launch_mass(*plan, ma, batch, s);
+        if (e != hipSuccess) return device_fail(e);
+    }
     bst::SpecArgs sa{sino,   sino_list, flat,    dark,       polar,          dc,
                      plan->taper, plan->kc, plan->tw_M, plan->n, plan->V, plan->S,
-                     plan->lead,  plan->S - plan->lead - plan->M / 2, (float)plan->dt};
+                     plan->lead,  plan->S - plan->lead - plan->M / 2, (float)plan->dt,
+                     mass, plan->mono_phi, plan->mono_inv};
     {
         bst::TraceRange tr("bst P1-P4 spectrum");
         e = bst::launch_spectrum(*plan, sa, batch, s);
@@ -512,7 +552,8 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         e = hipEventRecord(static_cast<hipEvent_t>(ev[2]), s);
         if (e != hipSuccess) return device_fail(e);
     }
-    bst::RowArgs ra{grid, img, img_list, plan->tw_G, plan->N, plan->GT, plan->out_scale};
+    bst::RowArgs ra{grid, img, img_list, plan->tw_G, plan->N, plan->GT, plan->out_scale, 0,
+                    mass, plan->mono_inv, plan->mono_amp, plan->mono_rho_px};
     {
         bst::TraceRange tr("bst P6-P8 row C2R + crop");
         e = bst::launch_row_c2r(*plan, ra, batch, s);

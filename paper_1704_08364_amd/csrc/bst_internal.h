@@ -51,6 +51,9 @@ struct bst_plan_s {
     uint2* csr_ent;      // [entries]    (point index a*G + b | conj << 31, weight bits)
     size_t n_entries;
     float* proj_row;     // [V]          d^2 / (dt w_j): makes R the weighted adjoint of B
+    float* mono_phi;     // [n]          phi(t_i - beta dt), monopole Gaussian (if enabled)
+    bool monopole;
+    float mono_inv, mono_amp, mono_rho_px;
     int gather_slices;   // slices per gather block (coordinates reused across them)
     int gather_e;        // values per thread of the column transform, 8 or 16: fewer
                          // values mean less per-thread state and more resident waves
@@ -62,12 +65,14 @@ namespace bst {
 void set_last_error(hipError_t e);
 
 struct WsLayout {
-    size_t polar_off, dc_off, grid_off, total;
+    size_t polar_off, dc_off, grid_off, mass_off, total;
 };
+// Partial sinogram sums per slice for the monopole mass (one per reduction block).
+constexpr int kMassChunks = 64;
 // Row stride of a polar spectrum and tile-row width of the grid (complex values).
 int polar_stride(int M, int interp);
 int grid_width(int G);
-WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp);
+WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole);
 
 struct ProjWsLayout {
     size_t grid_off, cart_off, polar_off, total;
@@ -88,6 +93,20 @@ struct SpecArgs {
     int lead;               // slots before sample 0 (1: conj of sample 1 there)
     int tail;               // zero slots after sample M/2 - 1
     float dt;
+    // monopole subtraction (mono_part != nullptr): y[i] - m phi[i] is loaded, with
+    // m = mono_inv * (sum of the slice's kMassChunks partial sums)
+    const float* mono_part; // [batch][kMassChunks]
+    const float* mono_phi;  // [n] phi(t_i - beta dt)
+    float mono_inv;         // 1 / (V sum_i phi_i)
+};
+
+struct MassArgs {           // partial sums of each slice's sinogram (monopole mass)
+    const float* sino;
+    const float* const* sino_list;
+    const float* flat;      // raw counts when non-null, as in SpecArgs
+    const float* dark;
+    float* part;            // [batch][kMassChunks]
+    int n, V;
 };
 
 struct GatherArgs {
@@ -117,6 +136,10 @@ struct RowArgs {
     int GT;                     // grid tile-row width (columns)
     float scale;
     int tiles;                  // row-pair groups per block (set by the launcher)
+    // monopole add-back (mono_part != nullptr): + m amp e^-rho I0(rho),
+    // rho = rho_px * ((p - N/2)^2 + (q - N/2)^2)
+    const float* mono_part;     // [batch][kMassChunks]
+    float mono_inv, mono_amp, mono_rho_px;
 };
 
 struct BfArgs {
@@ -168,6 +191,7 @@ hipError_t launch_proj_cols(const bst_plan_s& p, const ProjColArgs& a, int batch
 hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipStream_t st);
 hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int batch, hipStream_t st);
 
+hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st);
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st);
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st);
 hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipStream_t st);

@@ -12,6 +12,7 @@
 // that each wave's loads are contiguous.
 #include "bst_internal.h"
 #include "fft_lds.h"
+#include "monopole.h"
 
 namespace bst {
 
@@ -40,7 +41,9 @@ struct RowCfg {
     static_assert(T * 16 == G, "16 values per thread");
 };
 
-template <int LOGG>
+// MONO: adds m b_phi(u), the closed-form backprojection of the subtracted
+// monopole, to every output pixel.
+template <int LOGG, bool MONO>
 __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     using C = RowCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
@@ -58,6 +61,8 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     const int g0 = blockIdx.x * a.tiles;
     float* const img_s = a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N;
     const FftTwiddles<LOGG, +1, 16> tw(j, a.tw);
+    float mamp = 0.f;
+    if constexpr (MONO) mamp = monopole_mass(a.mono_part, s, a.mono_inv) * a.mono_amp;
 
     // Thread j's slots e < 8 are k = j + e*T < G/2: the block reads every
     // stored column once (all loads first, no branch between them) and puts
@@ -115,8 +120,17 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
                 const int x = jv + e * T;
                 const int c = (x + half_n) & (G - 1);
                 if (c < a.N) {
-                    o0[c] = v[e].x * a.scale;
-                    o1[c] = v[e].y * a.scale;
+                    float b0 = v[e].x * a.scale, b1 = v[e].y * a.scale;
+                    if constexpr (MONO) {
+                        // pixel offsets from the centre: exact in float (|.|^2 <= 2^23)
+                        const float dx = (float)(c - half_n), dy = (float)(row0 - half_n);
+                        const float r0 = dx * dx + dy * dy;
+                        const float r1 = r0 + 2.f * dy + 1.f;
+                        b0 += mamp * scaled_bessel_i0(a.mono_rho_px * r0);
+                        b1 += mamp * scaled_bessel_i0(a.mono_rho_px * r1);
+                    }
+                    o0[c] = b0;
+                    o1[c] = b1;
                 }
             }
         }
@@ -134,7 +148,8 @@ static hipError_t launch_row_t(const RowArgs& a0, int batch, hipStream_t st) {
     tiles = tiles < 1 ? 1 : (tiles > C::MAX_TILES ? C::MAX_TILES : tiles);
     a.tiles = tiles;
     dim3 grid((groups + tiles - 1) / tiles, batch);
-    hipLaunchKernelGGL(k_row_c2r<LOGG>, grid, dim3(C::WG), 0, st, a);
+    if (a.mono_part) hipLaunchKernelGGL((k_row_c2r<LOGG, true>), grid, dim3(C::WG), 0, st, a);
+    else hipLaunchKernelGGL((k_row_c2r<LOGG, false>), grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }
 

@@ -15,8 +15,12 @@
 // interpolation (samples m0, m0+1), four plus a leading conj Yh[1] (the
 // sample at m = -1) for cubic interpolation (samples m0-1 .. m0+2).
 // The unweighted DC values dt*Y_j[0] go to a separate array for the origin rule.
+// With monopole subtraction (plain B), a reduction kernel first sums each
+// slice's sinogram (partial sums of kMassChunks blocks); the spectrum kernel
+// turns them into the mass m and loads y[i] - m phi[i] in place of y[i].
 #include "bst_internal.h"
 #include "fft_lds.h"
+#include "monopole.h"
 
 // waves per SIMD the register allocation must leave room for
 #ifndef BST_SPEC_WAVES
@@ -32,8 +36,57 @@ namespace bst {
 
 // Groups per block: the prefetch needs registers for one more group's data
 // slots, which only the P_r >= 2 plain-input variants have to spare.
-template <int LOGP, bool COUNTS>
-constexpr int spec_pairs() { return (LOGP >= 1 && !COUNTS) ? BST_SPEC_PAIRS : 1; }
+template <int LOGP, bool COUNTS, bool MONO>
+constexpr int spec_pairs() { return (LOGP >= 1 && !COUNTS && !MONO) ? BST_SPEC_PAIRS : 1; }
+
+// Partial sums of each slice's sinogram for the monopole mass: block (c, s)
+// adds up lines j = c, c + kMassChunks, ... (raw counts normalised as the
+// spectrum kernel does), every thread over a fixed set of elements and the
+// block in a fixed tree, so each call gives the same sums.
+constexpr int kMassThreads = 256;
+
+template <bool COUNTS>
+__global__ void __launch_bounds__(kMassThreads) k_mass(MassArgs a) {
+    __shared__ float red[kMassThreads / 64];
+    const int c = blockIdx.x, s = blockIdx.y;
+    const float* base = a.sino_list ? a.sino_list[s] : a.sino + (size_t)s * a.V * a.n;
+    const int lines = c < a.V ? (a.V - 1 - c) / kMassChunks + 1 : 0;
+    const int logn = __ffs(a.n) - 1;  // n is a power of two
+    const long long items = (long long)lines << logn;
+    const float* fs = COUNTS ? a.flat + (size_t)s * a.n : nullptr;
+    const float* ds = COUNTS ? a.dark + (size_t)s * a.n : nullptr;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (long long it0 = threadIdx.x; it0 < items; it0 += 4LL * kMassThreads) {
+        float x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long it = it0 + (long long)u * kMassThreads;
+            const bool ok = it < items;
+            const long long itc = ok ? it : 0;
+            const int l = (int)(itc >> logn);
+            const int i = (int)(itc & (a.n - 1));
+            float v = base[(size_t)(c + l * kMassChunks) * a.n + i];
+            if constexpr (COUNTS) {
+                const float inv = 1.0f / (fs[i] - ds[i]);
+                v = -logf((v - ds[i]) * inv);
+            }
+            x[u] = ok ? v : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += x[u];
+    }
+    float v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+#pragma unroll
+        for (int w = 0; w < kMassThreads / 64; ++w) t += red[w];
+        a.part[(size_t)s * kMassChunks + c] = t;
+    }
+}
 
 template <int LOGM>
 struct SpecCfg {
@@ -47,9 +100,16 @@ struct SpecCfg {
 // e < E0 or e >= 16 - E0 (E0 = 8 / P_r): the middle of every line is padding,
 // known at compile time, so it is never loaded. COUNTS: the input is raw
 // counts with per-slice flat and dark fields.
-template <int LOGM, int LOGP, bool COUNTS>
-__global__ void __launch_bounds__(SpecCfg<LOGM>::WG) __attribute__((amdgpu_waves_per_eu(BST_SPEC_WAVES, 8)))
-k_spectrum(SpecArgs a) {
+// Unpadded raw counts with the monopole hold the most per-thread state (16
+// data slots and their flat and dark values): they get room for 3 waves per
+// SIMD instead of spilling.
+template <int LOGP, bool COUNTS, bool MONO>
+constexpr int spec_waves() { return (MONO && COUNTS && LOGP == 0) ? 3 : BST_SPEC_WAVES; }
+
+// MONO: monopole subtraction, y[i] - m phi[i] (m from the partial sums).
+template <int LOGM, int LOGP, bool COUNTS, bool MONO>
+__global__ void __launch_bounds__(SpecCfg<LOGM>::WG)
+__attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spectrum(SpecArgs a) {
     using C = SpecCfg<LOGM>;
     constexpr int M = C::M, T = C::T;
     constexpr int E0 = 8 >> LOGP;
@@ -60,7 +120,7 @@ k_spectrum(SpecArgs a) {
     float2* my = lds + fid * FftShape<LOGM>::LDS;
     const int s = blockIdx.y;
     const int h = a.n >> 1;
-    constexpr int PAIRS = spec_pairs<LOGP, COUNTS>();
+    constexpr int PAIRS = spec_pairs<LOGP, COUNTS, MONO>();
     const int npairs = (a.V + 1) >> 1;
 
     // detector bin of data slot q: positions e = q (q < E0) and e = 16 - 2*E0 + q (q >= E0)
@@ -103,6 +163,12 @@ k_spectrum(SpecArgs a) {
             dk[q] = ds[i];
         }
     }
+    float mph[MONO ? NQ : 1];  // m phi at the thread's bins
+    if constexpr (MONO) {
+        const float m = monopole_mass(a.mono_part, s, a.mono_inv);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) mph[q] = m * a.mono_phi[bin_of(q)];
+    }
     float2 kc[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) kc[e] = a.kc[j + e * T];
@@ -130,6 +196,10 @@ k_spectrum(SpecArgs a) {
                 const float inv = 1.0f / (fl[q] - dk[q]);
                 xa = -logf((xa - dk[q]) * inv);
                 xb = -logf((xb - dk[q]) * inv);
+            }
+            if constexpr (MONO) {
+                xa -= mph[q];
+                xb -= mph[q];
             }
             v[q < E0 ? q : 16 - 2 * E0 + q] = make_float2(va ? w[q] * xa : 0.f, vb ? w[q] * xb : 0.f);
         }
@@ -183,18 +253,24 @@ k_spectrum(SpecArgs a) {
     }
 }
 
+template <int LOGM, int LOGP, bool COUNTS, bool MONO>
+static void launch_spec_k(const SpecArgs& a, int groups, int batch, hipStream_t st) {
+    using C = SpecCfg<LOGM>;
+    constexpr int P = spec_pairs<LOGP, COUNTS, MONO>();
+    hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, COUNTS, MONO>), dim3((groups + P - 1) / P, batch), dim3(C::WG), 0,
+                       st, a);
+}
+
 template <int LOGM, int LOGP>
 static hipError_t launch_spec_t(const SpecArgs& a, int batch, hipStream_t st) {
     using C = SpecCfg<LOGM>;
     const int pairs = (a.V + 1) / 2;
     const int groups = (pairs + C::F - 1) / C::F;
-    if (a.flat != nullptr) {
-        constexpr int P = spec_pairs<LOGP, true>();
-        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, true>), dim3((groups + P - 1) / P, batch), dim3(C::WG), 0, st, a);
-    } else {
-        constexpr int P = spec_pairs<LOGP, false>();
-        hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, false>), dim3((groups + P - 1) / P, batch), dim3(C::WG), 0, st, a);
-    }
+    const bool counts = a.flat != nullptr, mono = a.mono_part != nullptr;
+    if (counts && mono) launch_spec_k<LOGM, LOGP, true, true>(a, groups, batch, st);
+    else if (counts) launch_spec_k<LOGM, LOGP, true, false>(a, groups, batch, st);
+    else if (mono) launch_spec_k<LOGM, LOGP, false, true>(a, groups, batch, st);
+    else launch_spec_k<LOGM, LOGP, false, false>(a, groups, batch, st);
     return hipGetLastError();
 }
 
@@ -210,6 +286,14 @@ static hipError_t launch_spec_p(const SpecArgs& a, int pr, int batch, hipStream_
         if (pr == 4) return launch_spec_t<LOGM, 2>(a, batch, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st) {
+    (void)p;
+    const dim3 grid(kMassChunks, batch);
+    if (a.flat != nullptr) hipLaunchKernelGGL(k_mass<true>, grid, dim3(kMassThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_mass<false>, grid, dim3(kMassThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st) {

@@ -177,3 +177,30 @@ def test_adjoint_takes_non_uniform_angles():
     p.adjoint = 1
     assert _validate(p) == 0
     assert P.query_workspace(p, 1) > 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(filter="none", monopole_width=0.4), 0),
+    (dict(filter="none", monopole_width=4 * 2.0 / 256), 0),        # the narrowest: 4 dt
+    (dict(filter="none", monopole_width=2.0), 0),
+    (dict(filter="ramp", monopole_width=0.4), 4),                   # plain B only
+    (dict(filter="none", monopole_width=0.4, adjoint=True), 4),     # no longer the transpose
+    (dict(filter="none", monopole_width=3.9 * 2.0 / 256), 4),       # under-resolved
+    (dict(filter="none", monopole_width=2.5), 4),
+    (dict(filter="none", monopole_width=-0.4), 4),
+    (dict(filter="none", monopole_width=float("nan")), 4),
+    (dict(filter="none", monopole_width=float("inf")), 4),
+])
+def test_monopole_validation(kw, code):
+    p, _ = _params(n=256, V=128, **kw)
+    assert _validate(p) == code
+
+
+def test_monopole_workspace_adds_the_partial_sums():
+    for B in (1, 3, 64):
+        plain, _ = _params(n=256, V=128, filter="none", max_batch=B)
+        mono, _ = _params(n=256, V=128, filter="none", max_batch=B, monopole_width=0.4)
+        a = P.query_workspace(plain, B)
+        b = P.query_workspace(mono, B)
+        # [B][64] float32 partial sums, rounded to 256 bytes
+        assert b - a == -(-B * 64 * 4 // 256) * 256

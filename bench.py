@@ -75,7 +75,7 @@ def measured_traffic(kernel: str, config_key: str):
         return None
 
 
-def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear"):
+def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear", filter="ramp", monopole=0.0):
     """FP64 oracle on `slices` slices of the same batch, single thread."""
     import numpy as np
 
@@ -83,7 +83,8 @@ def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear"):
     from oracle.geometry import Geometry
 
     geom = Geometry(n, V, N)
-    prm = obst.Params(taper="keys", interp="keys") if interp == "keys" else obst.Params()
+    kw = dict(taper="keys", interp="keys") if interp == "keys" else {}
+    prm = obst.Params(filter=filter, monopole=monopole, **kw)
     t0 = time.perf_counter()
     refs = [obst.backproject(sino_cpu[i], geom, prm) for i in range(slices)]
     dt = time.perf_counter() - t0
@@ -240,6 +241,10 @@ def main():
     ap.add_argument("--slices", type=int, default=2048)
     ap.add_argument("--interp", choices=("linear", "keys"), default="linear",
                     help="radial interpolation of the gather (keys: cubic, narrower gap to brute force)")
+    ap.add_argument("--filter", choices=("ramp", "none"), default="ramp",
+                    help="ramp: FBP (default); none: plain backprojection B y")
+    ap.add_argument("--monopole", type=float, default=0.0,
+                    help="with --filter none: subtract a Gaussian monopole of this width (units of t)")
     ap.add_argument("--input", choices=("phantom", "random"), default="phantom",
                     help="random: N(0,1) sinograms (for hardware-counter runs, where generating "
                          "phantoms with thousands of small kernels is slow)")
@@ -284,7 +289,7 @@ def main():
     else:
         sino = synth.batch_sinograms(B, n, V, seed=170408366, device=dev)
     interp_kw = dict(taper="keys", interp="keys") if args.interp == "keys" else {}
-    plan = P.Plan(n, V, max_batch=B, **interp_kw)
+    plan = P.Plan(n, V, max_batch=B, filter=args.filter, monopole_width=args.monopole, **interp_kw)
     M, G = plan.M, plan.G
     ws = plan.workspace(B)
     img = torch.empty(B, N, N, dtype=torch.float32, device=dev)
@@ -346,7 +351,7 @@ def main():
         sino_cpu = sino[:s].double().cpu().numpy()
         img_cpu = img[:s].double().cpu().numpy()
         log(f"timing the FP64 oracle on {s} slices ...")
-        rate, dt, errs = cpu_baseline(sino_cpu, img_cpu, n, V, N, s, args.interp)
+        rate, dt, errs = cpu_baseline(sino_cpu, img_cpu, n, V, N, s, args.interp, args.filter, args.monopole)
         cpu = {"value": round(rate, 4), "unit": "slices/s", "cores": 1, "kind": "oracle",
                "sample": f"{s} of the {B} slices ({V}x{n} -> {N}^2), FP64 NumPy BST, "
                          f"single thread, {dt:.1f} s"}
@@ -367,13 +372,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"FBP of {B} slices x {V} angles x {n} bins -> {B} x {N}x{N}, "
+            "workload": ("FBP" if args.filter == "ramp" else "plain backprojection")
+                        + f" of {B} slices x {V} angles x {n} bins -> {B} x {N}x{N}, "
                         f"random 5-20 ellipse phantoms + 1% noise, P_r=P_c=2, "
                         + ("cubic (Keys) radial interpolation + its de-apodiser" if args.interp == "keys"
-                           else "de-apodising taper"),
+                           else "de-apodising taper")
+                        + (f", monopole subtraction (s = {args.monopole})" if args.monopole else ""),
             "batch": B, "n_det": n, "n_angles": V, "n_out": N, "pad_radial": 2, "pad_cart": 2,
-            "filter": "ramp", "input": args.input, "interp": args.interp,
+            "filter": args.filter, "input": args.input, "interp": args.interp, "monopole_width": args.monopole,
+            "seed": 170408366,
         },
+        "env": {"device": torch.cuda.get_device_name(0), "torch": torch.__version__, "hip": torch.version.hip,
+                "host_cpus": os.cpu_count()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},

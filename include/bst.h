@@ -144,6 +144,15 @@ bst_status bst_validate(const bst_params* p);
  * [batch][V][M/2] (complex64); the larger of the two needs is returned. */
 bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes);
 
+/* The largest batch Q <= p->max_batch whose device buffers fit in budget_bytes
+ * (host only, no plan needed): the sinograms [Q][V][n] and images [Q][N][N]
+ * float32 plus the workspace of bst_query_workspace(p, Q). This is the bound
+ * the paper puts on its block size Q (Section 4: the per-block allocations of
+ * all stages must fit in one GPU's memory). The plan's own tables (a few MB;
+ * with adjoint also the transposed-gather lists) come on top. *batch = 0 and
+ * BST_E_NOMEM when not even Q = 1 fits. */
+bst_status bst_query_max_batch(const bst_params* p, size_t budget_bytes, int32_t* batch);
+
 /* Validate *p, then build the plan on p->device: FP64-derived tables (twiddles
  * of lengths M and G, taper, radial weights K[m] of step P4, angle tables)
  * uploaded in one small allocation. On error *out is left NULL. */

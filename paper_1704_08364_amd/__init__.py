@@ -14,5 +14,6 @@ from .binding import (  # noqa: F401
     LIB_PATH,
     lib,
     make_params,
+    query_max_batch,
     query_workspace,
 )

@@ -51,6 +51,7 @@ SIGNATURES = {
     "bst_params_default": (None, [C.POINTER(bst_params), _I, _I, _I]),
     "bst_validate": (C.c_int, [C.POINTER(bst_params)]),
     "bst_query_workspace": (C.c_int, [C.POINTER(bst_params), _I, C.POINTER(_S)]),
+    "bst_query_max_batch": (C.c_int, [C.POINTER(bst_params), _S, C.POINTER(_I)]),
     "bst_plan": (C.c_int, [C.POINTER(bst_params), C.POINTER(_P)]),
     "bst_workspace_size": (C.c_int, [_P, _I, C.POINTER(_S)]),
     "bst_backproject": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
@@ -150,6 +151,16 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
 def query_workspace(params: bst_params, batch: int) -> int:
     out = C.c_size_t(0)
     _check(lib().bst_query_workspace(C.byref(params), batch, C.byref(out)), "bst_query_workspace")
+    return int(out.value)
+
+
+def query_max_batch(params: bst_params, budget_bytes: int) -> int:
+    """Largest batch whose sinograms, images and workspace fit in budget_bytes
+    (0 when not even one slice fits)."""
+    out = C.c_int32(0)
+    st = lib().bst_query_max_batch(C.byref(params), int(budget_bytes), C.byref(out))
+    if st not in (BST_OK, 6):  # 6: BST_E_NOMEM, nothing fits
+        _check(st, "bst_query_max_batch")
     return int(out.value)
 
 

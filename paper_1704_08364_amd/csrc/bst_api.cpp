@@ -201,6 +201,29 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     return BST_OK;
 }
 
+bst_status bst_query_max_batch(const bst_params* p, size_t budget_bytes, int32_t* batch) {
+    if (!batch) return BST_E_NULL;
+    *batch = 0;
+    const bst_status st = bst_validate(p);
+    if (st != BST_OK) return st;
+    const int M = pad_or_default(p->pad_radial) * p->n_det;
+    const int G = pad_or_default(p->pad_cart) * p->n_out;
+    const size_t io = ((size_t)p->n_angles * p->n_det + (size_t)p->n_out * p->n_out) * sizeof(float);
+    auto need = [&](int32_t q) {
+        return (size_t)q * io + bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, q, p->adjoint != 0,
+                                                     p->interp, p->monopole_width != 0.0);
+    };
+    // need(q) grows with q: binary search for the last q that fits
+    int32_t lo = 0, hi = p->max_batch;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (need(mid) <= budget_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    *batch = lo;
+    return lo > 0 ? BST_OK : BST_E_NOMEM;
+}
+
 bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     if (!out) return BST_E_NULL;
     *out = nullptr;

@@ -204,3 +204,32 @@ def test_monopole_workspace_adds_the_partial_sums():
         b = P.query_workspace(mono, B)
         # [B][64] float32 partial sums, rounded to 256 bytes
         assert b - a == -(-B * 64 * 4 // 256) * 256
+
+
+def test_max_batch_is_the_largest_that_fits():
+    # Section 4's bound on the block size Q: sinograms + images + workspace <= budget
+    for kw in (dict(), dict(filter="none", monopole_width=0.4), dict(adjoint=True), dict(interp="keys")):
+        p, _ = _params(n=256, V=200, max_batch=500, **kw)
+
+        def need(q):
+            return q * (200 * 256 + 256 * 256) * 4 + P.query_workspace(p, q)
+
+        for q in (1, 2, 7, 64, 499):
+            assert P.query_max_batch(p, need(q)) == q
+            assert P.query_max_batch(p, need(q + 1) - 1) == q
+        assert P.query_max_batch(p, need(500) * 4) == 500          # capped at max_batch
+        assert P.query_max_batch(p, need(1) - 1) == 0
+
+
+def test_max_batch_codes():
+    L = P.lib()
+    p, _ = _params(n=256, V=200, max_batch=8)
+    q = C.c_int32(-1)
+    assert L.bst_query_max_batch(C.byref(p), 0, C.byref(q)) == 6 and q.value == 0   # BST_E_NOMEM
+    assert L.bst_query_max_batch(C.byref(p), 1 << 40, None) == 1
+    assert L.bst_query_max_batch(None, 1 << 40, C.byref(q)) == 1
+    p.n_det = 100
+    assert L.bst_query_max_batch(C.byref(p), 1 << 40, C.byref(q)) == 2
+    # 288 GB of HBM holds far more than a 2048^2 x 2048-angle batch of 64
+    p2, _ = _params(n=2048, V=2048, max_batch=4096)
+    assert 64 < P.query_max_batch(p2, 288 * 10**9) < 4096

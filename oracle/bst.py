@@ -32,7 +32,15 @@ Discrete steps (readings where the paper is silent are listed beside each):
       interpolation"; the option interp='keys' replaces the linear radial
       weights by the Keys cubic convolution kernel (a = -1/2) over samples
       m0-1 .. m0+2 (sample -1 is conj Yh[1], since Yh(-sigma) = conj Yh(sigma)),
-      keeping linear interpolation in angle. The origin takes its own rule:
+      keeping linear interpolation in angle. The option angular='tent'
+      widens the angular kernel where the polar grid is denser in angle than
+      the Cartesian one: a tent of half-width h = max(1, V / (pi rho)) angle
+      steps (rho = |k| / dk, the point's radius in Cartesian steps), its
+      weights normalised to sum 1, so each Cartesian point averages the polar
+      angles across its own cell (h = 1 is the bilinear rule; uniform angles
+      only). The transpose of this gather then deposits every polar sample
+      over the Cartesian cells it covers, which makes the adjoint projector
+      a close Radon approximation. The origin takes its own rule:
       RAMP: mean_j Y_j[0]; NONE: (kappa / dk) mean_j Y_j[0], kappa = 4 asinh(1),
       the average of 1/|k| over the origin cell times dk. The Nyquist column
       a = G/2 is set to zero (like the radial Nyquist sample in P4).
@@ -70,6 +78,7 @@ KAPPA = 4.0 * np.arcsinh(1.0)
 
 APODIZATIONS = ("ramlak", "shepp", "hann", "cosine")
 INTERPS = ("linear", "keys")
+ANGULARS = ("linear", "tent")
 
 
 class Params:
@@ -80,12 +89,16 @@ class Params:
     P4 by the phase exp(+2 pi i sigma beta dt). `interp` is the radial
     interpolation of P5: 'linear' or 'keys' (cubic convolution). `monopole` is
     the width s of the subtracted Gaussian (plain B only; 0 = off), in the
-    units of t (the detector spans [-1, 1))."""
+    units of t (the detector spans [-1, 1)). `angular` is the angular kernel
+    of P5: 'linear', or 'tent' (widened at small radii; with linear radial
+    interpolation and uniform angles)."""
 
     def __init__(self, pad_radial: int = 2, pad_cart: int = 2, filter: str = "ramp",
                  taper: str = "deapod", beta: float = 8.0, apod: str = "ramlak",
-                 center_shift: float = 0.0, interp: str = "linear", monopole: float = 0.0):
+                 center_shift: float = 0.0, interp: str = "linear", monopole: float = 0.0,
+                 angular: str = "linear"):
         assert filter in ("ramp", "none")
+        assert angular in ANGULARS and (angular == "linear" or interp == "linear")
         assert monopole >= 0.0 and (monopole == 0.0 or filter == "none")
         assert taper in ("deapod", "none", "kb", "keys")
         assert apod in APODIZATIONS
@@ -99,6 +112,7 @@ class Params:
         self.center_shift = float(center_shift)
         self.interp = interp
         self.monopole = float(monopole)
+        self.angular = angular
 
 
 def sizes(geom: Geometry, prm: Params):
@@ -229,10 +243,58 @@ def angle_bracket(theta: np.ndarray, geom: Geometry):
     return j0, j1, f, flip0, flip1
 
 
+def tent_taps(theta: np.ndarray, rho: np.ndarray, V: int):
+    """Angular taps of the tent rule for directions theta in [0, pi) at
+    Cartesian radii rho (flat arrays): (p, j, flip, w) flat arrays, one entry
+    per nonzero tap of point p; j in [0, V), flip marking taps taken from the
+    continuation past pi or below 0 (the conjugated images theta_j +- pi);
+    weights (1 - |q - j| / h)+ with q = theta V / pi, h = max(1, V / (pi rho)),
+    normalised to sum 1. Points with h = 1 get the two bilinear taps. (rho is
+    at least 1 off the origin, which has its own rule; it is clamped there.)"""
+    q = theta * (V / np.pi)
+    h = np.maximum(1.0, V / (np.pi * np.maximum(rho, 1.0)))
+    ps, js, ws = [], [], []
+    idx = np.arange(q.size)
+    narrow = h <= 1.0
+    # h = 1: the bilinear taps floor(q), floor(q) + 1
+    qn = q[narrow]
+    j0 = np.floor(qn)
+    f = qn - j0
+    for jc, w in ((j0, 1.0 - f), (j0 + 1.0, f)):
+        ps.append(idx[narrow]); js.append(jc.astype(np.int64)); ws.append(w)
+    # h > 1: every integer j with |q - j| < h
+    wide = ~narrow
+    if np.any(wide):
+        qw, hw, pw = q[wide], h[wide], idx[wide]
+        lo = np.floor(qw - hw).astype(np.int64)
+        span = int(np.ceil(2.0 * hw.max())) + 2
+        raw = [(lo + k, np.maximum(0.0, 1.0 - np.abs(qw - (lo + k)) / hw)) for k in range(span)]
+        total = sum(w for _, w in raw)
+        for jc, w in raw:
+            ps.append(pw); js.append(jc); ws.append(w / total)
+    p = np.concatenate(ps)
+    jc = np.concatenate(js)
+    w = np.concatenate(ws)
+    ok = w != 0.0
+    p, jc, w = p[ok], jc[ok], w[ok]
+    flip = (np.floor_divide(jc, V) % 2) == 1
+    return p, np.mod(jc, V), flip, w
+
+
 def gather(Yh: np.ndarray, Y0: np.ndarray, geom: Geometry, prm: Params) -> np.ndarray:
     """Cartesian half-plane spectrum C[b][a], b in FFT order over G rows, a in [0, G/2]."""
     M, G, _, dk = sizes(geom, prm)
     V = geom.V
+    if prm.angular == "tent":
+        assert geom.uniform, "the tent angular rule is defined for uniform angles"
+        C = np.zeros((G, G // 2 + 1), dtype=np.complex128)
+        for bb, aa, jj, mm, ww, cc in _gather_stencil(geom, prm):
+            v = Yh[jj, mm]
+            np.add.at(C, (bb, aa), ww * np.where(cc, np.conj(v), v))
+        mean0 = np.mean(Y0)
+        C[0, 0] = mean0 if prm.filter == "ramp" else (KAPPA / dk) * mean0
+        C[:, G // 2] = 0.0
+        return C
     # radial samples past the data are zero: extend with zeros to cover |k| up to the corner
     ext = np.zeros((V, M + 4), dtype=np.complex128)
     ext[:, :M // 2 + 1] = Yh
@@ -392,12 +454,23 @@ def _gather_stencil(geom: Geometry, prm: Params):
     else:
         radial = tuple(zip((-1, 0, 1, 2), keys_weights(g)))
     entries = []
+    if prm.angular == "tent":
+        assert geom.uniform, "the tent angular rule is defined for uniform angles"
+        rho = np.sqrt(a * a + b * b) + 0.0 * b
+        pp, jj, fl, wa = tent_taps(theta.ravel(), rho.ravel(), geom.V)
+        bbf, aaf, m0f, kf, lf = bb.ravel()[pp], aa.ravel()[pp], m0.ravel()[pp], keep.ravel()[pp], lower.ravel()[pp]
+        for off, wr in radial:
+            mm = m0f + off
+            w = wa * wr.ravel()[pp]
+            ok = kf & (mm < M // 2) & (w != 0.0)
+            entries.append((bbf[ok], aaf[ok], jj[ok], mm[ok], w[ok], (lf ^ fl)[ok]))
+        return entries
     for jj, wa, cc in ((j0, 1 - f, lower ^ flip0), (j1, f, lower ^ flip1)):
         for off, wr in radial:
             mm = m0 + off
             neg = mm < 0
             mm = np.where(neg, -mm, mm)
-            ok = keep & (mm < M // 2)
+            ok = keep & (mm < M // 2) & (wa * wr != 0.0)
             entries.append((bb[ok], aa[ok], jj[ok], mm[ok], (wa * wr)[ok], (cc ^ neg)[ok]))
     return entries
 

@@ -83,6 +83,20 @@ typedef enum {
                                force (pair it with BST_TAPER_KEYS)                    */
 } bst_interp;
 
+/* Angular kernel of step P5. */
+typedef enum {
+    BST_ANGULAR_LINEAR = 0, /* the two bracketing angles, linear weights              */
+    BST_ANGULAR_TENT = 1    /* where one Cartesian cell spans several polar angles
+                               (radius rho < V/pi grid steps) all angles within
+                               h = V/(pi rho) steps, tent weights (1 - |q - j|/h)
+                               normalised; elsewhere linear. Uniform angles and
+                               BST_INTERP_LINEAR only. Its transpose (bst_project)
+                               is then a close Radon approximation; the backprojection
+                               is as accurate as with LINEAR. Costs a pre-gather
+                               kernel over the ~V^2/(2 pi) small-radius points and a
+                               [batch][that many] complex64 workspace array        */
+} bst_angular;
+
 typedef struct {
     int32_t n_det;          /* n: detector bins; power of two in [16, 4096]            */
     int32_t n_angles;       /* V: projections; [2, 16384]                               */
@@ -118,6 +132,7 @@ typedef struct {
                                4 dt <= s <= 2; not with adjoint (the result is no longer
                                the transpose of bst_project). Adds a reduction kernel
                                and a [batch][64] float32 workspace array.                */
+    int32_t angular;        /* bst_angular (step P5)                                     */
 } bst_params;
 
 typedef enum {

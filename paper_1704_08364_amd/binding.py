@@ -27,6 +27,7 @@ STATUS_NAMES = {
 FILTERS = {"none": 0, "ramp": 1}
 TAPERS = {"deapod": 0, "none": 1, "kaiser": 2, "kb": 2, "keys": 3}
 INTERPS = {"linear": 0, "keys": 1}
+ANGULARS = {"linear": 0, "tent": 1}
 APODIZATIONS = {"ramlak": 0, "shepp": 1, "hann": 2, "cosine": 3}
 
 # Every symbol include/bst.h declares, with its ctypes signature.
@@ -43,7 +44,7 @@ class bst_params(C.Structure):
         ("filter", C.c_int32), ("taper", C.c_int32), ("taper_beta", C.c_double),
         ("max_batch", C.c_int32), ("device", C.c_int32), ("adjoint", C.c_int32),
         ("apodization", C.c_int32), ("center_shift", C.c_double),
-        ("interp", C.c_int32), ("monopole_width", C.c_double),
+        ("interp", C.c_int32), ("monopole_width", C.c_double), ("angular", C.c_int32),
     ]
 
 
@@ -121,11 +122,13 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
                 taper_beta: float = 8.0, max_batch: int = 1, device: int = 0,
                 angles: Optional[Sequence[float]] = None, adjoint: bool = False,
                 apodization: str = "ramlak", center_shift: float = 0.0, interp: str = "linear",
-                monopole_width: float = 0.0):
+                monopole_width: float = 0.0, angular: str = "linear"):
     """bst_params plus the ctypes array that backs `angles` (keep both alive).
     interp='keys' (cubic radial interpolation) pairs with taper='keys';
     monopole_width > 0 (filter='none' only) subtracts a Gaussian monopole of that
-    width (units of t, detector in [-1, 1)) and adds its backprojection back."""
+    width (units of t, detector in [-1, 1)) and adds its backprojection back;
+    angular='tent' (uniform angles, linear interp) widens the angular kernel at
+    small radii, which makes plan.project a close Radon approximation."""
     p = bst_params()
     lib().bst_params_default(C.byref(p), n_det, n_angles, n_det if n_out is None else n_out)
     p.pad_radial = pad_radial
@@ -140,6 +143,7 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
     p.center_shift = center_shift
     p.interp = INTERPS[interp] if isinstance(interp, str) else int(interp)
     p.monopole_width = monopole_width
+    p.angular = ANGULARS[angular] if isinstance(angular, str) else int(angular)
     keep = None
     if angles is not None:
         arr = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))

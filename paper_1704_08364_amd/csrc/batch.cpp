@@ -83,7 +83,8 @@ void release(bst_batch_s* b) {
 hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStream_t st) {
     const bst_plan_s& p = *c.plan;
     const int batch = (int)c.members.size();
-    const bst::WsLayout L = bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch, p.prm.interp, p.monopole);
+    const bst::WsLayout L =
+        bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch, p.prm.interp, p.monopole, p.tent_w);
     unsigned char* w = static_cast<unsigned char*>(ws) + c.ws_off;
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
@@ -119,6 +120,15 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     ga.vpi_f = (float)p.vpi;
     ga.ang = p.ang;
     ga.dc_scale = p.dc_scale;
+    if (p.tent) {
+        float2* patch = reinterpret_cast<float2*>(w + L.tent_off);
+        const bst::TentArgs ta{polar, patch, p.tent_off, p.tent_ent, (int)p.tent_w, p.V * p.S};
+        e = bst::launch_tent(p, ta, batch, st);
+        if (e != hipSuccess) return e;
+        ga.tent_cols = p.tent_cols;
+        ga.patch = patch;
+        ga.tent_w = (int)p.tent_w;
+    }
     e = bst::launch_gather_colifft(p, ga, st);
     if (e != hipSuccess) return e;
     bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.GT, p.out_scale, 0,

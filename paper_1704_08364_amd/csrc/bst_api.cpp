@@ -21,7 +21,11 @@
 
 namespace bst {
 bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<double>& theta, bool uniform,
-                          int taps, std::vector<int>& off, std::vector<uint2>& ent);
+                          int taps, const std::vector<int2>* tent_cols, std::vector<int>& off,
+                          std::vector<uint2>& ent);
+size_t tent_columns(int G, int V, std::vector<int2>& cols);
+bool build_tent_tables(int V, int M, int G, double rscale, int S, int lead, const std::vector<int2>& cols,
+                       std::vector<int>& off, std::vector<uint2>& ent);
 }
 
 namespace {
@@ -88,7 +92,8 @@ void set_last_error(hipError_t e) { g_last_error = hipGetErrorString(e); }
 int polar_stride(int M, int interp) { return M / 2 + (interp == BST_INTERP_KEYS ? 5 : 2); }
 int grid_width(int G) { return G / 2; }
 
-WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole) {
+WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole,
+                          size_t tent_w) {
     (void)n;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     WsLayout L{};
@@ -101,7 +106,8 @@ WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int inte
     const size_t grid = B * (size_t)N * (size_t)grid_width(G) * sizeof(float2);
     L.mass_off = up(L.grid_off + grid);
     const size_t mass = monopole ? B * (size_t)kMassChunks * sizeof(float) : 0;
-    L.total = up(L.mass_off + mass);
+    L.tent_off = up(L.mass_off + mass);
+    L.total = up(L.tent_off + B * tent_w * sizeof(float2));
     return L;
 }
 
@@ -116,9 +122,10 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
     return L;
 }
 
-size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp, bool monopole) {
+size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp, bool monopole,
+                       size_t tent_w) {
     if (batch == 0) return 0;
-    size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole).total;
+    size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole, tent_w).total;
     if (adjoint) {
         const size_t pj = project_workspace_layout(V, N, M, G, batch).total;
         if (pj > need) need = pj;
@@ -149,6 +156,7 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
     p->center_shift = 0.0;
     p->interp = BST_INTERP_LINEAR;
     p->monopole_width = 0.0;
+    p->angular = BST_ANGULAR_LINEAR;
 }
 
 bst_status bst_validate(const bst_params* p) {
@@ -170,6 +178,8 @@ bst_status bst_validate(const bst_params* p) {
         return BST_E_PARAM;
     if (p->apodization < BST_APOD_RAMLAK || p->apodization > BST_APOD_COSINE) return BST_E_PARAM;
     if (!std::isfinite(p->center_shift) || std::fabs(p->center_shift) >= 0.25 * p->n_det) return BST_E_PARAM;
+    if (p->angular != BST_ANGULAR_LINEAR && p->angular != BST_ANGULAR_TENT) return BST_E_PARAM;
+    if (p->angular == BST_ANGULAR_TENT && (p->angles || p->interp != BST_INTERP_LINEAR)) return BST_E_PARAM;
     if (p->monopole_width != 0.0) {
         // plain B only, not with the adjoint, and a Gaussian the detector resolves
         const double s = p->monopole_width, dt = 2.0 / p->n_det;
@@ -189,6 +199,14 @@ bst_status bst_validate(const bst_params* p) {
     return BST_OK;
 }
 
+namespace {
+size_t params_tent_w(const bst_params* p, int G) {
+    if (p->angular != BST_ANGULAR_TENT) return 0;
+    std::vector<int2> cols;
+    return bst::tent_columns(G, p->n_angles, cols);
+}
+}  // namespace
+
 bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes) {
     if (!bytes) return BST_E_NULL;
     const bst_status st = bst_validate(p);
@@ -197,7 +215,7 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
-                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0);
+                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0, params_tent_w(p, G));
     return BST_OK;
 }
 
@@ -209,9 +227,10 @@ bst_status bst_query_max_batch(const bst_params* p, size_t budget_bytes, int32_t
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     const size_t io = ((size_t)p->n_angles * p->n_det + (size_t)p->n_out * p->n_out) * sizeof(float);
+    const size_t tw = params_tent_w(p, G);
     auto need = [&](int32_t q) {
         return (size_t)q * io + bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, q, p->adjoint != 0,
-                                                     p->interp, p->monopole_width != 0.0);
+                                                     p->interp, p->monopole_width != 0.0, tw);
     };
     // need(q) grows with q: binary search for the last q that fits
     int32_t lo = 0, hi = p->max_batch;
@@ -262,6 +281,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->gather_slices = BST_GATHER_SLICES;
     pl->gather_e = BST_GATHER_E;
     pl->monopole = (p->monopole_width != 0.0);
+    pl->tent = (p->angular == BST_ANGULAR_TENT);
 
     // ---- FP64 tables ----
     const int n = pl->n, M = pl->M, G = pl->G, V = pl->V;
@@ -404,16 +424,49 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
         delete pl;
         return device_fail(e);
     }
+    std::vector<int2> tent_cols;
+    if (pl->tent) {
+        pl->tent_w = bst::tent_columns(G, V, tent_cols);
+        std::vector<int> toff;
+        std::vector<uint2> tent;
+        bst::build_tent_tables(V, M, G, pl->rscale, pl->S, pl->lead, tent_cols, toff, tent);
+        const size_t o_off = up((size_t)(G / 2) * sizeof(int2));
+        const size_t o_ent = up(o_off + toff.size() * sizeof(int));
+        const size_t t_total = o_ent + std::max<size_t>(tent.size(), 1) * sizeof(uint2);
+        e = hipMalloc(&pl->tent_block, t_total);
+        if (e != hipSuccess) {
+            g_last_error = hipGetErrorString(e);
+            (void)hipFree(pl->dev_block);
+            delete pl;
+            return BST_E_NOMEM;
+        }
+        unsigned char* tb = static_cast<unsigned char*>(pl->tent_block);
+        e = hipMemcpy(tb, tent_cols.data(), tent_cols.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(tb + o_off, toff.data(), toff.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !tent.empty())
+            e = hipMemcpy(tb + o_ent, tent.data(), tent.size() * sizeof(uint2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(pl->tent_block);
+            (void)hipFree(pl->dev_block);
+            delete pl;
+            return device_fail(e);
+        }
+        pl->tent_cols = reinterpret_cast<int2*>(tb);
+        pl->tent_off = reinterpret_cast<int*>(tb + o_off);
+        pl->tent_ent = reinterpret_cast<uint2*>(tb + o_ent);
+    }
     if (pl->adjoint) {
         std::vector<int> off;
         std::vector<uint2> ent;
-        bst::build_adjoint_tables(V, M, G, pl->rscale, theta, pl->uniform, pl->taps, off, ent);
+        bst::build_adjoint_tables(V, M, G, pl->rscale, theta, pl->uniform, pl->taps,
+                                  pl->tent ? &tent_cols : nullptr, off, ent);
         pl->n_entries = ent.size();
         const size_t o_ent = up(off.size() * sizeof(int));
         const size_t adj_total = o_ent + std::max<size_t>(ent.size(), 1) * sizeof(uint2);
         e = hipMalloc(&pl->adj_block, adj_total);
         if (e != hipSuccess) {
             g_last_error = hipGetErrorString(e);
+            if (pl->tent_block) (void)hipFree(pl->tent_block);
             (void)hipFree(pl->dev_block);
             delete pl;
             return BST_E_NOMEM;
@@ -424,6 +477,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
                           ent.size() * sizeof(uint2), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(pl->adj_block);
+            if (pl->tent_block) (void)hipFree(pl->tent_block);
             (void)hipFree(pl->dev_block);
             delete pl;
             return device_fail(e);
@@ -451,7 +505,7 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
     if (!plan || !bytes) return BST_E_NULL;
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
     *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint,
-                                  plan->prm.interp, plan->monopole);
+                                  plan->prm.interp, plan->monopole, plan->tent_w);
     return BST_OK;
 }
 
@@ -467,7 +521,7 @@ bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const vo
     if (!in || !out) return BST_E_NULL;
     if (need_ws) {
         *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp,
-                                      plan->monopole)
+                                      plan->monopole, plan->tent_w)
                     .total;
         if (!ws) return BST_E_NULL;
         if (ws_bytes < *need) return BST_E_WORKSPACE;
@@ -507,7 +561,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     bst::TraceRange trace(spectrum_only ? "bst_debug_spectrum" : "bst_backproject");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bst::WsLayout L = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch,
-                                                  plan->prm.interp, plan->monopole);
+                                                  plan->prm.interp, plan->monopole, plan->tent_w);
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
@@ -566,6 +620,17 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.inv_gap = plan->inv_gap;
     ga.uniform = plan->uniform ? 1 : 0;
     ga.dc_scale = plan->dc_scale;
+    if (plan->tent) {
+        float2* patch = reinterpret_cast<float2*>(w + L.tent_off);
+        const bst::TentArgs ta{polar, patch, plan->tent_off, plan->tent_ent, (int)plan->tent_w,
+                               plan->V * plan->S};
+        bst::TraceRange tr("bst P5 tent pre-gather");
+        e = bst::launch_tent(*plan, ta, batch, s);
+        if (e != hipSuccess) return device_fail(e);
+        ga.tent_cols = plan->tent_cols;
+        ga.patch = patch;
+        ga.tent_w = (int)plan->tent_w;
+    }
     {
         bst::TraceRange tr("bst P5-P6 gather + column IFFT");
         e = bst::launch_gather_colifft(*plan, ga, s);
@@ -688,14 +753,11 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
 bst_status bst_destroy(bst_plan_t plan) {
     if (!plan) return BST_OK;
     bst_status st = BST_OK;
-    if (plan->dev_block || plan->adj_block) {
+    if (plan->dev_block || plan->adj_block || plan->tent_block) {
         DeviceGuard guard(plan->device);
-        if (plan->dev_block) {
-            const hipError_t e = hipFree(plan->dev_block);
-            if (e != hipSuccess) st = device_fail(e);
-        }
-        if (plan->adj_block) {
-            const hipError_t e = hipFree(plan->adj_block);
+        for (void* blk : {plan->dev_block, plan->adj_block, plan->tent_block}) {
+            if (!blk) continue;
+            const hipError_t e = hipFree(blk);
             if (e != hipSuccess) st = device_fail(e);
         }
     }

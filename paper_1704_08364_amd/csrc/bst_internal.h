@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include <cstddef>
+#include <vector>
+
 #include "bst.h"
 
 namespace bst {
@@ -54,6 +57,13 @@ struct bst_plan_s {
     float* mono_phi;     // [n]          phi(t_i - beta dt), monopole Gaussian (if enabled)
     bool monopole;
     float mono_inv, mono_amp, mono_rho_px;
+    // tent angular rule: small-radius ("wide") points, column by column
+    bool tent;
+    size_t tent_w;       // wide point slots (origin slot included)
+    void* tent_block;
+    int2* tent_cols;     // [G/2]        (first slot of column a, B_a): rows |b| <= B_a are wide
+    int* tent_off;       // [tent_w + 1] entry range of each wide point
+    uint2* tent_ent;     // [entries]    (polar offset j*S + lead + m | conj << 31, weight bits)
     int gather_slices;   // slices per gather block (coordinates reused across them)
     int gather_e;        // values per thread of the column transform, 8 or 16: fewer
                          // values mean less per-thread state and more resident waves
@@ -65,14 +75,17 @@ namespace bst {
 void set_last_error(hipError_t e);
 
 struct WsLayout {
-    size_t polar_off, dc_off, grid_off, mass_off, total;
+    size_t polar_off, dc_off, grid_off, mass_off, tent_off, total;
 };
 // Partial sinogram sums per slice for the monopole mass (one per reduction block).
 constexpr int kMassChunks = 64;
 // Row stride of a polar spectrum and tile-row width of the grid (complex values).
 int polar_stride(int M, int interp);
 int grid_width(int G);
-WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole);
+WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole,
+                          size_t tent_w);
+// wide points of the tent rule (column table filled when cols != nullptr)
+size_t tent_columns(int G, int V, std::vector<int2>& cols);
 
 struct ProjWsLayout {
     size_t grid_off, cart_off, polar_off, total;
@@ -125,6 +138,19 @@ struct GatherArgs {
     const double2* ang;      // [V] (cos theta_j, sin theta_j)
     const float* inv_gap;    // [V] 1 / angle gap (non-uniform angles)
     int uniform;             // angles are j pi / V
+    // tent angular rule (tent_cols != nullptr): wide points read their value
+    // from the pre-gathered patch [batch][tent_w] instead of the polar rows
+    const int2* tent_cols;
+    const float2* patch;
+    int tent_w;
+};
+
+struct TentArgs {            // pre-gather of the wide points of the tent rule
+    const float2* polar;     // [batch][V][S]
+    float2* patch;           // [batch][W]
+    const int* off;
+    const uint2* ent;
+    int W, VS;
 };
 
 struct RowArgs {
@@ -194,6 +220,7 @@ hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int ba
 hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st);
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st);
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st);
+hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStream_t st);
 hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipStream_t st);
 hipError_t launch_bruteforce(const bst_plan_s& p, const BfArgs& a, int batch, hipStream_t st);
 

@@ -43,10 +43,11 @@ namespace bst {
 
 // Groups of points whose sample reads are issued together (the E points of a
 // thread split into this many): uniform angles with linear radial taps issue
-// all reads first (1 group); cubic taps and non-uniform angles read one point
-// at a time (E groups), which measured faster for them -- 3.7 instead of
-// 5.5 ms for cubic taps at 64 x 2048^2: a point's four reads share cache
-// lines, and fewer reads in flight keep them in L1.
+// all reads first (1 group); cubic taps, non-uniform angles and the tent rule
+// read one point at a time (E groups), which measured faster for the first
+// two -- 3.7 instead of 5.5 ms for cubic taps at 64 x 2048^2: a point's four
+// reads share cache lines, and fewer reads in flight keep them in L1 -- and
+// leaves the tent variant the registers of its wide-point mask.
 #ifndef BST_GATHER_GROUPS_LINEAR
 #define BST_GATHER_GROUPS_LINEAR 1
 #endif
@@ -143,12 +144,22 @@ __device__ __forceinline__ bool lower_j0(unsigned flips, int e, bool lower) {
 }
 
 // Stencil of Cartesian point (col, bs); bs signed. NU: non-uniform angles.
-template <bool NU>
+// TENT: a wide point of the tent rule (|bs| <= B_col) gets bit 31 of o0 and
+// its patch slot's byte offset in the low bits; its polar reads go to the
+// zero slots.
+template <bool NU, bool TENT>
 __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a) {
     Stencil st;
     st.o0 = (unsigned)a.zero_slot * sizeof(float2);
     st.g = st.w1 = 0.f;
     if (col == 0 && bs == 0) return st;
+    if constexpr (TENT) {
+        const int2 tc = a.tent_cols[col];
+        if (bs >= -tc.y && bs <= tc.y) {
+            st.o0 = ((unsigned)(tc.x + bs + tc.y) * sizeof(float2)) | 0x80000000u;
+            return st;
+        }
+    }
     const double r = sqrt((double)(col * col + bs * bs)) * a.rscale;
     if (r >= (double)a.zero_slot) return st;
     const double mf = floor(r);
@@ -235,7 +246,7 @@ __device__ __forceinline__ float2 angular(float2 u0, float2 u1, float w1, bool l
     return make_float2(fmaf(fabsf(w1), u1.x, a0 * u0.x), fmaf(w1, u1.y, w0 * u0.y));
 }
 
-template <int LOGG, int EV, int TAPS, bool NU>
+template <int LOGG, int EV, int TAPS, bool NU, bool TENT>
 __global__ void __launch_bounds__((GatherCfg<LOGG, EV>::WG))
 __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather_colifft(GatherArgs a) {
     using C = GatherCfg<LOGG, EV>;
@@ -264,7 +275,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
         for (int h = 0; h < CH; ++h) {
             const int b = j + (c0 + h) * T;
             const int bs = b < G / 2 ? b : b - G;
-            const Stencil st = point_stencil<NU>(live ? col : 0, live ? bs : 0, a);
+            const Stencil st = point_stencil<NU, TENT>(live ? col : 0, live ? bs : 0, a);
             unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
             d[0] = st.o0;
             d[C::WG] = __float_as_uint(st.g);
@@ -289,6 +300,17 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
             pt[e].o0 &= kOffsetMask;
         }
     }
+    // tent rule: wide points as a bit mask; their o0 keeps the patch offset
+    // and their polar reads go to the zero slots (zoff)
+    unsigned wide = 0u;
+    const unsigned zoff = (unsigned)a.zero_slot * sizeof(float2);
+    if constexpr (TENT) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            wide |= (pt[e].o0 >> 31) << e;
+            pt[e].o0 &= kOffsetMask;
+        }
+    }
 
     const int s_begin = blockIdx.y * a.slices_per_block;
     const int s_end = min(a.batch, s_begin + a.slices_per_block);
@@ -306,7 +328,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
         float2 v[E];
         float dcv = 0.f;
         // rows b = j + e*T with e >= E/2 are the lower half-plane (b - G < 0)
-        constexpr int GROUPS0 = (TAPS == 2 && !NU) ? BST_GATHER_GROUPS_LINEAR : BST_GATHER_GROUPS_OTHER;
+        constexpr int GROUPS0 = (TAPS == 2 && !NU && !TENT) ? BST_GATHER_GROUPS_LINEAR : BST_GATHER_GROUPS_OTHER;
         constexpr int GROUPS = GROUPS0 < E ? GROUPS0 : E;
         if constexpr (GROUPS == 1 && TAPS == 2) {
             // all 2E sample-pair loads are issued before any is used
@@ -314,7 +336,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const bool wrap = __float_as_uint(pt[e].g) >> 31;
-                const unsigned o0 = pt[e].o0;
+                const unsigned o0 = (TENT && ((wide >> e) & 1u)) ? zoff : pt[e].o0;
                 pa[e] = load_pair(P, o0);
                 pb[e] = load_pair(P, o0 + (wrap ? wrap_bytes : row_bytes));
             }
@@ -344,11 +366,12 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
                 for (int i = 0; i < H; ++i) {
                     const Stencil& st = pt[h0 + i];
-                    const unsigned o1 = st.o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes);
-                    pa[i] = load_pair(P, st.o0);
+                    const unsigned o0 = (TENT && ((wide >> (h0 + i)) & 1u)) ? zoff : st.o0;
+                    const unsigned o1 = o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes);
+                    pa[i] = load_pair(P, o0);
                     pb[i] = load_pair(P, o1);
                     if constexpr (TAPS == 4) {
-                        qa[i] = load_pair(P, st.o0 + 16u);
+                        qa[i] = load_pair(P, o0 + 16u);
                         qb[i] = load_pair(P, o1 + 16u);
                     }
                 }
@@ -367,6 +390,15 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
                     v[e] = angular(u0, u1, pt[e].w1, lower_j0<NU>(flips, e, 2 * e >= E));
                 }
                 asm volatile("" ::: "memory");
+            }
+        }
+        if constexpr (TENT) {
+            // wide points: the value pre-gathered over their tent of angles
+            if (wide) {
+                const float2* Pt = a.patch + (size_t)s * a.tent_w;
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if ((wide >> e) & 1u) v[e] = Pt[pt[e].o0 / sizeof(float2)];
             }
         }
         // origin: column 0, row 0 is thread j = 0's first point
@@ -394,10 +426,43 @@ static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
     const int cols = C::G / 2;
     const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
     dim3 grid((cols + C::F - 1) / C::F, chunks);
-    if (a.uniform)
-        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, false>), grid, dim3(C::WG), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, true>), grid, dim3(C::WG), 0, st, a);
+    if (a.tent_cols) {
+        // tent rule: uniform angles and linear radial taps only (checked by the plan)
+        if constexpr (TAPS == 2)
+            hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, false, true>), grid, dim3(C::WG), 0, st, a);
+        else
+            return hipErrorInvalidValue;
+    } else if (a.uniform) {
+        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, false, false>), grid, dim3(C::WG), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, true, false>), grid, dim3(C::WG), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+// Pre-gather of the tent rule's wide points: each sums its list of polar
+// samples (weights and conjugations from the plan), in list order.
+__global__ void __launch_bounds__(256) k_tent(TentArgs a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= a.W) return;
+    const float2* P = a.polar + (size_t)s * a.VS;
+    const int e1 = a.off[i + 1];
+    float ax = 0.f, ay = 0.f;
+    for (int e = a.off[i]; e < e1; ++e) {
+        const uint2 en = a.ent[e];
+        const float2 v = P[en.x & kOffsetMask];
+        const float w = __uint_as_float(en.y);
+        ax = fmaf(w, v.x, ax);
+        ay = fmaf((en.x >> 31) ? -w : w, v.y, ay);
+    }
+    a.patch[(size_t)s * a.W + i] = make_float2(ax, ay);
+}
+
+hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStream_t st) {
+    (void)p;
+    if (a.W <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tent, dim3((a.W + 255) / 256, batch), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

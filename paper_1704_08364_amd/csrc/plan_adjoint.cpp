@@ -12,6 +12,15 @@
 // m >= M/2 zero; the origin and the Nyquist column k_x = G/2 excluded (they
 // have their own rules). Lists are filled in increasing point order, so the
 // device sum has a fixed order.
+//
+// The tent angular rule (an option of P5, uniform angles, linear radial taps)
+// replaces the two bracketing angles of a point at Cartesian radius
+// rho < V/pi by every angle index j of the period-pi continuation with
+// |q - j| < h, h = V/(pi rho), weighted (1 - |q - j|/h) and normalised; index
+// j + V is the conjugated image of angle j. These "wide" points are
+// enumerated column by column (column a holds rows |b| <= B_a, the origin
+// slot included but left empty), and their forward gather is a list per point
+// (build_tent_tables); the transposed lists of bst_project take the same taps.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -38,10 +47,96 @@ double keys_weight(double x) {
     return 0.0;
 }
 
+struct Tap {
+    int j;
+    bool flip;
+    double w;
+};
+
+// Tent taps of direction th in [0, pi) at Cartesian radius rho >= 1 (h > 1).
+void tent_taps(double th, double rho, int V, std::vector<Tap>& out) {
+    out.clear();
+    const double q = th * ((double)V / M_PI);
+    const double h = (double)V / (M_PI * rho);
+    const long lo = (long)std::floor(q - h), hi = (long)std::ceil(q + h);
+    double total = 0.0;
+    for (long jc = lo; jc <= hi; ++jc) {
+        const double w = 1.0 - std::fabs(q - (double)jc) / h;
+        if (w <= 0.0) continue;
+        long wraps = jc >= 0 ? jc / V : -((-jc + V - 1) / V);  // floor(jc / V)
+        const int j = (int)(jc - wraps * (long)V);
+        out.push_back({j, (wraps & 1) != 0, w});
+        total += w;
+    }
+    for (auto& t : out) t.w /= total;
+}
+
 }  // namespace
 
+size_t tent_columns(int G, int V, std::vector<int2>& cols) {
+    // wide points: a^2 + b^2 < (V/pi)^2 (where the tent is wider than one step)
+    const double R = (double)V / M_PI;
+    cols.assign(G / 2, make_int2(0, -1));
+    size_t total = 0;
+    for (int a = 0; a < G / 2; ++a) {
+        int B = -1;
+        if ((double)a < R) {
+            B = (int)std::floor(std::sqrt(std::max(0.0, R * R - (double)a * a)));
+            while (B >= 0 && (double)a * a + (double)B * B >= R * R) --B;
+            B = std::min(B, G / 2 - 1);
+        }
+        cols[a] = make_int2((int)total, B);
+        if (B >= 0) total += (size_t)(2 * B + 1);
+    }
+    return total;
+}
+
+bool build_tent_tables(int V, int M, int G, double rscale, int S, int lead, const std::vector<int2>& cols,
+                       std::vector<int>& off, std::vector<uint2>& ent) {
+    const int Mh = M / 2;
+    size_t W = 0;
+    for (const auto& c : cols)
+        if (c.y >= 0) W = (size_t)c.x + 2 * (size_t)c.y + 1;
+    off.assign(W + 1, 0);
+    ent.clear();
+    std::vector<Tap> taps;
+    for (int a = 0; a < G / 2; ++a) {
+        const int B = cols[a].y;
+        for (int b = -B; b <= B; ++b) {
+            const size_t idx = (size_t)cols[a].x + (size_t)(b + B);
+            if (!(a == 0 && b == 0)) {
+                const double rho = std::sqrt((double)a * a + (double)b * b);
+                const double r = rho * rscale;
+                const double phi = std::atan2((double)b, (double)a);
+                const bool lower = phi < 0.0;
+                const double th = lower ? phi + M_PI : phi;
+                tent_taps(th, rho, V, taps);
+                const double mf = std::floor(r);
+                const double g = r - mf;
+                const int m0 = (int)mf;
+                for (const auto& t : taps) {
+                    const bool c = lower != t.flip;
+                    for (int k = 0; k < 2; ++k) {
+                        const int m = m0 + k;
+                        const double w = t.w * (k ? g : 1.0 - g);
+                        if (m >= Mh || w == 0.0) continue;
+                        const float wf = (float)w;
+                        uint32_t wbits;
+                        std::memcpy(&wbits, &wf, 4);
+                        const uint32_t o = (uint32_t)(t.j * S + lead + m);
+                        ent.push_back(make_uint2(o | (c ? 0x80000000u : 0u), wbits));
+                    }
+                }
+            }
+            off[idx + 1] = (int)ent.size();
+        }
+    }
+    return true;
+}
+
 bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<double>& theta, bool uniform,
-                          int taps, std::vector<int>& off, std::vector<uint2>& ent) {
+                          int taps, const std::vector<int2>* tent_cols, std::vector<int>& off,
+                          std::vector<uint2>& ent) {
     const int Mh = M / 2;
     const size_t samples = (size_t)V * Mh;
     off.assign(samples + 1, 0);
@@ -56,6 +151,28 @@ bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<
             const double phi = std::atan2((double)b, (double)a);
             const bool lower = phi < 0.0;
             const double th = lower ? phi + M_PI : phi;
+            const uint32_t pt = (uint32_t)a * (uint32_t)G + (uint32_t)bi;
+            const double rho = std::sqrt((double)a * a + (double)b * b);
+            if (tent_cols && std::abs(b) <= (*tent_cols)[a].y) {
+                // wide point: the tent taps, linear radial taps
+                std::vector<Tap> tt;
+                tent_taps(th, rho, V, tt);
+                const double mf = std::floor(r);
+                const double g = r - mf;
+                const int m0 = (int)mf;
+                for (const auto& t : tt) {
+                    const bool c = lower != t.flip;
+                    for (int k = 0; k < 2; ++k) {
+                        const int m = m0 + k;
+                        const double w = t.w * (k ? g : 1.0 - g);
+                        if (m >= Mh || w == 0.0) continue;
+                        const int smp = t.j * Mh + m;
+                        tmp.push_back({smp, pt | (c ? 0x80000000u : 0u), (float)w});
+                        off[smp + 1]++;
+                    }
+                }
+                continue;
+            }
             int j0;
             double f;
             bool flip0 = false;
@@ -89,7 +206,6 @@ bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<
             const double mf = std::floor(r);
             const double g = r - mf;
             const int m0 = (int)mf;
-            const uint32_t pt = (uint32_t)a * (uint32_t)G + (uint32_t)bi;
             const int first = (taps == 4) ? -1 : 0;
             for (int side = 0; side < 2; ++side) {
                 const int j = side ? j1 : j0;

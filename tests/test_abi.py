@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1704_08364_amd as P
@@ -233,3 +234,28 @@ def test_max_batch_codes():
     # 288 GB of HBM holds far more than a 2048^2 x 2048-angle batch of 64
     p2, _ = _params(n=2048, V=2048, max_batch=4096)
     assert 64 < P.query_max_batch(p2, 288 * 10**9) < 4096
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(angular="tent"), 0),
+    (dict(angular="tent", filter="none", adjoint=True), 0),
+    (dict(angular="tent", interp="keys", taper="keys"), 4),          # linear radial taps only
+    (dict(angular="tent", angles=np.linspace(0, 3.0, 128)), 4),     # uniform angles only
+    (dict(angular=2), 4),
+    (dict(angular=-1), 4),
+])
+def test_tent_validation(kw, code):
+    p, _ = _params(n=256, V=128, **kw)
+    assert _validate(p) == code
+
+
+def test_tent_workspace_adds_the_wide_points():
+    # wide points: a^2 + b^2 < (V/pi)^2 over the half-plane columns a >= 0
+    n, V = 256, 300
+    R = V / np.pi
+    W = sum(2 * int(np.floor(np.sqrt(R * R - a * a) - 1e-12)) + 1 for a in range(int(np.ceil(R))) if a < R)
+    for B in (1, 5):
+        plain, _ = _params(n=n, V=V, max_batch=B)
+        tent, _ = _params(n=n, V=V, max_batch=B, angular="tent")
+        extra = P.query_workspace(tent, B) - P.query_workspace(plain, B)
+        assert extra == -(-B * W * 8 // 256) * 256

@@ -75,7 +75,8 @@ def measured_traffic(kernel: str, config_key: str):
         return None
 
 
-def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear", filter="ramp", monopole=0.0):
+def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear", filter="ramp", monopole=0.0,
+                 angular="linear"):
     """FP64 oracle on `slices` slices of the same batch, single thread."""
     import numpy as np
 
@@ -84,7 +85,7 @@ def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear", filter
 
     geom = Geometry(n, V, N)
     kw = dict(taper="keys", interp="keys") if interp == "keys" else {}
-    prm = obst.Params(filter=filter, monopole=monopole, **kw)
+    prm = obst.Params(filter=filter, monopole=monopole, angular=angular, **kw)
     t0 = time.perf_counter()
     refs = [obst.backproject(sino_cpu[i], geom, prm) for i in range(slices)]
     dt = time.perf_counter() - t0
@@ -158,7 +159,7 @@ def ls_workload(args):
     B, n, V = args.batch, args.n, args.angles
     dev = "cuda:0"
     g = synth.batch_sinograms(B, n, V, seed=170408369, device=dev)
-    plan = P.Plan(n, V, filter="none", max_batch=B, adjoint=True)
+    plan = P.Plan(n, V, filter="none", max_batch=B, adjoint=True, angular=args.angular)
     step = 1.0 / AG.lipschitz(plan, (B, n, n))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -169,7 +170,8 @@ def ls_workload(args):
            "value": round(args.steps / el, 3), "unit": "steps/s", "ms_per_step": round(el * 1e3 / args.steps, 3),
            "n_gpus": 1, "dtype": "f32", "data": "synthetic",
            "loss_first": losses[0], "loss_last": losses[-1],
-           "config": {"workload": f"{B} slices x {V} angles x {n} bins, random ellipse phantoms", "steps": args.steps}}
+           "config": {"workload": f"{B} slices x {V} angles x {n} bins, random ellipse phantoms",
+                      "steps": args.steps, "angular": args.angular}}
     print(json.dumps(out), flush=True)
 
 
@@ -245,6 +247,8 @@ def main():
                     help="ramp: FBP (default); none: plain backprojection B y")
     ap.add_argument("--monopole", type=float, default=0.0,
                     help="with --filter none: subtract a Gaussian monopole of this width (units of t)")
+    ap.add_argument("--angular", choices=("linear", "tent"), default="linear",
+                    help="angular kernel of the gather (tent: widened at small radii; uniform angles, linear interp)")
     ap.add_argument("--input", choices=("phantom", "random"), default="phantom",
                     help="random: N(0,1) sinograms (for hardware-counter runs, where generating "
                          "phantoms with thousands of small kernels is slow)")
@@ -289,7 +293,8 @@ def main():
     else:
         sino = synth.batch_sinograms(B, n, V, seed=170408366, device=dev)
     interp_kw = dict(taper="keys", interp="keys") if args.interp == "keys" else {}
-    plan = P.Plan(n, V, max_batch=B, filter=args.filter, monopole_width=args.monopole, **interp_kw)
+    plan = P.Plan(n, V, max_batch=B, filter=args.filter, monopole_width=args.monopole, angular=args.angular,
+                  **interp_kw)
     M, G = plan.M, plan.G
     ws = plan.workspace(B)
     img = torch.empty(B, N, N, dtype=torch.float32, device=dev)
@@ -351,7 +356,8 @@ def main():
         sino_cpu = sino[:s].double().cpu().numpy()
         img_cpu = img[:s].double().cpu().numpy()
         log(f"timing the FP64 oracle on {s} slices ...")
-        rate, dt, errs = cpu_baseline(sino_cpu, img_cpu, n, V, N, s, args.interp, args.filter, args.monopole)
+        rate, dt, errs = cpu_baseline(sino_cpu, img_cpu, n, V, N, s, args.interp, args.filter, args.monopole,
+                                      args.angular)
         cpu = {"value": round(rate, 4), "unit": "slices/s", "cores": 1, "kind": "oracle",
                "sample": f"{s} of the {B} slices ({V}x{n} -> {N}^2), FP64 NumPy BST, "
                          f"single thread, {dt:.1f} s"}
@@ -377,9 +383,11 @@ def main():
                         f"random 5-20 ellipse phantoms + 1% noise, P_r=P_c=2, "
                         + ("cubic (Keys) radial interpolation + its de-apodiser" if args.interp == "keys"
                            else "de-apodising taper")
-                        + (f", monopole subtraction (s = {args.monopole})" if args.monopole else ""),
+                        + (f", monopole subtraction (s = {args.monopole})" if args.monopole else "")
+                        + (", tent angular rule" if args.angular == "tent" else ""),
             "batch": B, "n_det": n, "n_angles": V, "n_out": N, "pad_radial": 2, "pad_cart": 2,
             "filter": args.filter, "input": args.input, "interp": args.interp, "monopole_width": args.monopole,
+            "angular": args.angular,
             "seed": 170408366,
         },
         "env": {"device": torch.cuda.get_device_name(0), "torch": torch.__version__, "hip": torch.version.hip,

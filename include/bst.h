@@ -89,8 +89,8 @@ typedef enum {
     BST_ANGULAR_TENT = 1    /* where one Cartesian cell spans several polar angles
                                (radius rho < V/pi grid steps) all angles within
                                h = V/(pi rho) steps, tent weights (1 - |q - j|/h)
-                               normalised; elsewhere linear. Uniform angles and
-                               BST_INTERP_LINEAR only. Its transpose (bst_project)
+                               normalised; elsewhere linear. Uniform angles,
+                               BST_INTERP_LINEAR and V/pi < G/2 - 1 only. Its transpose (bst_project)
                                is then a close Radon approximation; the backprojection
                                is as accurate as with LINEAR. Costs a pre-gather
                                kernel over the ~V^2/(2 pi) small-radius points and a

@@ -23,9 +23,6 @@ namespace bst {
 bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<double>& theta, bool uniform,
                           int taps, const std::vector<int2>* tent_cols, std::vector<int>& off,
                           std::vector<uint2>& ent);
-size_t tent_columns(int G, int V, std::vector<int2>& cols);
-bool build_tent_tables(int V, int M, int G, double rscale, int S, int lead, const std::vector<int2>& cols,
-                       std::vector<int>& off, std::vector<uint2>& ent);
 }
 
 namespace {
@@ -93,7 +90,7 @@ int polar_stride(int M, int interp) { return M / 2 + (interp == BST_INTERP_KEYS 
 int grid_width(int G) { return G / 2; }
 
 WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole,
-                          size_t tent_w) {
+                          size_t tent_elems) {
     (void)n;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     WsLayout L{};
@@ -107,7 +104,7 @@ WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int inte
     L.mass_off = up(L.grid_off + grid);
     const size_t mass = monopole ? B * (size_t)kMassChunks * sizeof(float) : 0;
     L.tent_off = up(L.mass_off + mass);
-    L.total = up(L.tent_off + B * tent_w * sizeof(float2));
+    L.total = up(L.tent_off + B * tent_elems * sizeof(float2));
     return L;
 }
 
@@ -123,9 +120,9 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
 }
 
 size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp, bool monopole,
-                       size_t tent_w) {
+                       size_t tent_elems) {
     if (batch == 0) return 0;
-    size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole, tent_w).total;
+    size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole, tent_elems).total;
     if (adjoint) {
         const size_t pj = project_workspace_layout(V, N, M, G, batch).total;
         if (pj > need) need = pj;
@@ -179,7 +176,11 @@ bst_status bst_validate(const bst_params* p) {
     if (p->apodization < BST_APOD_RAMLAK || p->apodization > BST_APOD_COSINE) return BST_E_PARAM;
     if (!std::isfinite(p->center_shift) || std::fabs(p->center_shift) >= 0.25 * p->n_det) return BST_E_PARAM;
     if (p->angular != BST_ANGULAR_LINEAR && p->angular != BST_ANGULAR_TENT) return BST_E_PARAM;
-    if (p->angular == BST_ANGULAR_TENT && (p->angles || p->interp != BST_INTERP_LINEAR)) return BST_E_PARAM;
+    if (p->angular == BST_ANGULAR_TENT) {
+        if (p->angles || p->interp != BST_INTERP_LINEAR) return BST_E_PARAM;
+        // the wide disk (radius V/pi) must stay inside the Cartesian grid
+        if ((double)p->n_angles / M_PI >= (double)(pc * p->n_out / 2 - 1)) return BST_E_PARAM;
+    }
     if (p->monopole_width != 0.0) {
         // plain B only, not with the adjoint, and a Gaussian the detector resolves
         const double s = p->monopole_width, dt = 2.0 / p->n_det;
@@ -200,10 +201,21 @@ bst_status bst_validate(const bst_params* p) {
 }
 
 namespace {
-size_t params_tent_w(const bst_params* p, int G) {
+// complex values per slice of the tent rule's buffers: the wide points'
+// values and the radius-major copy of the polar samples they read
+size_t params_tent_elems(const bst_params* p, int M, int G) {
     if (p->angular != BST_ANGULAR_TENT) return 0;
     std::vector<int2> cols;
-    return bst::tent_columns(G, p->n_angles, cols);
+    std::vector<int4> chunks;
+    std::vector<int> coff;
+    const double rscale = (double)pad_or_default(p->pad_radial) / (double)pad_or_default(p->pad_cart);
+    const size_t W = bst::tent_columns(G, p->n_angles, cols);
+    bst::tent_chunks(p->n_angles, cols, chunks, coff);
+    return bst::tent_workspace_elems(W, bst::tent_rows(p->n_angles, M, rscale), p->n_angles, chunks.size());
+}
+
+size_t tent_elems(const bst_plan_s* plan) {
+    return plan->tent ? bst::tent_workspace_elems(plan->tent_w, plan->tent_rows, plan->V, plan->tent_chunks) : 0;
 }
 }  // namespace
 
@@ -215,7 +227,7 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
-                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0, params_tent_w(p, G));
+                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0, params_tent_elems(p, M, G));
     return BST_OK;
 }
 
@@ -227,7 +239,7 @@ bst_status bst_query_max_batch(const bst_params* p, size_t budget_bytes, int32_t
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     const size_t io = ((size_t)p->n_angles * p->n_det + (size_t)p->n_out * p->n_out) * sizeof(float);
-    const size_t tw = params_tent_w(p, G);
+    const size_t tw = params_tent_elems(p, M, G);
     auto need = [&](int32_t q) {
         return (size_t)q * io + bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, q, p->adjoint != 0,
                                                      p->interp, p->monopole_width != 0.0, tw);
@@ -427,12 +439,14 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::vector<int2> tent_cols;
     if (pl->tent) {
         pl->tent_w = bst::tent_columns(G, V, tent_cols);
-        std::vector<int> toff;
-        std::vector<uint2> tent;
-        bst::build_tent_tables(V, M, G, pl->rscale, pl->S, pl->lead, tent_cols, toff, tent);
-        const size_t o_off = up((size_t)(G / 2) * sizeof(int2));
-        const size_t o_ent = up(o_off + toff.size() * sizeof(int));
-        const size_t t_total = o_ent + std::max<size_t>(tent.size(), 1) * sizeof(uint2);
+        pl->tent_rows = bst::tent_rows(V, M, pl->rscale);
+        std::vector<int4> chunks;
+        std::vector<int> coff;
+        bst::tent_chunks(V, tent_cols, chunks, coff);
+        pl->tent_chunks = chunks.size();
+        const size_t o_chunk = up(tent_cols.size() * sizeof(int2));
+        const size_t o_coff = up(o_chunk + std::max<size_t>(chunks.size(), 1) * sizeof(int4));
+        const size_t t_total = o_coff + coff.size() * sizeof(int);
         e = hipMalloc(&pl->tent_block, t_total);
         if (e != hipSuccess) {
             g_last_error = hipGetErrorString(e);
@@ -442,9 +456,9 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
         }
         unsigned char* tb = static_cast<unsigned char*>(pl->tent_block);
         e = hipMemcpy(tb, tent_cols.data(), tent_cols.size() * sizeof(int2), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(tb + o_off, toff.data(), toff.size() * sizeof(int), hipMemcpyHostToDevice);
-        if (e == hipSuccess && !tent.empty())
-            e = hipMemcpy(tb + o_ent, tent.data(), tent.size() * sizeof(uint2), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !chunks.empty())
+            e = hipMemcpy(tb + o_chunk, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(tb + o_coff, coff.data(), coff.size() * sizeof(int), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipFree(pl->tent_block);
             (void)hipFree(pl->dev_block);
@@ -452,8 +466,8 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
             return device_fail(e);
         }
         pl->tent_cols = reinterpret_cast<int2*>(tb);
-        pl->tent_off = reinterpret_cast<int*>(tb + o_off);
-        pl->tent_ent = reinterpret_cast<uint2*>(tb + o_ent);
+        pl->tent_chunk = reinterpret_cast<int4*>(tb + o_chunk);
+        pl->tent_coff = reinterpret_cast<int*>(tb + o_coff);
     }
     if (pl->adjoint) {
         std::vector<int> off;
@@ -505,7 +519,7 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
     if (!plan || !bytes) return BST_E_NULL;
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
     *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint,
-                                  plan->prm.interp, plan->monopole, plan->tent_w);
+                                  plan->prm.interp, plan->monopole, tent_elems(plan));
     return BST_OK;
 }
 
@@ -521,7 +535,7 @@ bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const vo
     if (!in || !out) return BST_E_NULL;
     if (need_ws) {
         *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp,
-                                      plan->monopole, plan->tent_w)
+                                      plan->monopole, tent_elems(plan))
                     .total;
         if (!ws) return BST_E_NULL;
         if (ws_bytes < *need) return BST_E_WORKSPACE;
@@ -561,7 +575,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     bst::TraceRange trace(spectrum_only ? "bst_debug_spectrum" : "bst_backproject");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bst::WsLayout L = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch,
-                                                  plan->prm.interp, plan->monopole, plan->tent_w);
+                                                  plan->prm.interp, plan->monopole, tent_elems(plan));
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
@@ -622,8 +636,12 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.dc_scale = plan->dc_scale;
     if (plan->tent) {
         float2* patch = reinterpret_cast<float2*>(w + L.tent_off);
-        const bst::TentArgs ta{polar, patch, plan->tent_off, plan->tent_ent, (int)plan->tent_w,
-                               plan->V * plan->S};
+        float2* trans = patch + (size_t)batch * plan->tent_w;
+        float2* part = trans + (size_t)batch * plan->tent_rows * plan->V;
+        float* wsum = reinterpret_cast<float*>(part + (size_t)batch * plan->tent_chunks);
+        const bst::TentArgs ta{polar, trans, patch, part, wsum, plan->tent_cols, plan->tent_chunk, plan->tent_coff,
+                               (int)plan->tent_w, (int)plan->tent_chunks, plan->V, plan->S, plan->lead,
+                               plan->tent_rows, plan->G / 2, plan->rscale};
         bst::TraceRange tr("bst P5 tent pre-gather");
         e = bst::launch_tent(*plan, ta, batch, s);
         if (e != hipSuccess) return device_fail(e);

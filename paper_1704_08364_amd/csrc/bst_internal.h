@@ -60,10 +60,12 @@ struct bst_plan_s {
     // tent angular rule: small-radius ("wide") points, column by column
     bool tent;
     size_t tent_w;       // wide point slots (origin slot included)
+    int tent_rows;       // radial samples the wide points read: min(M/2, floor(rscale V/pi) + 2)
+    size_t tent_chunks;  // tap chunks (at most kTentChunk angle taps each)
     void* tent_block;
     int2* tent_cols;     // [G/2]        (first slot of column a, B_a): rows |b| <= B_a are wide
-    int* tent_off;       // [tent_w + 1] entry range of each wide point
-    uint2* tent_ent;     // [entries]    (polar offset j*S + lead + m | conj << 31, weight bits)
+    int4* tent_chunk;    // [chunks]     (slot, first tap j, last tap j, 0) in the continuation
+    int* tent_coff;      // [tent_w + 1] chunk range of each slot
     int gather_slices;   // slices per gather block (coordinates reused across them)
     int gather_e;        // values per thread of the column transform, 8 or 16: fewer
                          // values mean less per-thread state and more resident waves
@@ -82,10 +84,20 @@ constexpr int kMassChunks = 64;
 // Row stride of a polar spectrum and tile-row width of the grid (complex values).
 int polar_stride(int M, int interp);
 int grid_width(int G);
+// tent_elems: complex values per slice of the tent rule's buffers (0 without it)
 WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole,
-                          size_t tent_w);
-// wide points of the tent rule (column table filled when cols != nullptr)
+                          size_t tent_elems);
+// wide points of the tent rule and their column table
 size_t tent_columns(int G, int V, std::vector<int2>& cols);
+// radial samples the wide points read
+int tent_rows(int V, int M, double rscale);
+// angle taps per chunk of the tent pre-gather; the chunks of every slot
+constexpr int kTentChunk = 32;
+void tent_chunks(int V, const std::vector<int2>& cols, std::vector<int4>& chunks, std::vector<int>& coff);
+// complex values per slice of the tent rule's workspace (0 without it): the
+// slots' values, the radius-major copy of the samples they read, the chunk
+// partial sums; plus chunks real weight sums once
+size_t tent_workspace_elems(size_t W, int rows, int V, size_t chunks);
 
 struct ProjWsLayout {
     size_t grid_off, cart_off, polar_off, total;
@@ -147,10 +159,15 @@ struct GatherArgs {
 
 struct TentArgs {            // pre-gather of the wide points of the tent rule
     const float2* polar;     // [batch][V][S]
+    float2* trans;           // [batch][rows][V]: the first rows radial samples, radius-major
     float2* patch;           // [batch][W]
-    const int* off;
-    const uint2* ent;
-    int W, VS;
+    float2* part;            // [batch][C] chunk sums (conjugated for the lower half-plane)
+    float* wsum;             // [C] chunk weight sums
+    const int2* cols;        // [G/2] column table of the wide points
+    const int4* chunk;       // [C]
+    const int* coff;         // [W + 1]
+    int W, C, V, S, lead, rows, ncols;
+    double rscale;           // P_r / P_c
 };
 
 struct RowArgs {

@@ -440,29 +440,130 @@ static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Pre-gather of the tent rule's wide points: each sums its list of polar
-// samples (weights and conjugations from the plan), in list order.
-__global__ void __launch_bounds__(256) k_tent(TentArgs a) {
+// Tent rule, step 1: the first `rows` radial samples of every angle,
+// radius-major ([m][j]), through 32 x 32 tiles in LDS, so the angular sums of
+// step 2 walk contiguous memory.
+__global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a) {
+    __shared__ float2 tile[32][33];
+    const int s = blockIdx.z;
+    const int m0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const float2* P = a.polar + (size_t)s * a.V * a.S + a.lead;
+    float2* T = a.trans + (size_t)s * a.rows * a.V;
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int j = j0 + ty + k, m = m0 + tx;
+        if (j < a.V && m < a.rows) tile[ty + k][tx] = P[(size_t)j * a.S + m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int m = m0 + ty + k, j = j0 + tx;
+        if (j < a.V && m < a.rows) T[(size_t)m * a.V + j] = tile[tx][ty + k];
+    }
+}
+
+// Tent rule, step 2: one thread per chunk of at most kTentChunk angle taps
+// of one wide point, for kTentSlices slices. The point (a, b) of the chunk's
+// slot comes from the column table; its taps are the angle indices j of the
+// period-pi continuation with |q - j| < h, weights (1 - |q - j| / h), on the
+// two radial samples m0, m0 + 1 (linear weights); j outside [0, V) reads the
+// conjugated image of j mod V, and the lower half-plane conjugates the
+// result. Coordinates are formed in FP64 as on the host. Splitting the long
+// tap ranges near the origin (over a thousand taps) into chunks keeps every
+// thread's loop short.
+constexpr int kTentSlices = 8;
+
+__device__ __forceinline__ int tent_column(const TentArgs& a, int slot) {
+    // the last column whose first slot is <= slot
+    int lo = 0, hi = a.ncols - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.cols[mid].x <= slot) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_tent_chunks(TentArgs a, int batch) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int s0 = blockIdx.y * kTentSlices;
+    if (c >= a.C) return;
+    const int ns = min(kTentSlices, batch - s0);
+    const int4 ch = a.chunk[c];
+    const int col = tent_column(a, ch.x);
+    const int2 tc = a.cols[col];
+    const int b = ch.x - tc.x - tc.y;
+    const double rho = sqrt((double)col * col + (double)b * b);
+    const double phi = atan2((double)b, (double)col);
+    const bool lower = phi < 0.0;
+    const double q = (lower ? phi + M_PI : phi) * ((double)a.V / M_PI);
+    const double h = (double)a.V / (M_PI * rho);
+    const double r = rho * a.rscale;
+    const int m0 = (int)floor(r);
+    const float g = (float)(r - (double)m0);
+    const float w1r = m0 + 1 < a.rows ? g : 0.f;  // samples past M/2 are zero
+    const float inv_h = (float)(1.0 / h);
+    const size_t sstride = (size_t)a.rows * a.V;
+    const float2* T0 = a.trans + (size_t)s0 * sstride + (size_t)m0 * a.V;
+    const float2* T1 = T0 + (m0 + 1 < a.rows ? a.V : 0);
+    float ax[kTentSlices], ay[kTentSlices];
+#pragma unroll
+    for (int k = 0; k < kTentSlices; ++k) ax[k] = ay[k] = 0.f;
+    float total = 0.f;
+    for (int jc = ch.y; jc <= ch.z; ++jc) {
+        const float w = 1.f - fabsf((float)(q - (double)jc)) * inv_h;
+        if (w <= 0.f) continue;
+        total += w;
+        const bool flip = jc < 0 || jc >= a.V;
+        const int jj = jc < 0 ? jc + a.V : (jc >= a.V ? jc - a.V : jc);
+        const float wy = flip ? -w : w;
+        float2 v0[kTentSlices], v1[kTentSlices];
+#pragma unroll
+        for (int k = 0; k < kTentSlices; ++k) {
+            const size_t so = (size_t)(k < ns ? k : 0) * sstride + jj;
+            v0[k] = T0[so];
+            v1[k] = T1[so];
+        }
+#pragma unroll
+        for (int k = 0; k < kTentSlices; ++k) {
+            const float vx = fmaf(w1r, v1[k].x - v0[k].x, v0[k].x);
+            const float vy = fmaf(w1r, v1[k].y - v0[k].y, v0[k].y);
+            ax[k] = fmaf(w, vx, ax[k]);
+            ay[k] = fmaf(wy, vy, ay[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kTentSlices; ++k)
+        if (k < ns) a.part[(size_t)(s0 + k) * a.C + c] = make_float2(ax[k], lower ? -ay[k] : ay[k]);
+    if (blockIdx.y == 0) a.wsum[c] = total;
+}
+
+// Tent rule, step 3: each wide point's value is the sum of its chunks'
+// partial sums over the sum of their weights (chunks in order).
+__global__ void __launch_bounds__(256) k_tent_reduce(TentArgs a) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int s = blockIdx.y;
     if (i >= a.W) return;
-    const float2* P = a.polar + (size_t)s * a.VS;
-    const int e1 = a.off[i + 1];
-    float ax = 0.f, ay = 0.f;
-    for (int e = a.off[i]; e < e1; ++e) {
-        const uint2 en = a.ent[e];
-        const float2 v = P[en.x & kOffsetMask];
-        const float w = __uint_as_float(en.y);
-        ax = fmaf(w, v.x, ax);
-        ay = fmaf((en.x >> 31) ? -w : w, v.y, ay);
+    const int c1 = a.coff[i + 1];
+    float ax = 0.f, ay = 0.f, tot = 0.f;
+    for (int c = a.coff[i]; c < c1; ++c) {
+        const float2 p = a.part[(size_t)s * a.C + c];
+        ax += p.x;
+        ay += p.y;
+        tot += a.wsum[c];
     }
-    a.patch[(size_t)s * a.W + i] = make_float2(ax, ay);
+    const float inv = tot > 0.f ? 1.f / tot : 0.f;
+    a.patch[(size_t)s * a.W + i] = make_float2(ax * inv, ay * inv);
 }
 
 hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStream_t st) {
     (void)p;
     if (a.W <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tent, dim3((a.W + 255) / 256, batch), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_tent_transpose, dim3((a.rows + 31) / 32, (a.V + 31) / 32, batch), dim3(256), 0, st, a);
+    if (a.C > 0)
+        hipLaunchKernelGGL(k_tent_chunks, dim3((a.C + 255) / 256, (batch + kTentSlices - 1) / kTentSlices), dim3(256),
+                           0, st, a, batch);
+    hipLaunchKernelGGL(k_tent_reduce, dim3((a.W + 255) / 256, batch), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -19,8 +19,8 @@
 // |q - j| < h, h = V/(pi rho), weighted (1 - |q - j|/h) and normalised; index
 // j + V is the conjugated image of angle j. These "wide" points are
 // enumerated column by column (column a holds rows |b| <= B_a, the origin
-// slot included but left empty), and their forward gather is a list per point
-// (build_tent_tables); the transposed lists of bst_project take the same taps.
+// slot included but left empty); the forward gather evaluates their taps on
+// the device, and the transposed lists of bst_project take the same taps.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -91,47 +91,42 @@ size_t tent_columns(int G, int V, std::vector<int2>& cols) {
     return total;
 }
 
-bool build_tent_tables(int V, int M, int G, double rscale, int S, int lead, const std::vector<int2>& cols,
-                       std::vector<int>& off, std::vector<uint2>& ent) {
-    const int Mh = M / 2;
+void tent_chunks(int V, const std::vector<int2>& cols, std::vector<int4>& chunks, std::vector<int>& coff) {
+    chunks.clear();
     size_t W = 0;
     for (const auto& c : cols)
         if (c.y >= 0) W = (size_t)c.x + 2 * (size_t)c.y + 1;
-    off.assign(W + 1, 0);
-    ent.clear();
-    std::vector<Tap> taps;
-    for (int a = 0; a < G / 2; ++a) {
+    coff.assign(W + 1, 0);
+    for (int a = 0; a < (int)cols.size(); ++a) {
         const int B = cols[a].y;
         for (int b = -B; b <= B; ++b) {
             const size_t idx = (size_t)cols[a].x + (size_t)(b + B);
             if (!(a == 0 && b == 0)) {
+                // the tap range of the point, one index wider on each side than
+                // |q - j| < h needs (taps outside it get weight 0 on the device)
                 const double rho = std::sqrt((double)a * a + (double)b * b);
-                const double r = rho * rscale;
                 const double phi = std::atan2((double)b, (double)a);
-                const bool lower = phi < 0.0;
-                const double th = lower ? phi + M_PI : phi;
-                tent_taps(th, rho, V, taps);
-                const double mf = std::floor(r);
-                const double g = r - mf;
-                const int m0 = (int)mf;
-                for (const auto& t : taps) {
-                    const bool c = lower != t.flip;
-                    for (int k = 0; k < 2; ++k) {
-                        const int m = m0 + k;
-                        const double w = t.w * (k ? g : 1.0 - g);
-                        if (m >= Mh || w == 0.0) continue;
-                        const float wf = (float)w;
-                        uint32_t wbits;
-                        std::memcpy(&wbits, &wf, 4);
-                        const uint32_t o = (uint32_t)(t.j * S + lead + m);
-                        ent.push_back(make_uint2(o | (c ? 0x80000000u : 0u), wbits));
-                    }
-                }
+                const double q = (phi < 0.0 ? phi + M_PI : phi) * ((double)V / M_PI);
+                const double h = (double)V / (M_PI * rho);
+                const int lo = (int)std::floor(q - h) - 1, hi = (int)std::ceil(q + h) + 1;
+                for (int j0 = lo; j0 <= hi; j0 += kTentChunk)
+                    chunks.push_back(make_int4((int)idx, j0, std::min(hi, j0 + kTentChunk - 1), 0));
             }
-            off[idx + 1] = (int)ent.size();
+            coff[idx + 1] = (int)chunks.size();
         }
     }
-    return true;
+}
+
+size_t tent_workspace_elems(size_t W, int rows, int V, size_t chunks) {
+    // per slice: W values, rows x V transposed samples, chunks partial sums;
+    // the chunks weight sums (float) fit in chunks/2 + 1 complex slots once
+    return W + (size_t)rows * (size_t)V + chunks + (chunks / 2 + 1);
+}
+
+int tent_rows(int V, int M, double rscale) {
+    // wide points have rho < V/pi, so radial taps m0 <= floor(rscale V/pi) and m0 + 1
+    const int rows = (int)std::floor(rscale * (double)V / M_PI) + 2;
+    return std::min(rows, M / 2);
 }
 
 bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<double>& theta, bool uniform,

@@ -243,19 +243,41 @@ def test_max_batch_codes():
     (dict(angular="tent", angles=np.linspace(0, 3.0, 128)), 4),     # uniform angles only
     (dict(angular=2), 4),
     (dict(angular=-1), 4),
+    (dict(angular="tent", V=790), 0),                                 # V/pi = 251.5 < G/2 - 1 = 255
+    (dict(angular="tent", V=802), 4),                                 # V/pi = 255.3: the disk leaves the grid
 ])
 def test_tent_validation(kw, code):
-    p, _ = _params(n=256, V=128, **kw)
+    kw = dict(kw)
+    p, _ = _params(n=256, V=kw.pop("V", 128), **kw)
     assert _validate(p) == code
 
 
 def test_tent_workspace_adds_the_wide_points():
-    # wide points: a^2 + b^2 < (V/pi)^2 over the half-plane columns a >= 0
+    # wide points: a^2 + b^2 < (V/pi)^2 over the half-plane columns a >= 0, plus
+    # a radius-major copy of the radial samples they read (m <= floor(V/pi) + 1
+    # at P_r = P_c), complex64 per slice
+    # and the pre-gather's chunk sums: each point's tap range floor(q-h)-1 ..
+    # ceil(q+h)+1 in chunks of 32, one complex sum per slice and one weight
+    # sum per chunk
+    import math
     n, V = 256, 300
     R = V / np.pi
-    W = sum(2 * int(np.floor(np.sqrt(R * R - a * a) - 1e-12)) + 1 for a in range(int(np.ceil(R))) if a < R)
+    W, C = 0, 0
+    for a in range(int(np.ceil(R))):
+        Bc = int(np.floor(np.sqrt(R * R - a * a) - 1e-12))
+        W += 2 * Bc + 1
+        for b in range(-Bc, Bc + 1):
+            if a == 0 and b == 0:
+                continue
+            rho = math.hypot(a, b)
+            phi = math.atan2(b, a)
+            q = (phi + math.pi if phi < 0 else phi) * V / math.pi
+            h = V / (math.pi * rho)
+            lo, hi = math.floor(q - h) - 1, math.ceil(q + h) + 1
+            C += -(-(hi - lo + 1) // 32)
+    rows = min(int(np.floor(R)) + 2, n)
     for B in (1, 5):
         plain, _ = _params(n=n, V=V, max_batch=B)
         tent, _ = _params(n=n, V=V, max_batch=B, angular="tent")
         extra = P.query_workspace(tent, B) - P.query_workspace(plain, B)
-        assert extra == -(-B * W * 8 // 256) * 256
+        assert extra == -(-B * (W + rows * V + C + C // 2 + 1) * 8 // 256) * 256

@@ -799,7 +799,8 @@ def test_tent_adjoint_identity_and_least_squares(P):
     for b in range(B):
         lhs = obf.inner_sino(Rf[b], y[b].double().cpu().numpy(), geom)
         rhs = obf.inner_image(f[b].double().cpu().numpy(), By[b], geom)
-        assert abs(lhs - rhs) <= 2e-6 * max(abs(lhs), abs(rhs))
+        # FP32 sums of random data cancel: the same 1e-5 as the bilinear identity test
+        assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
     # least squares against analytic sinograms: with the tent the forward
     # model is the Radon transform, so the iterates approach the phantom
     sgeom = synth.Geometry(N, V, N)

@@ -83,9 +83,13 @@ void release(bst_batch_s* b) {
 hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStream_t st) {
     const bst_plan_s& p = *c.plan;
     const int batch = (int)c.members.size();
-    const size_t tent_elems = p.tent ? bst::tent_workspace_elems(p.tent_w, p.tent_rows, p.V, p.tent_chunks) : 0;
-    const bst::WsLayout L =
-        bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch, p.prm.interp, p.monopole, tent_elems);
+    bst::TentSizes tent;
+    if (p.tent) {
+        tent.W = p.tent_w;
+        tent.rowsV = (size_t)p.tent_rows * (size_t)p.V;
+        tent.C = p.tent_chunks;
+    }
+    const bst::WsLayout L = bst::workspace_layout(p.n, p.V, p.N, p.M, p.G, batch, p.prm.interp, p.monopole, tent);
     unsigned char* w = static_cast<unsigned char*>(ws) + c.ws_off;
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
@@ -123,9 +127,9 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     ga.dc_scale = p.dc_scale;
     if (p.tent) {
         float2* patch = reinterpret_cast<float2*>(w + L.tent_off);
-        float2* trans = patch + (size_t)batch * p.tent_w;
-        float2* part = trans + (size_t)batch * p.tent_rows * p.V;
-        float* wsum = reinterpret_cast<float*>(part + (size_t)batch * p.tent_chunks);
+        float2* trans = reinterpret_cast<float2*>(w + L.tent_trans_off);
+        float2* part = reinterpret_cast<float2*>(w + L.tent_part_off);
+        float* wsum = reinterpret_cast<float*>(w + L.tent_wsum_off);
         const bst::TentArgs ta{polar, trans, patch, part, wsum, p.tent_cols, p.tent_chunk, p.tent_coff,
                                (int)p.tent_w, (int)p.tent_chunks, p.V, p.S, p.lead, p.tent_rows, p.G / 2, p.rscale};
         e = bst::launch_tent(p, ta, batch, st);

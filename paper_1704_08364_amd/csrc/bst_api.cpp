@@ -90,7 +90,7 @@ int polar_stride(int M, int interp) { return M / 2 + (interp == BST_INTERP_KEYS 
 int grid_width(int G) { return G / 2; }
 
 WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole,
-                          size_t tent_elems) {
+                          const TentSizes& tent) {
     (void)n;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     WsLayout L{};
@@ -104,7 +104,13 @@ WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int inte
     L.mass_off = up(L.grid_off + grid);
     const size_t mass = monopole ? B * (size_t)kMassChunks * sizeof(float) : 0;
     L.tent_off = up(L.mass_off + mass);
-    L.total = up(L.tent_off + B * tent_elems * sizeof(float2));
+    // tent rule: wide-point values [B][W], the radius-major copy [ceil(B/8)][rows][V][8],
+    // chunk sums [B][C], chunk weight sums [C] (float)
+    const size_t groups = (B + kTentSlices - 1) / kTentSlices;
+    L.tent_trans_off = up(L.tent_off + B * tent.W * sizeof(float2));
+    L.tent_part_off = up(L.tent_trans_off + groups * kTentSlices * tent.rowsV * sizeof(float2));
+    L.tent_wsum_off = up(L.tent_part_off + B * tent.C * sizeof(float2));
+    L.total = up(L.tent_wsum_off + tent.C * sizeof(float));
     return L;
 }
 
@@ -120,9 +126,9 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
 }
 
 size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp, bool monopole,
-                       size_t tent_elems) {
+                       const TentSizes& tent) {
     if (batch == 0) return 0;
-    size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole, tent_elems).total;
+    size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole, tent).total;
     if (adjoint) {
         const size_t pj = project_workspace_layout(V, N, M, G, batch).total;
         if (pj > need) need = pj;
@@ -203,19 +209,27 @@ bst_status bst_validate(const bst_params* p) {
 namespace {
 // complex values per slice of the tent rule's buffers: the wide points'
 // values and the radius-major copy of the polar samples they read
-size_t params_tent_elems(const bst_params* p, int M, int G) {
-    if (p->angular != BST_ANGULAR_TENT) return 0;
+bst::TentSizes params_tent_sizes(const bst_params* p, int M, int G) {
+    bst::TentSizes t;
+    if (p->angular != BST_ANGULAR_TENT) return t;
     std::vector<int2> cols;
     std::vector<int4> chunks;
     std::vector<int> coff;
     const double rscale = (double)pad_or_default(p->pad_radial) / (double)pad_or_default(p->pad_cart);
-    const size_t W = bst::tent_columns(G, p->n_angles, cols);
+    t.W = bst::tent_columns(G, p->n_angles, cols);
     bst::tent_chunks(p->n_angles, cols, chunks, coff);
-    return bst::tent_workspace_elems(W, bst::tent_rows(p->n_angles, M, rscale), p->n_angles, chunks.size());
+    t.rowsV = (size_t)bst::tent_rows(p->n_angles, M, rscale) * (size_t)p->n_angles;
+    t.C = chunks.size();
+    return t;
 }
 
-size_t tent_elems(const bst_plan_s* plan) {
-    return plan->tent ? bst::tent_workspace_elems(plan->tent_w, plan->tent_rows, plan->V, plan->tent_chunks) : 0;
+bst::TentSizes tent_sizes(const bst_plan_s* plan) {
+    bst::TentSizes t;
+    if (!plan->tent) return t;
+    t.W = plan->tent_w;
+    t.rowsV = (size_t)plan->tent_rows * (size_t)plan->V;
+    t.C = plan->tent_chunks;
+    return t;
 }
 }  // namespace
 
@@ -227,7 +241,7 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
-                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0, params_tent_elems(p, M, G));
+                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0, params_tent_sizes(p, M, G));
     return BST_OK;
 }
 
@@ -239,7 +253,7 @@ bst_status bst_query_max_batch(const bst_params* p, size_t budget_bytes, int32_t
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
     const size_t io = ((size_t)p->n_angles * p->n_det + (size_t)p->n_out * p->n_out) * sizeof(float);
-    const size_t tw = params_tent_elems(p, M, G);
+    const bst::TentSizes tw = params_tent_sizes(p, M, G);
     auto need = [&](int32_t q) {
         return (size_t)q * io + bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, q, p->adjoint != 0,
                                                      p->interp, p->monopole_width != 0.0, tw);
@@ -519,7 +533,7 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
     if (!plan || !bytes) return BST_E_NULL;
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
     *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint,
-                                  plan->prm.interp, plan->monopole, tent_elems(plan));
+                                  plan->prm.interp, plan->monopole, tent_sizes(plan));
     return BST_OK;
 }
 
@@ -535,7 +549,7 @@ bst_status check_call(bst_plan_t plan, const void* in, size_t in_bytes, const vo
     if (!in || !out) return BST_E_NULL;
     if (need_ws) {
         *need = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp,
-                                      plan->monopole, tent_elems(plan))
+                                      plan->monopole, tent_sizes(plan))
                     .total;
         if (!ws) return BST_E_NULL;
         if (ws_bytes < *need) return BST_E_WORKSPACE;
@@ -575,7 +589,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     bst::TraceRange trace(spectrum_only ? "bst_debug_spectrum" : "bst_backproject");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bst::WsLayout L = bst::workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch,
-                                                  plan->prm.interp, plan->monopole, tent_elems(plan));
+                                                  plan->prm.interp, plan->monopole, tent_sizes(plan));
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
@@ -636,9 +650,9 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
     ga.dc_scale = plan->dc_scale;
     if (plan->tent) {
         float2* patch = reinterpret_cast<float2*>(w + L.tent_off);
-        float2* trans = patch + (size_t)batch * plan->tent_w;
-        float2* part = trans + (size_t)batch * plan->tent_rows * plan->V;
-        float* wsum = reinterpret_cast<float*>(part + (size_t)batch * plan->tent_chunks);
+        float2* trans = reinterpret_cast<float2*>(w + L.tent_trans_off);
+        float2* part = reinterpret_cast<float2*>(w + L.tent_part_off);
+        float* wsum = reinterpret_cast<float*>(w + L.tent_wsum_off);
         const bst::TentArgs ta{polar, trans, patch, part, wsum, plan->tent_cols, plan->tent_chunk, plan->tent_coff,
                                (int)plan->tent_w, (int)plan->tent_chunks, plan->V, plan->S, plan->lead,
                                plan->tent_rows, plan->G / 2, plan->rscale};

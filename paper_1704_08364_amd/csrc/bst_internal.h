@@ -77,16 +77,24 @@ namespace bst {
 void set_last_error(hipError_t e);
 
 struct WsLayout {
-    size_t polar_off, dc_off, grid_off, mass_off, tent_off, total;
+    size_t polar_off, dc_off, grid_off, mass_off;
+    size_t tent_off, tent_trans_off, tent_part_off, tent_wsum_off;  // tent rule buffers
+    size_t total;
 };
+// Sizes of the tent rule's buffers (all zero without it): wide points W, the
+// radius-major copy's rows x V per slice, tap chunks C.
+struct TentSizes {
+    size_t W = 0, rowsV = 0, C = 0;
+};
+// slices interleaved in the tent rule's radius-major copy
+constexpr int kTentSlices = 8;
 // Partial sinogram sums per slice for the monopole mass (one per reduction block).
 constexpr int kMassChunks = 64;
 // Row stride of a polar spectrum and tile-row width of the grid (complex values).
 int polar_stride(int M, int interp);
 int grid_width(int G);
-// tent_elems: complex values per slice of the tent rule's buffers (0 without it)
 WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int interp, bool monopole,
-                          size_t tent_elems);
+                          const TentSizes& tent);
 // wide points of the tent rule and their column table
 size_t tent_columns(int G, int V, std::vector<int2>& cols);
 // radial samples the wide points read
@@ -94,10 +102,6 @@ int tent_rows(int V, int M, double rscale);
 // angle taps per chunk of the tent pre-gather; the chunks of every slot
 constexpr int kTentChunk = 32;
 void tent_chunks(int V, const std::vector<int2>& cols, std::vector<int4>& chunks, std::vector<int>& coff);
-// complex values per slice of the tent rule's workspace (0 without it): the
-// slots' values, the radius-major copy of the samples they read, the chunk
-// partial sums; plus chunks real weight sums once
-size_t tent_workspace_elems(size_t W, int rows, int V, size_t chunks);
 
 struct ProjWsLayout {
     size_t grid_off, cart_off, polar_off, total;
@@ -159,7 +163,8 @@ struct GatherArgs {
 
 struct TentArgs {            // pre-gather of the wide points of the tent rule
     const float2* polar;     // [batch][V][S]
-    float2* trans;           // [batch][rows][V]: the first rows radial samples, radius-major
+    float2* trans;           // [batch/8][rows][V][8]: the first rows radial samples,
+                             // radius-major, 8 slices interleaved
     float2* patch;           // [batch][W]
     float2* part;            // [batch][C] chunk sums (conjugated for the lower half-plane)
     float* wsum;             // [C] chunk weight sums

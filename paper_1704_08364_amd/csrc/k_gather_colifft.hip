@@ -441,25 +441,34 @@ static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
 }
 
 // Tent rule, step 1: the first `rows` radial samples of every angle,
-// radius-major ([m][j]), through 32 x 32 tiles in LDS, so the angular sums of
-// step 2 walk contiguous memory.
-__global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a) {
-    __shared__ float2 tile[32][33];
-    const int s = blockIdx.z;
-    const int m0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    const float2* P = a.polar + (size_t)s * a.V * a.S + a.lead;
-    float2* T = a.trans + (size_t)s * a.rows * a.V;
+// radius-major with kTentSlices slices interleaved ([group][m][j][slice]), so
+// one angular tap of step 2 reads its slices' values as one contiguous 64-byte
+// run. A block moves a tile of 32 radii x 8 angles of every slice of its
+// group through LDS: reads are 32-sample runs of a polar row, writes are the
+// tile's 8 angles x 8 slices of each radius, one contiguous 512-byte run.
+// Slices past the batch are written as zeros.
+__global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a, int batch) {
+    __shared__ float2 tile[kTentSlices][8][33];
+    const int grp = blockIdx.z;
+    const int m0 = blockIdx.x * 32, j0 = blockIdx.y * 8;
 #pragma unroll
-    for (int k = 0; k < 32; k += 8) {
-        const int j = j0 + ty + k, m = m0 + tx;
-        if (j < a.V && m < a.rows) tile[ty + k][tx] = P[(size_t)j * a.S + m];
+    for (int it = 0; it < 8; ++it) {
+        const int idx = it * 256 + threadIdx.x;
+        const int m = idx & 31, j = (idx >> 5) & 7, k = idx >> 8;
+        const int s = grp * kTentSlices + k;
+        float2 v = make_float2(0.f, 0.f);
+        if (s < batch && j0 + j < a.V && m0 + m < a.rows)
+            v = a.polar[((size_t)s * a.V + j0 + j) * a.S + a.lead + m0 + m];
+        tile[k][j][m] = v;
     }
     __syncthreads();
+    float2* Tg = a.trans + (size_t)grp * a.rows * a.V * kTentSlices;
 #pragma unroll
-    for (int k = 0; k < 32; k += 8) {
-        const int m = m0 + ty + k, j = j0 + tx;
-        if (j < a.V && m < a.rows) T[(size_t)m * a.V + j] = tile[tx][ty + k];
+    for (int it = 0; it < 8; ++it) {
+        const int idx = it * 256 + threadIdx.x;
+        const int k = idx & 7, j = (idx >> 3) & 7, m = idx >> 6;
+        if (m0 + m < a.rows && j0 + j < a.V)
+            Tg[((size_t)(m0 + m) * a.V + j0 + j) * kTentSlices + k] = tile[k][j][m];
     }
 }
 
@@ -472,8 +481,6 @@ __global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a) {
 // result. Coordinates are formed in FP64 as on the host. Splitting the long
 // tap ranges near the origin (over a thousand taps) into chunks keeps every
 // thread's loop short.
-constexpr int kTentSlices = 8;
-
 __device__ __forceinline__ int tent_column(const TentArgs& a, int slot) {
     // the last column whose first slot is <= slot
     int lo = 0, hi = a.ncols - 1;
@@ -503,9 +510,10 @@ __global__ void __launch_bounds__(256) k_tent_chunks(TentArgs a, int batch) {
     const float g = (float)(r - (double)m0);
     const float w1r = m0 + 1 < a.rows ? g : 0.f;  // samples past M/2 are zero
     const float inv_h = (float)(1.0 / h);
-    const size_t sstride = (size_t)a.rows * a.V;
-    const float2* T0 = a.trans + (size_t)s0 * sstride + (size_t)m0 * a.V;
-    const float2* T1 = T0 + (m0 + 1 < a.rows ? a.V : 0);
+    // the slice group's radius-major rows m0 and m0 + 1, 8 slices per angle
+    const float4* T0 = reinterpret_cast<const float4*>(
+        a.trans + ((size_t)blockIdx.y * a.rows + m0) * a.V * kTentSlices);
+    const float4* T1 = T0 + (m0 + 1 < a.rows ? (size_t)a.V * (kTentSlices / 2) : 0);
     float ax[kTentSlices], ay[kTentSlices];
 #pragma unroll
     for (int k = 0; k < kTentSlices; ++k) ax[k] = ay[k] = 0.f;
@@ -519,10 +527,13 @@ __global__ void __launch_bounds__(256) k_tent_chunks(TentArgs a, int batch) {
         const float wy = flip ? -w : w;
         float2 v0[kTentSlices], v1[kTentSlices];
 #pragma unroll
-        for (int k = 0; k < kTentSlices; ++k) {
-            const size_t so = (size_t)(k < ns ? k : 0) * sstride + jj;
-            v0[k] = T0[so];
-            v1[k] = T1[so];
+        for (int k = 0; k < kTentSlices; k += 2) {
+            const float4 p0 = T0[(size_t)jj * (kTentSlices / 2) + k / 2];
+            const float4 p1 = T1[(size_t)jj * (kTentSlices / 2) + k / 2];
+            v0[k] = make_float2(p0.x, p0.y);
+            v0[k + 1] = make_float2(p0.z, p0.w);
+            v1[k] = make_float2(p1.x, p1.y);
+            v1[k + 1] = make_float2(p1.z, p1.w);
         }
 #pragma unroll
         for (int k = 0; k < kTentSlices; ++k) {
@@ -559,7 +570,9 @@ __global__ void __launch_bounds__(256) k_tent_reduce(TentArgs a) {
 hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStream_t st) {
     (void)p;
     if (a.W <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tent_transpose, dim3((a.rows + 31) / 32, (a.V + 31) / 32, batch), dim3(256), 0, st, a);
+    const int groups = (batch + kTentSlices - 1) / kTentSlices;
+    hipLaunchKernelGGL(k_tent_transpose, dim3((a.rows + 31) / 32, (a.V + 7) / 8, groups), dim3(256), 0, st, a,
+                       batch);
     if (a.C > 0)
         hipLaunchKernelGGL(k_tent_chunks, dim3((a.C + 255) / 256, (batch + kTentSlices - 1) / kTentSlices), dim3(256),
                            0, st, a, batch);

@@ -117,12 +117,6 @@ void tent_chunks(int V, const std::vector<int2>& cols, std::vector<int4>& chunks
     }
 }
 
-size_t tent_workspace_elems(size_t W, int rows, int V, size_t chunks) {
-    // per slice: W values, rows x V transposed samples, chunks partial sums;
-    // the chunks weight sums (float) fit in chunks/2 + 1 complex slots once
-    return W + (size_t)rows * (size_t)V + chunks + (chunks / 2 + 1);
-}
-
 int tent_rows(int V, int M, double rscale) {
     // wide points have rho < V/pi, so radial taps m0 <= floor(rscale V/pi) and m0 + 1
     const int rows = (int)std::floor(rscale * (double)V / M_PI) + 2;

@@ -256,9 +256,9 @@ def test_tent_workspace_adds_the_wide_points():
     # wide points: a^2 + b^2 < (V/pi)^2 over the half-plane columns a >= 0, plus
     # a radius-major copy of the radial samples they read (m <= floor(V/pi) + 1
     # at P_r = P_c), complex64 per slice
-    # and the pre-gather's chunk sums: each point's tap range floor(q-h)-1 ..
-    # ceil(q+h)+1 in chunks of 32, one complex sum per slice and one weight
-    # sum per chunk
+    # (8 slices interleaved, whole groups), and the pre-gather's chunk sums:
+    # each point's tap range floor(q-h)-1 .. ceil(q+h)+1 in chunks of 32, one
+    # complex sum per slice and one weight sum per chunk
     import math
     n, V = 256, 300
     R = V / np.pi
@@ -276,8 +276,14 @@ def test_tent_workspace_adds_the_wide_points():
             lo, hi = math.floor(q - h) - 1, math.ceil(q + h) + 1
             C += -(-(hi - lo + 1) // 32)
     rows = min(int(np.floor(R)) + 2, n)
-    for B in (1, 5):
+
+    def up(x):
+        return -(-x // 256) * 256
+
+    for B in (1, 5, 9):
         plain, _ = _params(n=n, V=V, max_batch=B)
         tent, _ = _params(n=n, V=V, max_batch=B, angular="tent")
         extra = P.query_workspace(tent, B) - P.query_workspace(plain, B)
-        assert extra == -(-B * (W + rows * V + C + C // 2 + 1) * 8 // 256) * 256
+        # values [B][W], the copy for whole groups of 8 slices, chunk sums [B][C], weight sums [C]
+        groups = -(-B // 8)
+        assert extra == up(B * W * 8) + up(groups * 8 * rows * V * 8) + up(B * C * 8) + up(C * 4)

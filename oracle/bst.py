@@ -267,11 +267,21 @@ def tent_taps(theta: np.ndarray, rho: np.ndarray, V: int):
     if np.any(wide):
         qw, hw, pw = q[wide], h[wide], idx[wide]
         lo = np.floor(qw - hw).astype(np.int64)
-        span = int(np.ceil(2.0 * hw.max())) + 2
-        raw = [(lo + k, np.maximum(0.0, 1.0 - np.abs(qw - (lo + k)) / hw)) for k in range(span)]
-        total = sum(w for _, w in raw)
-        for jc, w in raw:
-            ps.append(pw); js.append(jc); ws.append(w / total)
+        # taps lo .. lo + span - 1 cover |q - j| < h; points sorted by span, so
+        # step k only visits the points that still have a tap there
+        span = np.ceil(2.0 * hw).astype(np.int64) + 2
+        order = np.argsort(-span, kind="stable")
+        qw, hw, pw, lo, span = qw[order], hw[order], pw[order], lo[order], span[order]
+        raw = []
+        total = np.zeros(qw.size)
+        for k in range(int(span[0])):
+            n_act = int(np.searchsorted(-span, -k, side="left"))  # points with span > k
+            jc = lo[:n_act] + k
+            w = np.maximum(0.0, 1.0 - np.abs(qw[:n_act] - jc) / hw[:n_act])
+            raw.append((n_act, jc, w))
+            total[:n_act] += w
+        for n_act, jc, w in raw:
+            ps.append(pw[:n_act]); js.append(jc); ws.append(w / total[:n_act])
     p = np.concatenate(ps)
     jc = np.concatenate(js)
     w = np.concatenate(ws)

@@ -833,3 +833,28 @@ def test_tent_in_an_uneven_batch(P):
             ref = obst.backproject(batch.sino_view(sinos, i).double().cpu().numpy(), Geometry(n, v, n),
                                    obst.Params(angular="tent"))
             assert rel_l2(batch.img_view(imgs, i).cpu().numpy(), ref) <= 1e-5, (r, i)
+
+
+# --- the options at the benchmark's size ---------------------------------------
+
+@pytest.mark.parametrize("option", ["keys", "tent", "monopole"])
+def test_options_at_2048(P, option):
+    # one 2048 x 2048-angle slice per option against the oracle, in a plan
+    # sized for the 64-slice batch the benchmark times
+    N = V = 2048
+    kw, okw = {}, {}
+    if option == "keys":
+        kw, okw = dict(interp="keys", taper="keys"), dict(interp="keys", taper="keys")
+    elif option == "tent":
+        kw, okw = dict(angular="tent"), dict(angular="tent")
+    else:
+        kw, okw = dict(filter="none", monopole_width=0.4), dict(filter="none", monopole=0.4)
+    _say(f"[2048] {option}")
+    plan = P.Plan(N, V, max_batch=64, **kw)
+    sino = _sinos(2, V, N, 9100)
+    img = plan.backproject(sino)
+    torch.cuda.synchronize()
+    ref = obst.backproject(sino[1].double().cpu().numpy(), Geometry(N, V, N), obst.Params(**okw))
+    err = rel_l2(img[1].cpu().numpy(), ref)
+    _say(f"   rel-L2 {err:.2e}")
+    assert err <= 1e-5

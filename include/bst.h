@@ -215,10 +215,12 @@ bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float*
  * <g,g'> = dt sum_j w_j sum_i g g' (w_j = pi/V, or half the neighbour gap)
  *     <R f, g> = <f, B g>   (B = R* as in Section 1).
  * With a BST_FILTER_NONE plan R is a Fourier-slice (Eq. 1) projector; its
- * transposed gridding is exact as an adjoint but, where polar samples are denser
- * than Cartesian ones (radius < V/pi grid steps), it weights lattice-aligned
- * angles unevenly, so as a stand-alone Radon approximation it is coarse at low
- * frequencies. img: device float32 [batch][N][N]; sino: device float32
+ * transposed gridding is exact as an adjoint but, with BST_ANGULAR_LINEAR and
+ * where polar samples are denser than Cartesian ones (radius < V/pi grid
+ * steps), it weights lattice-aligned angles unevenly, so as a stand-alone Radon
+ * approximation it is coarse at low frequencies (several times the signal);
+ * with BST_ANGULAR_TENT it is within about 8 % of the Radon transform of a
+ * smooth object. img: device float32 [batch][N][N]; sino: device float32
  * [batch][V][n]. Needs a plan built with adjoint != 0 (else BST_E_UNSUPPORTED)
  * and a workspace of bst_workspace_size bytes. Deterministic (no atomics). */
 bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t batch,

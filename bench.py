@@ -232,7 +232,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--angles", type=int, default=2048)
-    ap.add_argument("--cpu-slices", type=int, default=2)
+    ap.add_argument("--cpu-slices", type=int, default=16,
+                    help="slices the FP64 oracle times (about 10-20 s on one host core)")
     ap.add_argument("--bf-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bruteforce", action="store_true")

@@ -876,3 +876,17 @@ def test_options_are_deterministic_and_batch_independent(P, option):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert torch.equal(a[9], alone[0])
+
+
+def test_tent_with_monopole_shift_and_apodisation(P):
+    # every pre- and post-pass of the plain-B path in one plan
+    N, V, B = 256, 240, 3
+    plan = P.Plan(N, V, filter="none", angular="tent", monopole_width=0.45, center_shift=1.75,
+                  apodization="hann", max_batch=B)
+    sino = _sinos(B, V, N, 4242)
+    img = plan.backproject(sino)
+    torch.cuda.synchronize()
+    prm = obst.Params(filter="none", angular="tent", monopole=0.45, center_shift=1.75, apod="hann")
+    for b in range(B):
+        ref = obst.backproject(sino[b].double().cpu().numpy(), Geometry(N, V, N), prm)
+        assert rel_l2(img[b].cpu().numpy(), ref) <= 1e-5

@@ -265,6 +265,14 @@ bst_status bst_destroy(bst_plan_t plan);
    "unknown status"). */
 const char* bst_status_string(int32_t status);
 
+/* Index checks of the checked build (compiled with BST_CHECKED, e.g. by
+ * `python -m paper_1704_08364_amd.build --checked`): *flags receives the bits
+ * of every kernel index check that failed since the last call (spectrum
+ * bits 0-7, gather 8-15, row 16-23, projector 24-31) and they are cleared; a
+ * failing index was replaced by 0, so the access stayed in bounds. Device
+ * `device`. Returns BST_E_UNSUPPORTED in ordinary builds. */
+bst_status bst_debug_check(int32_t device, uint32_t* flags);
+
 /* Text of the last HIP error seen by this thread ("" if none). */
 const char* bst_last_error_string(void);
 

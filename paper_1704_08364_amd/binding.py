@@ -63,6 +63,7 @@ SIGNATURES = {
     "bst_debug_spectrum": (C.c_int, [_P, _P, _P, _P, _I, _P, _S, _P]),
     "bst_destroy": (C.c_int, [_P]),
     "bst_status_string": (C.c_char_p, [C.c_int]),
+    "bst_debug_check": (C.c_int, [_I, C.POINTER(C.c_uint32)]),
     "bst_last_error_string": (C.c_char_p, []),
     "bst_event_create": (C.c_int, [C.POINTER(_P)]),
     "bst_event_destroy": (C.c_int, [_P]),

@@ -9,6 +9,10 @@ AddressSanitizer and UndefinedBehaviorSanitizer, linked with the ordinary
 kernel objects (device code is never instrumented). GCC's ASan runtime leaves
 the HSA allocator alone, so the library also runs kernels on a GPU. Load it
 in a process started with the variables of host_sanitizer_env().
+
+`--checked` (or build(checked=True)) builds _build_checked/libbst_checked.so
+with BST_CHECKED defined: the kernels verify their computed global indices and
+record failures for bst_debug_check (load it with BST_LIBRARY=<path>).
 """
 from __future__ import annotations
 
@@ -26,6 +30,8 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbst.so")
 SAN_DIR = os.path.join(HERE, "_build_hostsan")
 SAN_LIB = os.path.join(SAN_DIR, "libbst_hostsan.so")
+CHECK_DIR = os.path.join(HERE, "_build_checked")
+CHECK_LIB = os.path.join(CHECK_DIR, "libbst_checked.so")
 
 SOURCES = ["bst_api.cpp", "plan_adjoint.cpp", "batch.cpp", "k_spectrum.hip", "k_gather_colifft.hip", "k_row_c2r.hip",
            "k_bruteforce.hip", "k_project.hip"]
@@ -54,13 +60,15 @@ def _stale(obj: str, src: str) -> bool:
     return os.path.getmtime(obj) < max(os.path.getmtime(d) for d in deps)
 
 
-def _compile(src: str, sanitize: bool = False) -> str:
-    obj = os.path.join(SAN_DIR if sanitize else OBJDIR, os.path.splitext(src)[0] + ".o")
+def _compile(src: str, sanitize: bool = False, checked: bool = False) -> str:
+    objdir = SAN_DIR if sanitize else (CHECK_DIR if checked else OBJDIR)
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
     if sanitize:
         cmd = [GXX] + SAN_COMPILE + ["-c", os.path.join(CSRC, src), "-o", obj]
     else:
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        extra = ["-DBST_CHECKED"] if checked else []
+        cmd = [HIPCC] + COMMON + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -105,11 +113,11 @@ def host_sanitizer_env(log_dir: str | None = None) -> dict:
             "ASAN_OPTIONS": asan, "UBSAN_OPTIONS": ubsan}
 
 
-def build(verbose: bool = False, host_sanitize: bool = False) -> str:
+def build(verbose: bool = False, host_sanitize: bool = False, checked: bool = False) -> str:
     if shutil.which(HIPCC) is None and not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
-    out = SAN_LIB if host_sanitize else LIB
-    os.makedirs(SAN_DIR if host_sanitize else OBJDIR, exist_ok=True)
+    out = SAN_LIB if host_sanitize else (CHECK_LIB if checked else LIB)
+    os.makedirs(SAN_DIR if host_sanitize else (CHECK_DIR if checked else OBJDIR), exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
     if host_sanitize:
         # instrumented host sources + the ordinary kernel objects (rebuilt only when stale)
@@ -122,7 +130,7 @@ def build(verbose: bool = False, host_sanitize: bool = False) -> str:
         objs += [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in kern]
     else:
         with ThreadPoolExecutor(max_workers=jobs) as ex:
-            objs = list(ex.map(_compile, SOURCES))
+            objs = list(ex.map(lambda src: _compile(src, checked=checked), SOURCES))
     tmp = out + ".tmp"
     libs = [f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
     if host_sanitize:
@@ -139,5 +147,5 @@ def build(verbose: bool = False, host_sanitize: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True, host_sanitize="--host-sanitize" in sys.argv[1:])
+    build(verbose=True, host_sanitize="--host-sanitize" in sys.argv[1:], checked="--checked" in sys.argv[1:])
     sys.exit(0)

@@ -20,6 +20,12 @@
 #endif
 
 namespace bst {
+#ifdef BST_CHECKED
+unsigned check_flags_spectrum();
+unsigned check_flags_gather();
+unsigned check_flags_row();
+unsigned check_flags_project();
+#endif
 bool build_adjoint_tables(int V, int M, int G, double rscale, const std::vector<double>& theta, bool uniform,
                           int taps, const std::vector<int2>* tent_cols, std::vector<int>& off,
                           std::vector<uint2>& ent);
@@ -816,6 +822,25 @@ const char* bst_status_string(int32_t status) {
 }
 
 const char* bst_last_error_string(void) { return g_last_error.c_str(); }
+
+bst_status bst_debug_check(int32_t device, uint32_t* flags) {
+    if (!flags) return BST_E_NULL;
+    *flags = 0;
+#ifdef BST_CHECKED
+    DeviceGuard guard(device);
+    if (guard.err != hipSuccess) return device_fail(guard.err);
+    const unsigned parts[4] = {bst::check_flags_spectrum(), bst::check_flags_gather(), bst::check_flags_row(),
+                               bst::check_flags_project()};
+    for (int i = 0; i < 4; ++i) {
+        if (parts[i] == ~0u) return BST_E_DEVICE;
+        *flags |= (parts[i] & 0xFFu) << (8 * i);
+    }
+    return BST_OK;
+#else
+    (void)device;
+    return BST_E_UNSUPPORTED;
+#endif
+}
 
 bst_status bst_event_create(void** ev) {
     if (!ev) return BST_E_NULL;

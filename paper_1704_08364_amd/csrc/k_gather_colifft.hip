@@ -32,6 +32,7 @@
 //   Origin (0,0): dc_scale * sum_j dt*Y_j[0] (mean for FBP, kappa/dk * mean
 //   for plain B).
 #include "bst_internal.h"
+#include "bst_check.h"
 #include "fft_lds.h"
 
 namespace bst {
@@ -336,9 +337,10 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const bool wrap = __float_as_uint(pt[e].g) >> 31;
-                const unsigned o0 = (TENT && ((wide >> e) & 1u)) ? zoff : pt[e].o0;
+                const unsigned o0 = BST_IDX((TENT && ((wide >> e) & 1u)) ? zoff : pt[e].o0,
+                                            (unsigned)slice_bytes - 15u, 0);
                 pa[e] = load_pair(P, o0);
-                pb[e] = load_pair(P, o0 + (wrap ? wrap_bytes : row_bytes));
+                pb[e] = load_pair(P, BST_IDX(o0 + (wrap ? wrap_bytes : row_bytes), (unsigned)slice_bytes - 15u, 0));
             }
             if (lblock == 0) {
                 float acc = 0.f;
@@ -366,8 +368,10 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
 #pragma unroll
                 for (int i = 0; i < H; ++i) {
                     const Stencil& st = pt[h0 + i];
-                    const unsigned o0 = (TENT && ((wide >> (h0 + i)) & 1u)) ? zoff : st.o0;
-                    const unsigned o1 = o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes);
+                    const unsigned o0 = BST_IDX((TENT && ((wide >> (h0 + i)) & 1u)) ? zoff : st.o0,
+                                                (unsigned)slice_bytes - (TAPS == 4 ? 31u : 15u), 0);
+                    const unsigned o1 = BST_IDX(o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes),
+                                                (unsigned)slice_bytes - (TAPS == 4 ? 31u : 15u), 0);
                     pa[i] = load_pair(P, o0);
                     pb[i] = load_pair(P, o1);
                     if constexpr (TAPS == 4) {
@@ -398,7 +402,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
                 const float2* Pt = a.patch + (size_t)s * a.tent_w;
 #pragma unroll
                 for (int e = 0; e < E; ++e)
-                    if ((wide >> e) & 1u) v[e] = Pt[pt[e].o0 / sizeof(float2)];
+                    if ((wide >> e) & 1u) v[e] = Pt[BST_IDX(pt[e].o0 / (unsigned)sizeof(float2), (unsigned)a.tent_w, 1)];
             }
         }
         // origin: column 0, row 0 is thread j = 0's first point
@@ -414,7 +418,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
             for (int e = 0; e < E; ++e) {
                 const int y = jv + e * T;
                 const int p = (y + half_n) & (G - 1);
-                if (p < a.N) D[((size_t)(p >> 3) * a.GT + col) * 8 + (p & 7)] = v[e];
+                if (p < a.N) D[BST_IDX(((size_t)(p >> 3) * a.GT + col) * 8 + (p & 7), (size_t)a.N * a.GT, 2)] = v[e];
             }
         }
     }
@@ -458,7 +462,7 @@ __global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a, int batch) {
         const int s = grp * kTentSlices + k;
         float2 v = make_float2(0.f, 0.f);
         if (s < batch && j0 + j < a.V && m0 + m < a.rows)
-            v = a.polar[((size_t)s * a.V + j0 + j) * a.S + a.lead + m0 + m];
+            v = a.polar[((size_t)s * a.V + j0 + j) * a.S + BST_IDX(a.lead + m0 + m, a.S, 3)];
         tile[k][j][m] = v;
     }
     __syncthreads();
@@ -468,7 +472,8 @@ __global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a, int batch) {
         const int idx = it * 256 + threadIdx.x;
         const int k = idx & 7, j = (idx >> 3) & 7, m = idx >> 6;
         if (m0 + m < a.rows && j0 + j < a.V)
-            Tg[((size_t)(m0 + m) * a.V + j0 + j) * kTentSlices + k] = tile[k][j][m];
+            Tg[BST_IDX(((size_t)(m0 + m) * a.V + j0 + j) * kTentSlices + k, (size_t)a.rows * a.V * kTentSlices, 4)] =
+                tile[k][j][m];
     }
 }
 
@@ -497,7 +502,7 @@ __global__ void __launch_bounds__(256) k_tent_chunks(TentArgs a, int batch) {
     if (c >= a.C) return;
     const int ns = min(kTentSlices, batch - s0);
     const int4 ch = a.chunk[c];
-    const int col = tent_column(a, ch.x);
+    const int col = BST_IDX(tent_column(a, ch.x), a.ncols, 5);
     const int2 tc = a.cols[col];
     const int b = ch.x - tc.x - tc.y;
     const double rho = sqrt((double)col * col + (double)b * b);
@@ -506,7 +511,7 @@ __global__ void __launch_bounds__(256) k_tent_chunks(TentArgs a, int batch) {
     const double q = (lower ? phi + M_PI : phi) * ((double)a.V / M_PI);
     const double h = (double)a.V / (M_PI * rho);
     const double r = rho * a.rscale;
-    const int m0 = (int)floor(r);
+    const int m0 = BST_IDX((int)floor(r), a.rows, 6);
     const float g = (float)(r - (double)m0);
     const float w1r = m0 + 1 < a.rows ? g : 0.f;  // samples past M/2 are zero
     const float inv_h = (float)(1.0 / h);
@@ -523,7 +528,7 @@ __global__ void __launch_bounds__(256) k_tent_chunks(TentArgs a, int batch) {
         if (w <= 0.f) continue;
         total += w;
         const bool flip = jc < 0 || jc >= a.V;
-        const int jj = jc < 0 ? jc + a.V : (jc >= a.V ? jc - a.V : jc);
+        const int jj = BST_IDX(jc < 0 ? jc + a.V : (jc >= a.V ? jc - a.V : jc), a.V, 7);
         const float wy = flip ? -w : w;
         float2 v0[kTentSlices], v1[kTentSlices];
 #pragma unroll
@@ -606,3 +611,5 @@ hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipSt
 }
 
 }  // namespace bst
+
+BST_CHECK_MODULE(gather)

@@ -25,6 +25,7 @@
 //                  the neighbour gap) that makes R the weighted-inner-product
 //                  adjoint of B.
 #include "bst_internal.h"
+#include "bst_check.h"
 #include "fft_lds.h"
 
 namespace bst {
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(256) k_proj_gather(ProjGatherArgs a) {
     for (int k = 0; k < kProjSlices; ++k) soff[k] = (size_t)(k < ns ? k : ns - 1) * a.cart_stride;
     for (int e = a.off[idx]; e < e1; ++e) {
         const uint2 en = a.ent[e];
-        const size_t pidx = en.x & 0x7FFFFFFFu;
+        const size_t pidx = BST_IDX((size_t)(en.x & 0x7FFFFFFFu), a.cart_stride, 0);
         const float w = __uint_as_float(en.y);
         const float wy = (en.x >> 31) != 0u ? -w : w;  // conjugation folded into the weight
         float2 v[kProjSlices];
@@ -293,3 +294,5 @@ hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipS
 }
 
 }  // namespace bst
+
+BST_CHECK_MODULE(project)

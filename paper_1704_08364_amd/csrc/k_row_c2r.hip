@@ -12,6 +12,7 @@
 // that each wave's loads are contiguous.
 #include "bst_internal.h"
 #include "fft_lds.h"
+#include "bst_check.h"
 #include "monopole.h"
 
 namespace bst {
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
         const float4* tile = reinterpret_cast<const float4*>(
             a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * a.GT);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) q[e] = tile[(j + e * T) * 4 + ((row0 & 7) >> 1)];
+        for (int e = 0; e < 8; ++e) q[e] = tile[BST_IDX((j + e * T) * 4 + ((row0 & 7) >> 1), 4 * a.GT, 0)];
     };
     float4 q[8];
     load(g0, q);
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
         fft<LOGG, +1>(v, my, jv, twl);
 
         if (grp < groups) {
-            const int row0 = grp * (2 * C::F) + 2 * fid;
+            const int row0 = BST_IDX(grp * (2 * C::F) + 2 * fid, a.N - 1, 1);
             float* o0 = img_s + (size_t)row0 * a.N;
             float* o1 = o0 + a.N;
             const int half_n = a.N >> 1;
@@ -129,8 +130,8 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
                         b0 += mamp * scaled_bessel_i0(a.mono_rho_px * r0);
                         b1 += mamp * scaled_bessel_i0(a.mono_rho_px * r1);
                     }
-                    o0[c] = b0;
-                    o1[c] = b1;
+                    o0[BST_IDX(c, a.N, 2)] = b0;
+                    o1[BST_IDX(c, a.N, 2)] = b1;
                 }
             }
         }
@@ -170,3 +171,5 @@ hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipS
 }
 
 }  // namespace bst
+
+BST_CHECK_MODULE(row)

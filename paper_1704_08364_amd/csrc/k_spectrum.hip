@@ -20,6 +20,7 @@
 // turns them into the mass m and loads y[i] - m phi[i] in place of y[i].
 #include "bst_internal.h"
 #include "fft_lds.h"
+#include "bst_check.h"
 #include "monopole.h"
 
 // waves per SIMD the register allocation must leave room for
@@ -65,7 +66,7 @@ __global__ void __launch_bounds__(kMassThreads) k_mass(MassArgs a) {
             const long long itc = ok ? it : 0;
             const int l = (int)(itc >> logn);
             const int i = (int)(itc & (a.n - 1));
-            float v = base[(size_t)(c + l * kMassChunks) * a.n + i];
+            float v = base[BST_IDX((size_t)(c + l * kMassChunks) * a.n + i, (size_t)a.V * a.n, 0)];
             if constexpr (COUNTS) {
                 const float inv = 1.0f / (fs[i] - ds[i]);
                 v = -logf((v - ds[i]) * inv);
@@ -142,7 +143,7 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
         const float* yb = base + (size_t)(jb < a.V ? jb : 0) * a.n;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int i = bin_of(q);
+            const int i = BST_IDX(bin_of(q), a.n, 1);
             ra[q] = ya[i];
             rb[q] = yb[i];
         }
@@ -225,8 +226,9 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
             const float2 zc = my[lds_pad((M - m) & (M - 1))];
             const float2 ya2 = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[e]);
             const float2 yb2 = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[e]);
-            if (va) pa[a.lead + m] = ya2;
-            if (vb) pb[a.lead + m] = yb2;
+            const int slot = BST_IDX(a.lead + m, a.S, 2);
+            if (va) pa[slot] = ya2;
+            if (vb) pb[slot] = yb2;
             // the sample before 0 (cubic radial taps): Yh(-sigma) = conj Yh(sigma)
             if (a.lead && m == 1) {
                 if (va) pa[0] = make_float2(ya2.x, -ya2.y);
@@ -234,13 +236,14 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
             }
         }
         for (int z = jv; z < a.tail; z += T) {
-            if (va) pa[a.lead + M / 2 + z] = make_float2(0.f, 0.f);
-            if (vb) pb[a.lead + M / 2 + z] = make_float2(0.f, 0.f);
+            const int slot = BST_IDX(a.lead + M / 2 + z, a.S, 2);
+            if (va) pa[slot] = make_float2(0.f, 0.f);
+            if (vb) pb[slot] = make_float2(0.f, 0.f);
         }
         if (jv == 0) {
             const float2 z0 = my[0];
-            if (va) a.dc[(size_t)s * a.V + ja] = a.dt * z0.x;
-            if (vb) a.dc[(size_t)s * a.V + jb] = a.dt * z0.y;
+            if (va) a.dc[(size_t)s * a.V + BST_IDX(ja, a.V, 3)] = a.dt * z0.x;
+            if (vb) a.dc[(size_t)s * a.V + BST_IDX(jb, a.V, 3)] = a.dt * z0.y;
         }
         if (it + 1 < PAIRS) {
             __syncthreads();  // the next transform overwrites this LDS
@@ -314,3 +317,5 @@ hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hi
 }
 
 }  // namespace bst
+
+BST_CHECK_MODULE(spectrum)

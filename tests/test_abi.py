@@ -287,3 +287,11 @@ def test_tent_workspace_adds_the_wide_points():
         # values [B][W], the copy for whole groups of 8 slices, chunk sums [B][C], weight sums [C]
         groups = -(-B // 8)
         assert extra == up(B * W * 8) + up(groups * 8 * rows * V * 8) + up(B * C * 8) + up(C * 4)
+
+
+def test_debug_check_in_the_ordinary_build():
+    L = P.lib()
+    flags = C.c_uint32(7)
+    assert L.bst_debug_check(0, None) == 1
+    if os.path.basename(binding.LIB_PATH) == "libbst.so":
+        assert L.bst_debug_check(0, C.byref(flags)) == 8 and flags.value == 0

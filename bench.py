@@ -261,7 +261,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: slices are independent, so a multi-GPU "
               "run is the single-GPU path on a slab of slices per GPU (no collectives); "
-              "this build measures N=1.", file=sys.stderr)
+              "this benchmark measures one GPU (N=1).", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "volume":

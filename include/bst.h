@@ -56,7 +56,7 @@ typedef enum {
     BST_E_WORKSPACE = 5,    /* workspace smaller than bst_workspace_size          */
     BST_E_NOMEM = 6,        /* device allocation of the plan tables failed        */
     BST_E_DEVICE = 7,       /* a HIP runtime call failed                          */
-    BST_E_UNSUPPORTED = 8,  /* valid request this build does not implement        */
+    BST_E_UNSUPPORTED = 8,  /* valid request the library as compiled lacks       */
     BST_E_BATCH = 9,        /* batch < 0 or batch > max_batch                     */
     BST_E_ALIAS = 10        /* input, output or workspace overlap                 */
 } bst_status;

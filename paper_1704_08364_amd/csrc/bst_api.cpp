@@ -814,7 +814,7 @@ const char* bst_status_string(int32_t status) {
         case BST_E_WORKSPACE: return "workspace smaller than bst_workspace_size";
         case BST_E_NOMEM: return "device allocation failed";
         case BST_E_DEVICE: return "HIP runtime error";
-        case BST_E_UNSUPPORTED: return "not supported by this build";
+        case BST_E_UNSUPPORTED: return "not supported by the library as compiled";
         case BST_E_BATCH: return "batch out of range [0, max_batch]";
         case BST_E_ALIAS: return "input, output and workspace must not overlap";
     }

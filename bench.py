@@ -25,10 +25,11 @@ if ROOT not in sys.path:
 METRIC = "BST slices/s at N=2048, 2048 angles vs GPU brute-force BP at rel-L2 ≤ 1e-5"
 HBM_PEAK_GBS = 8000.0
 KERNELS = ("k_spectrum", "k_gather_colifft", "k_row_c2r")
+_KERNEL_HEADERS = ["fft_lds.h", "bst_internal.h", "bst_check.h", "monopole.h"]
 KERNEL_SOURCES = {
-    "k_spectrum": ["k_spectrum.hip", "fft_lds.h"],
-    "k_gather_colifft": ["k_gather_colifft.hip", "fft_lds.h"],
-    "k_row_c2r": ["k_row_c2r.hip", "fft_lds.h"],
+    "k_spectrum": ["k_spectrum.hip"] + _KERNEL_HEADERS,
+    "k_gather_colifft": ["k_gather_colifft.hip"] + _KERNEL_HEADERS,
+    "k_row_c2r": ["k_row_c2r.hip"] + _KERNEL_HEADERS,
 }
 
 

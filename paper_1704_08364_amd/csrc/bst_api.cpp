@@ -124,9 +124,12 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     ProjWsLayout L{};
     const size_t B = (size_t)batch;
+    const size_t plane = (size_t)(G / 2) * (size_t)G;
+    const size_t groups = (B + kProjInterleave - 1) / kProjInterleave;
     L.grid_off = 0;
     L.cart_off = up(B * (size_t)N * (size_t)(G / 2) * sizeof(float2));
-    L.polar_off = up(L.cart_off + B * (size_t)(G / 2) * (size_t)G * sizeof(float2));
+    L.cart8_off = up(L.cart_off + B * plane * sizeof(float2));
+    L.polar_off = up(L.cart8_off + groups * kProjInterleave * plane * sizeof(float2));
     L.total = up(L.polar_off + B * (size_t)V * (size_t)(M / 2) * sizeof(float2));
     return L;
 }
@@ -767,6 +770,7 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
     float2* cart = reinterpret_cast<float2*>(w + L.cart_off);
+    float2* cart8 = reinterpret_cast<float2*>(w + L.cart8_off);
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     const int cart_stride = (plan->G / 2) * plan->G;
 
@@ -777,8 +781,11 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     bst::ProjColArgs ca{grid, cart, plan->tw_G, plan->N};
     e = bst::launch_proj_cols(*plan, ca, batch, s);
     if (e != hipSuccess) return device_fail(e);
-    bst::ProjGatherArgs ga{cart, polar, plan->csr_off, plan->csr_ent, plan->V * (plan->M / 2), cart_stride,
-                           batch, 8};
+    const bst::ProjInterleaveArgs ia{cart, cart8, cart_stride, batch};
+    e = bst::launch_proj_interleave(ia, s);
+    if (e != hipSuccess) return device_fail(e);
+    bst::ProjGatherArgs ga{cart8, polar, plan->csr_off, plan->csr_ent, plan->V * (plan->M / 2), cart_stride,
+                           batch, bst::kProjInterleave};
     e = bst::launch_proj_gather(*plan, ga, s);
     if (e != hipSuccess) return device_fail(e);
     bst::ProjPolarArgs pa{polar, cart, sino, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,

@@ -88,6 +88,9 @@ struct TentSizes {
 };
 // slices interleaved in the tent rule's radius-major copy
 constexpr int kTentSlices = 8;
+// slices interleaved in the projector's Cartesian spectra (and summed together
+// by one thread of its transposed gather)
+constexpr int kProjInterleave = 8;
 // Partial sinogram sums per slice for the monopole mass (one per reduction block).
 constexpr int kMassChunks = 64;
 // Row stride of a polar spectrum and tile-row width of the grid (complex values).
@@ -104,7 +107,7 @@ constexpr int kTentChunk = 32;
 void tent_chunks(int V, const std::vector<int2>& cols, std::vector<int4>& chunks, std::vector<int>& coff);
 
 struct ProjWsLayout {
-    size_t grid_off, cart_off, polar_off, total;
+    size_t grid_off, cart_off, cart8_off, polar_off, total;
 };
 ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch);
 
@@ -214,13 +217,19 @@ struct ProjColArgs {       // grid^T columns -> Cartesian half-plane spectrum^T 
     int N;
 };
 struct ProjGatherArgs {    // CSR transposed gather -> polar^T [V][M/2]
-    const float2* cart;
+    const float2* cart;    // [batch/8][G/2 * G][8]: the spectra of 8 slices interleaved
     float2* polar;
     const int* off;
     const uint2* ent;
     int samples;           // V * M/2
     int cart_stride;       // G/2 * G complex per slice
     int batch, slices_per_block;
+};
+struct ProjInterleaveArgs {  // [batch][P] -> [batch/8][P][8]
+    const float2* cart;
+    float2* cart8;
+    int plane;             // P = G/2 * G
+    int batch;
 };
 struct ProjPolarArgs {     // polar^T rows -> sinogram rows
     const float2* polar;
@@ -237,6 +246,7 @@ struct ProjPolarArgs {     // polar^T rows -> sinogram rows
 hipError_t launch_proj_rows(const bst_plan_s& p, const ProjRowArgs& a, int batch, hipStream_t st);
 hipError_t launch_proj_cols(const bst_plan_s& p, const ProjColArgs& a, int batch, hipStream_t st);
 hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipStream_t st);
+hipError_t launch_proj_interleave(const ProjInterleaveArgs& a, hipStream_t st);
 hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int batch, hipStream_t st);
 
 hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st);

@@ -133,39 +133,56 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
     }
 }
 
-constexpr int kProjSlices = 8;
+// The spectra of kProjInterleave slices interleaved per Cartesian point
+// ([group][a * G + b][slice]), so one entry of the transposed gather reads its
+// slices' values as one contiguous 64-byte run. Each thread moves one point of
+// all slices of its group; slices past the batch become zeros.
+__global__ void __launch_bounds__(256) k_proj_interleave(ProjInterleaveArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int g = blockIdx.y;
+    if (p >= a.plane) return;
+    float2 v[kProjInterleave];
+#pragma unroll
+    for (int k = 0; k < kProjInterleave; ++k) {
+        const int s = g * kProjInterleave + k;
+        v[k] = s < a.batch ? a.cart[(size_t)s * a.plane + p] : make_float2(0.f, 0.f);
+    }
+    float4* out = reinterpret_cast<float4*>(a.cart8 + ((size_t)g * a.plane + p) * kProjInterleave);
+#pragma unroll
+    for (int k = 0; k < kProjInterleave; k += 2) out[k / 2] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
+}
 
+// Transposed gather: one thread per polar sample and group of kProjInterleave
+// slices sums the sample's list of Cartesian points (weights and conjugation
+// flags from the plan), in list order.
 __global__ void __launch_bounds__(256) k_proj_gather(ProjGatherArgs a) {
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= a.samples) return;
-    const int s0 = blockIdx.y * a.slices_per_block;
-    const int ns = min(a.slices_per_block, a.batch - s0);
-    float2 acc[kProjSlices];
+    const int s0 = blockIdx.y * kProjInterleave;
+    const int ns = min(kProjInterleave, a.batch - s0);
+    float2 acc[kProjInterleave];
 #pragma unroll
-    for (int k = 0; k < kProjSlices; ++k) acc[k] = make_float2(0.f, 0.f);
+    for (int k = 0; k < kProjInterleave; ++k) acc[k] = make_float2(0.f, 0.f);
     const int e1 = a.off[idx + 1];
-    const float2* base = a.cart + (size_t)s0 * a.cart_stride;
-    // slices past the batch re-read the last one (their sums are dropped), so
-    // that every load is unconditional and all of an entry's loads are in flight together
-    size_t soff[kProjSlices];
-#pragma unroll
-    for (int k = 0; k < kProjSlices; ++k) soff[k] = (size_t)(k < ns ? k : ns - 1) * a.cart_stride;
+    const float4* base = reinterpret_cast<const float4*>(a.cart + (size_t)blockIdx.y * a.cart_stride * kProjInterleave);
     for (int e = a.off[idx]; e < e1; ++e) {
         const uint2 en = a.ent[e];
-        const size_t pidx = BST_IDX((size_t)(en.x & 0x7FFFFFFFu), a.cart_stride, 0);
+        const size_t pidx = BST_IDX((size_t)(en.x & 0x7FFFFFFFu), (size_t)a.cart_stride, 0);
         const float w = __uint_as_float(en.y);
         const float wy = (en.x >> 31) != 0u ? -w : w;  // conjugation folded into the weight
-        float2 v[kProjSlices];
+        float4 q[kProjInterleave / 2];
 #pragma unroll
-        for (int k = 0; k < kProjSlices; ++k) v[k] = base[soff[k] + pidx];
+        for (int k = 0; k < kProjInterleave / 2; ++k) q[k] = base[pidx * (kProjInterleave / 2) + k];
 #pragma unroll
-        for (int k = 0; k < kProjSlices; ++k) {
-            acc[k].x = fmaf(w, v[k].x, acc[k].x);
-            acc[k].y = fmaf(wy, v[k].y, acc[k].y);
+        for (int k = 0; k < kProjInterleave / 2; ++k) {
+            acc[2 * k].x = fmaf(w, q[k].x, acc[2 * k].x);
+            acc[2 * k].y = fmaf(wy, q[k].y, acc[2 * k].y);
+            acc[2 * k + 1].x = fmaf(w, q[k].z, acc[2 * k + 1].x);
+            acc[2 * k + 1].y = fmaf(wy, q[k].w, acc[2 * k + 1].y);
         }
     }
 #pragma unroll
-    for (int k = 0; k < kProjSlices; ++k)
+    for (int k = 0; k < kProjInterleave; ++k)
         if (k < ns) a.polar[(size_t)(s0 + k) * a.samples + idx] = acc[k];
 }
 
@@ -288,8 +305,14 @@ hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int ba
 }
 hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipStream_t st) {
     (void)p;
-    const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
-    hipLaunchKernelGGL(k_proj_gather, dim3((a.samples + 255) / 256, chunks), dim3(256), 0, st, a);
+    const int groups = (a.batch + kProjInterleave - 1) / kProjInterleave;
+    hipLaunchKernelGGL(k_proj_gather, dim3((a.samples + 255) / 256, groups), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_proj_interleave(const ProjInterleaveArgs& a, hipStream_t st) {
+    const int groups = (a.batch + kProjInterleave - 1) / kProjInterleave;
+    hipLaunchKernelGGL(k_proj_interleave, dim3((a.plane + 255) / 256, groups), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -90,7 +90,7 @@ struct TentSizes {
 constexpr int kTentSlices = 8;
 // slices interleaved in the projector's Cartesian spectra (and summed together
 // by one thread of its transposed gather)
-constexpr int kProjInterleave = 8;
+constexpr int kProjInterleave = 16;
 // Partial sinogram sums per slice for the monopole mass (one per reduction block).
 constexpr int kMassChunks = 64;
 // Row stride of a polar spectrum and tile-row width of the grid (complex values).
@@ -217,7 +217,7 @@ struct ProjColArgs {       // grid^T columns -> Cartesian half-plane spectrum^T 
     int N;
 };
 struct ProjGatherArgs {    // CSR transposed gather -> polar^T [V][M/2]
-    const float2* cart;    // [batch/8][G/2 * G][8]: the spectra of 8 slices interleaved
+    const float2* cart;    // [batch/16][G/2 * G][16]: the spectra of 16 slices interleaved
     float2* polar;
     const int* off;
     const uint2* ent;
@@ -225,7 +225,7 @@ struct ProjGatherArgs {    // CSR transposed gather -> polar^T [V][M/2]
     int cart_stride;       // G/2 * G complex per slice
     int batch, slices_per_block;
 };
-struct ProjInterleaveArgs {  // [batch][P] -> [batch/8][P][8]
+struct ProjInterleaveArgs {  // [batch][P] -> [batch/16][P][16]
     const float2* cart;
     float2* cart8;
     int plane;             // P = G/2 * G

@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
 
 // The spectra of kProjInterleave slices interleaved per Cartesian point
 // ([group][a * G + b][slice]), so one entry of the transposed gather reads its
-// slices' values as one contiguous 64-byte run. Each thread moves one point of
+// slices' values as one contiguous 128-byte run (one cache line). Each thread moves one point of
 // all slices of its group; slices past the batch become zeros.
 __global__ void __launch_bounds__(256) k_proj_interleave(ProjInterleaveArgs a) {
     const int p = blockIdx.x * 256 + threadIdx.x;

@@ -139,7 +139,7 @@ def test_adjoint_workspace_covers_both_directions():
     p.adjoint = 1
     both = P.query_workspace(p, 8)
     # projector: grid [N][G/2] + Cartesian half plane [G/2][G] twice (as computed,
-    # and with 8 slices interleaved for the transposed gather, whole groups of 8)
+    # and with 16 slices interleaved for the transposed gather, whole groups of 16)
     # + polar [V][M/2], complex64
     N = V = 1024
     G = M = 2048
@@ -148,8 +148,8 @@ def test_adjoint_workspace_covers_both_directions():
         plain = P.query_workspace(p, B)
         p.adjoint = 1
         both = P.query_workspace(p, B)
-        groups = -(-B // 8)
-        proj = 8 * (B * N * G // 2 + B * G // 2 * G + groups * 8 * G // 2 * G + B * V * M // 2)
+        groups = -(-B // 16)
+        proj = 8 * (B * N * G // 2 + B * G // 2 * G + groups * 16 * G // 2 * G + B * V * M // 2)
         assert both >= plain and abs(both - max(plain, proj)) < 5 * 256
 
 
@@ -288,7 +288,7 @@ def test_tent_workspace_adds_the_wide_points():
     def up(x):
         return -(-x // 256) * 256
 
-    for B in (1, 5, 9):
+    for B in (1, 5, 9, 17):
         plain, _ = _params(n=n, V=V, max_batch=B)
         tent, _ = _params(n=n, V=V, max_batch=B, angular="tent")
         extra = P.query_workspace(tent, B) - P.query_workspace(plain, B)

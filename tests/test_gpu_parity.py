@@ -486,15 +486,35 @@ def test_gpu_adjoint_identity(P, filt):
 
 
 def test_project_deterministic_and_batch_independent(P):
-    N, V, B = 128, 100, 11
+    # 19 slices: one full group of interleaved slices and a ragged one
+    N, V, B = 128, 100, 19
     plan = P.Plan(N, V, max_batch=B, adjoint=True)
     f = torch.randn(B, N, N, device=DEV)
     a = plan.project(f).clone()
     b = plan.project(f).clone()
-    one = plan.project(f[B - 1:B].contiguous())
     torch.cuda.synchronize()
     assert torch.equal(a, b)
-    assert torch.equal(a[B - 1], one[0])
+    for s in (0, 15, 16, B - 1):
+        one = plan.project(f[s:s + 1].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(a[s], one[0])
+
+
+def test_project_two_slice_groups_match_oracle(P):
+    """A batch spanning two groups of interleaved slices, the second ragged,
+    against the oracle slice by slice."""
+    N, V, B = 64, 50, 19
+    _say(f"[project-groups] N={N} V={V} B={B}")
+    plan = P.Plan(N, V, max_batch=B, adjoint=True)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(19)
+    img = torch.randn(B, N, N, generator=g).to(DEV)
+    out = plan.project(img).cpu().numpy()
+    geom = Geometry(N, V, N)
+    prm = obst.Params()
+    for b in (0, 7, 15, 16, 18):
+        ref = obst.project(img[b].double().cpu().numpy(), geom, prm)
+        assert rel_l2(out[b], ref) <= 1e-5
 
 
 @pytest.mark.parametrize("interp", ["linear", "keys"])
@@ -764,6 +784,27 @@ def test_tent_backproject_and_project_match_oracle(P, N, V, filt, P_r, P_c):
         ep = rel_l2(proj[b].cpu().numpy(), obst.project(f[b].double().cpu().numpy(), geom, prm))
         _say(f"   slice {b}: backproject rel-L2 {eb:.2e}, project rel-L2 {ep:.2e}")
         assert eb <= 1e-5 and ep <= 1e-5
+
+
+def test_tent_slice_groups_match_oracle(P):
+    """The pre-gather's radius-major copy holds the slices in interleaved
+    groups: a batch spanning several groups, the last ragged, against the
+    oracle slice by slice, and each sampled slice equal to its own one-slice
+    run."""
+    N, V, B = 64, 64, 19
+    _say(f"[tent-groups] N={N} V={V} B={B}")
+    plan = P.Plan(N, V, angular="tent", max_batch=B)
+    sino = _sinos(B, V, N, 7019)
+    img = plan.backproject(sino).clone()
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    prm = obst.Params(angular="tent")
+    for b in (0, 9, 15, 16, 18):
+        ref = obst.backproject(sino[b].double().cpu().numpy(), geom, prm)
+        assert rel_l2(img[b].cpu().numpy(), ref) <= 1e-5
+        one = plan.backproject(sino[b:b + 1].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(img[b], one[0])
 
 
 def test_tent_projector_approximates_the_radon_transform(P):

@@ -155,8 +155,8 @@ bst_status bst_validate(const bst_params* p);
  * DC terms [batch][V] float32, the half-transformed grid [batch][N][G/2]
  * complex64 and, with a monopole width, partial sinogram sums [batch][64]
  * float32. With p->adjoint set, the size also covers bst_project: the grid,
- * the full Cartesian half-plane spectrum [batch][G/2][G], the same with 16 slices
- * interleaved per point ([ceil(batch/16)][G/2 * G][16]) and the polar adjoint
+ * the full Cartesian half-plane spectra with 16 slices interleaved per point
+ * ([ceil(batch/16)][G/2 * G][16]) and the polar adjoint
  * [batch][V][M/2] (complex64); the larger of the two needs is returned. */
 bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes);
 

@@ -127,8 +127,7 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
     const size_t plane = (size_t)(G / 2) * (size_t)G;
     const size_t groups = (B + kProjInterleave - 1) / kProjInterleave;
     L.grid_off = 0;
-    L.cart_off = up(B * (size_t)N * (size_t)(G / 2) * sizeof(float2));
-    L.cart8_off = up(L.cart_off + B * plane * sizeof(float2));
+    L.cart8_off = up(B * (size_t)N * (size_t)(G / 2) * sizeof(float2));
     L.polar_off = up(L.cart8_off + groups * kProjInterleave * plane * sizeof(float2));
     L.total = up(L.polar_off + B * (size_t)V * (size_t)(M / 2) * sizeof(float2));
     return L;
@@ -769,7 +768,6 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
-    float2* cart = reinterpret_cast<float2*>(w + L.cart_off);
     float2* cart8 = reinterpret_cast<float2*>(w + L.cart8_off);
     float2* polar = reinterpret_cast<float2*>(w + L.polar_off);
     const int cart_stride = (plan->G / 2) * plan->G;
@@ -778,17 +776,15 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     bst::TraceRange tr("bst_project");
     hipError_t e = bst::launch_proj_rows(*plan, ra, batch, s);
     if (e != hipSuccess) return device_fail(e);
-    bst::ProjColArgs ca{grid, cart, plan->tw_G, plan->N};
+    const int groups = (batch + bst::kProjInterleave - 1) / bst::kProjInterleave;
+    bst::ProjColArgs ca{grid, cart8, plan->tw_G, plan->N, batch, groups * (plan->G / 2)};
     e = bst::launch_proj_cols(*plan, ca, batch, s);
-    if (e != hipSuccess) return device_fail(e);
-    const bst::ProjInterleaveArgs ia{cart, cart8, cart_stride, batch};
-    e = bst::launch_proj_interleave(ia, s);
     if (e != hipSuccess) return device_fail(e);
     bst::ProjGatherArgs ga{cart8, polar, plan->csr_off, plan->csr_ent, plan->V * (plan->M / 2), cart_stride,
                            batch, bst::kProjInterleave};
     e = bst::launch_proj_gather(*plan, ga, s);
     if (e != hipSuccess) return device_fail(e);
-    bst::ProjPolarArgs pa{polar, cart, sino, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
+    bst::ProjPolarArgs pa{polar, cart8, sino, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,
                           cart_stride, (float)(plan->dt * plan->dc_scale), plan->proj_row};
     e = bst::launch_proj_polar(*plan, pa, batch, s);
     if (e != hipSuccess) return device_fail(e);

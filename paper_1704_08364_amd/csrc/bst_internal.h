@@ -107,7 +107,7 @@ constexpr int kTentChunk = 32;
 void tent_chunks(int V, const std::vector<int2>& cols, std::vector<int4>& chunks, std::vector<int>& coff);
 
 struct ProjWsLayout {
-    size_t grid_off, cart_off, cart8_off, polar_off, total;
+    size_t grid_off, cart8_off, polar_off, total;
 };
 ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch);
 
@@ -210,11 +210,13 @@ struct ProjRowArgs {       // image rows -> grid^T tiles
     int N;
     float scale;           // dk^2
 };
-struct ProjColArgs {       // grid^T columns -> Cartesian half-plane spectrum^T [G/2][G]
+struct ProjColArgs {       // grid^T columns -> Cartesian half-plane spectra, interleaved
     const float2* grid;
-    float2* cart;
+    float2* cart8;         // [batch/16][G/2 * G][16]
     const float2* tw;
     int N;
+    int batch;
+    int units;             // blocks: ceil(batch/16) * G/2 (slice group x column)
 };
 struct ProjGatherArgs {    // CSR transposed gather -> polar^T [V][M/2]
     const float2* cart;    // [batch/16][G/2 * G][16]: the spectra of 16 slices interleaved
@@ -225,15 +227,10 @@ struct ProjGatherArgs {    // CSR transposed gather -> polar^T [V][M/2]
     int cart_stride;       // G/2 * G complex per slice
     int batch, slices_per_block;
 };
-struct ProjInterleaveArgs {  // [batch][P] -> [batch/16][P][16]
-    const float2* cart;
-    float2* cart8;
-    int plane;             // P = G/2 * G
-    int batch;
-};
 struct ProjPolarArgs {     // polar^T rows -> sinogram rows
     const float2* polar;
-    const float2* cart;    // origin value per slice at cart[s * cart_stride]
+    const float2* cart;    // interleaved spectra: slice s's origin value at
+                           // cart[(s / 16) * cart_stride * 16 + s % 16]
     float* sino;
     const float* taper;
     const float2* kc;      // dt * K[m] * A * phase (conjugated on use)
@@ -246,7 +243,6 @@ struct ProjPolarArgs {     // polar^T rows -> sinogram rows
 hipError_t launch_proj_rows(const bst_plan_s& p, const ProjRowArgs& a, int batch, hipStream_t st);
 hipError_t launch_proj_cols(const bst_plan_s& p, const ProjColArgs& a, int batch, hipStream_t st);
 hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipStream_t st);
-hipError_t launch_proj_interleave(const ProjInterleaveArgs& a, hipStream_t st);
 hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int batch, hipStream_t st);
 
 hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st);

@@ -8,13 +8,14 @@
 //                  columns twice); written to 8-row tiles [N/8][G/2][8].
 //   k_proj_cols    transpose of the column inverse DFT + crop: each column's N
 //                  rows are zero-embedded at (p - N/2) mod G and forward
-//                  transformed; the full half-plane spectrum is written
-//                  [G/2][G] (column-major).
+//                  transformed; the full half-plane spectra are written
+//                  column-major with 16 slices interleaved per point
+//                  ([batch/16][G/2 * G][16]).
 //   k_proj_gather  transpose of the bilinear polar -> Cartesian gather: every
 //                  polar sample sums, in a fixed order, the Cartesian values
 //                  whose stencil contains it (CSR lists built once per plan,
 //                  weight and conjugation per entry). No atomics, so the result
-//                  is bitwise reproducible. Each list is read once for up to 8
+//                  is bitwise reproducible. Each list is read once for up to 16
 //                  slices.
 //   k_proj_polar   transpose of P4..P1: the conjugate of the complex radial
 //                  weight dt*K[m]*A*phase (plus the origin rule's share
@@ -91,65 +92,60 @@ template <int LOGG>
 struct ProjColCfg {
     static constexpr int G = 1 << LOGG;
     static constexpr int T = G / 16;
-    static constexpr int F0 = T >= 512 ? 1 : 512 / T;
-    static constexpr int F = F0 > G / 2 ? G / 2 : F0;   // columns per block
-    static constexpr int WG = F * T;
+    static constexpr int SL0 = T >= 512 ? 1 : 512 / T;
+    static constexpr int SL = SL0 > kProjInterleave ? kProjInterleave : SL0;  // slices per round
+    static constexpr int ROUNDS = kProjInterleave / SL;
+    static constexpr int WG = SL * T;
 };
 
+// One block per Cartesian column a and group of kProjInterleave slices: the
+// group's slices are transformed SL at a time, and each result is stored
+// straight into the interleaved layout [group][a * G + b][slot] that the
+// transposed gather reads. The SL threads that hold point b of one round
+// write adjacent slots of one 128-byte line, and the block completes each of
+// its lines within a few rounds, so the partial writes meet in L2. Logical
+// blocks are spread XCD-contiguously, so neighbouring columns (which share
+// the input tiles' lines) share an L2. Slots past the batch are written as
+// zeros.
 template <int LOGG>
 __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs a) {
     using C = ProjColCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
-    __shared__ float2 lds[C::F * (FftShape<LOGG>::LDS + 8)];
-    const int fid = threadIdx.x % C::F;
-    const int j = threadIdx.x / C::F;
+    __shared__ float2 lds[C::SL * (FftShape<LOGG>::LDS + 8)];
+    const int unit = xcd_contiguous(blockIdx.x, gridDim.x);
+    if (unit >= a.units) return;  // whole block, before any barrier
+    const int grp = unit / (G / 2), col = unit % (G / 2);
+    const int fid = threadIdx.x % C::SL;
+    const int j = threadIdx.x / C::SL;
     float2* my = lds + fid * (FftShape<LOGG>::LDS + 8);
-    const int col = blockIdx.x * C::F + fid;
-    const bool live = col < G / 2;
-    const int s = blockIdx.y;
-    const float2* D = a.grid + (size_t)s * a.N * (G / 2);
     const int half_n = a.N >> 1;
-
-    // loads first, branch-free: rows outside the crop (and columns past the
-    // last) read a valid element and are replaced by zero
-    const int cc = live ? col : 0;
-    float2 v[16];
+    float2* out = a.cart8 + ((size_t)grp * (G / 2) * G + (size_t)col * G) * kProjInterleave;
+#pragma unroll 1
+    for (int r = 0; r < C::ROUNDS; ++r) {
+        const int slot = r * C::SL + fid;
+        const int s = grp * kProjInterleave + slot;
+        const bool live = s < a.batch;
+        // loads first, branch-free: rows outside the crop (and slots past the
+        // batch) read a valid element and are replaced by zero
+        const float2* D = a.grid + (size_t)(live ? s : 0) * a.N * (G / 2);
+        float2 v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int p = (j + e * T + half_n) & (G - 1);
-        const int pp = p < a.N ? p : 0;
-        v[e] = D[((size_t)(pp >> 3) * (G / 2) + cc) * 8 + (pp & 7)];
+        for (int e = 0; e < 16; ++e) {
+            const int p = (j + e * T + half_n) & (G - 1);
+            const int pp = p < a.N ? p : 0;
+            v[e] = D[((size_t)(pp >> 3) * (G / 2) + col) * 8 + (pp & 7)];
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int p = (j + e * T + half_n) & (G - 1);
+            if (!(live && p < a.N)) v[e] = make_float2(0.f, 0.f);
+        }
+        fft<LOGG, -1>(v, my, j, a.tw);
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            out[BST_IDX((size_t)(j + e * T) * kProjInterleave + slot, (size_t)G * kProjInterleave, 1)] = v[e];
+        __syncthreads();
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int p = (j + e * T + half_n) & (G - 1);
-        if (!(live && p < a.N)) v[e] = make_float2(0.f, 0.f);
-    }
-    fft<LOGG, -1>(v, my, j, a.tw);
-    if (live) {
-        float2* out = a.cart + (size_t)s * (G / 2) * G + (size_t)col * G;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) out[j + e * T] = v[e];
-    }
-}
-
-// The spectra of kProjInterleave slices interleaved per Cartesian point
-// ([group][a * G + b][slice]), so one entry of the transposed gather reads its
-// slices' values as one contiguous 128-byte run (one cache line). Each thread moves one point of
-// all slices of its group; slices past the batch become zeros.
-__global__ void __launch_bounds__(256) k_proj_interleave(ProjInterleaveArgs a) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    const int g = blockIdx.y;
-    if (p >= a.plane) return;
-    float2 v[kProjInterleave];
-#pragma unroll
-    for (int k = 0; k < kProjInterleave; ++k) {
-        const int s = g * kProjInterleave + k;
-        v[k] = s < a.batch ? a.cart[(size_t)s * a.plane + p] : make_float2(0.f, 0.f);
-    }
-    float4* out = reinterpret_cast<float4*>(a.cart8 + ((size_t)g * a.plane + p) * kProjInterleave);
-#pragma unroll
-    for (int k = 0; k < kProjInterleave; k += 2) out[k / 2] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
 // Transposed gather: one thread per polar sample and group of kProjInterleave
@@ -208,7 +204,8 @@ __global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG) k_proj_polar(ProjPolar
     const bool va = ja < a.V, vb = jb < a.V;
     const float2* PA = a.polar + ((size_t)s * a.V + (va ? ja : 0)) * (M / 2);
     const float2* PB = a.polar + ((size_t)s * a.V + (vb ? jb : 0)) * (M / 2);
-    const float dct = a.dc_dt * a.cart[(size_t)s * a.cart_stride].x;
+    const float dct =
+        a.dc_dt * a.cart[(size_t)(s / kProjInterleave) * a.cart_stride * kProjInterleave + s % kProjInterleave].x;
 
     // loads first, branch-free: sample m = |k| of both projections and its
     // weight; k = M/2 reads m = 0 and is replaced by zero
@@ -283,7 +280,8 @@ static hipError_t proj_rows_t(const ProjRowArgs& a, int batch, hipStream_t st) {
 template <int LOGG>
 static hipError_t proj_cols_t(const ProjColArgs& a, int batch, hipStream_t st) {
     using C = ProjColCfg<LOGG>;
-    hipLaunchKernelGGL(k_proj_cols<LOGG>, dim3((C::G / 2 + C::F - 1) / C::F, batch), dim3(C::WG), 0, st, a);
+    (void)batch;
+    hipLaunchKernelGGL(k_proj_cols<LOGG>, dim3(a.units), dim3(C::WG), 0, st, a);
     return hipGetLastError();
 }
 template <int LOGM>
@@ -307,12 +305,6 @@ hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipS
     (void)p;
     const int groups = (a.batch + kProjInterleave - 1) / kProjInterleave;
     hipLaunchKernelGGL(k_proj_gather, dim3((a.samples + 255) / 256, groups), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_proj_interleave(const ProjInterleaveArgs& a, hipStream_t st) {
-    const int groups = (a.batch + kProjInterleave - 1) / kProjInterleave;
-    hipLaunchKernelGGL(k_proj_interleave, dim3((a.plane + 255) / 256, groups), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

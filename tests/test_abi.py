@@ -134,22 +134,22 @@ def test_plan_without_device_fails_cleanly():
 
 
 def test_adjoint_workspace_covers_both_directions():
-    p, _ = _params(n=1024, V=1024, max_batch=8)
+    p, _ = _params(n=1024, V=1024, max_batch=17)
     plain = P.query_workspace(p, 8)
     p.adjoint = 1
     both = P.query_workspace(p, 8)
-    # projector: grid [N][G/2] + Cartesian half plane [G/2][G] twice (as computed,
-    # and with 16 slices interleaved for the transposed gather, whole groups of 16)
-    # + polar [V][M/2], complex64
+    # projector: grid [N][G/2] + Cartesian half plane [G/2][G] with 16 slices
+    # interleaved for the transposed gather (whole groups of 16) + polar [V][M/2],
+    # complex64
     N = V = 1024
     G = M = 2048
-    for B in (8, 3):
+    for B in (8, 3, 17):
         p.adjoint = 0
         plain = P.query_workspace(p, B)
         p.adjoint = 1
         both = P.query_workspace(p, B)
         groups = -(-B // 16)
-        proj = 8 * (B * N * G // 2 + B * G // 2 * G + groups * 16 * G // 2 * G + B * V * M // 2)
+        proj = 8 * (B * N * G // 2 + groups * 16 * G // 2 * G + B * V * M // 2)
         assert both >= plain and abs(both - max(plain, proj)) < 5 * 256
 
 

@@ -781,7 +781,7 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     e = bst::launch_proj_cols(*plan, ca, batch, s);
     if (e != hipSuccess) return device_fail(e);
     bst::ProjGatherArgs ga{cart8, polar, plan->csr_off, plan->csr_ent, plan->V * (plan->M / 2), cart_stride,
-                           batch, bst::kProjInterleave};
+                           batch, plan->M / 2};
     e = bst::launch_proj_gather(*plan, ga, s);
     if (e != hipSuccess) return device_fail(e);
     bst::ProjPolarArgs pa{polar, cart8, sino, plan->taper, plan->kc, plan->tw_M, plan->n, plan->V,

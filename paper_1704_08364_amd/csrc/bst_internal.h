@@ -225,7 +225,8 @@ struct ProjGatherArgs {    // CSR transposed gather -> polar^T [V][M/2]
     const uint2* ent;
     int samples;           // V * M/2
     int cart_stride;       // G/2 * G complex per slice
-    int batch, slices_per_block;
+    int batch;
+    int half_m;            // M/2 radial samples per angle
 };
 struct ProjPolarArgs {     // polar^T rows -> sinogram rows
     const float2* polar;

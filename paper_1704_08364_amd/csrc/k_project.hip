@@ -16,7 +16,8 @@
 //                  whose stencil contains it (CSR lists built once per plan,
 //                  weight and conjugation per entry). No atomics, so the result
 //                  is bitwise reproducible. Each list is read once for up to 16
-//                  slices.
+//                  slices; blocks take 16 x 16 tiles of (angle, radius),
+//                  spread XCD-contiguously.
 //   k_proj_polar   transpose of P4..P1: the conjugate of the complex radial
 //                  weight dt*K[m]*A*phase (plus the origin rule's share
 //                  on m = 0), the transpose of the real DFT as the inverse FFT
@@ -150,10 +151,19 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
 
 // Transposed gather: one thread per polar sample and group of kProjInterleave
 // slices sums the sample's list of Cartesian points (weights and conjugation
-// flags from the plan), in list order.
-__global__ void __launch_bounds__(256) k_proj_gather(ProjGatherArgs a) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= a.samples) return;
+// flags from the plan), in list order. A block takes a tile of
+// kProjTileAngles x kProjTileRadii samples, and the tiles, radius-fastest,
+// are spread XCD-contiguously: the samples of neighbouring angles and radii
+// share stencil points, so a tile and its successors on one XCD find them in
+// that XCD's L2.
+constexpr int kProjTileAngles = 16, kProjTileRadii = 16;
+__global__ void __launch_bounds__(kProjTileAngles * kProjTileRadii) k_proj_gather(ProjGatherArgs a) {
+    const int tiles_m = (a.half_m + kProjTileRadii - 1) / kProjTileRadii;
+    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int m = (tile % tiles_m) * kProjTileRadii + threadIdx.x % kProjTileRadii;
+    const int j = (tile / tiles_m) * kProjTileAngles + threadIdx.x / kProjTileRadii;
+    if (m >= a.half_m || j * a.half_m >= a.samples) return;
+    const int idx = j * a.half_m + m;
     const int s0 = blockIdx.y * kProjInterleave;
     const int ns = min(kProjInterleave, a.batch - s0);
     float2 acc[kProjInterleave];
@@ -304,7 +314,10 @@ hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int ba
 hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipStream_t st) {
     (void)p;
     const int groups = (a.batch + kProjInterleave - 1) / kProjInterleave;
-    hipLaunchKernelGGL(k_proj_gather, dim3((a.samples + 255) / 256, groups), dim3(256), 0, st, a);
+    const int angles = a.samples / a.half_m;
+    const int tiles = ((a.half_m + kProjTileRadii - 1) / kProjTileRadii) *
+                      ((angles + kProjTileAngles - 1) / kProjTileAngles);
+    hipLaunchKernelGGL(k_proj_gather, dim3(tiles, groups), dim3(kProjTileAngles * kProjTileRadii), 0, st, a);
     return hipGetLastError();
 }
 

@@ -509,7 +509,8 @@ __device__ __forceinline__ int tent_column(const TentArgs& a, int slot) {
 }
 
 __global__ void __launch_bounds__(256) k_tent_chunks(TentArgs a, int batch) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    // neighbouring chunks read the same angle taps: keep them on one XCD
+    const int c = xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     const int s0 = blockIdx.y * kTentSlices;
     if (c >= a.C) return;
     const int ns = min(kTentSlices, batch - s0);

@@ -102,12 +102,39 @@ struct ProjColCfg {
 // One block per Cartesian column a and group of kProjInterleave slices: the
 // group's slices are transformed SL at a time, and each result is stored
 // straight into the interleaved layout [group][a * G + b][slot] that the
-// transposed gather reads. The SL threads that hold point b of one round
-// write adjacent slots of one 128-byte line, and the block completes each of
-// its lines within a few rounds, so the partial writes meet in L2. Logical
+// transposed gather reads. Each thread takes two adjacent slots per pass, so
+// the SL threads that hold point b write 2 * SL adjacent slots of one
+// 128-byte line, and the block completes each of its lines within a few
+// passes, so the partial writes meet in L2. Logical
 // blocks are spread XCD-contiguously, so neighbouring columns (which share
 // the input tiles' lines) share an L2. Slots past the batch are written as
 // zeros.
+// Column transform of one slot of the group (zeros past the batch).
+template <int LOGG>
+__device__ __forceinline__ void proj_col_transform(const ProjColArgs& a, int grp, int col, int slot, int j,
+                                                   float2* my, float2 (&v)[16]) {
+    using C = ProjColCfg<LOGG>;
+    constexpr int G = C::G, T = C::T;
+    const int s = grp * kProjInterleave + slot;
+    const bool live = s < a.batch;
+    const int half_n = a.N >> 1;
+    // loads first, branch-free: rows outside the crop (and slots past the
+    // batch) read a valid element and are replaced by zero
+    const float2* D = a.grid + (size_t)(live ? s : 0) * a.N * (G / 2);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int p = (j + e * T + half_n) & (G - 1);
+        const int pp = p < a.N ? p : 0;
+        v[e] = D[((size_t)(pp >> 3) * (G / 2) + col) * 8 + (pp & 7)];
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int p = (j + e * T + half_n) & (G - 1);
+        if (!(live && p < a.N)) v[e] = make_float2(0.f, 0.f);
+    }
+    fft<LOGG, -1>(v, my, j, a.tw);
+}
+
 template <int LOGG>
 __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs a) {
     using C = ProjColCfg<LOGG>;
@@ -117,35 +144,37 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
     if (unit >= a.units) return;  // whole block, before any barrier
     const int grp = unit / (G / 2), col = unit % (G / 2);
     const int fid = threadIdx.x % C::SL;
-    const int j = threadIdx.x / C::SL;
+    const int j0 = threadIdx.x / C::SL;
     float2* my = lds + fid * (FftShape<LOGG>::LDS + 8);
-    const int half_n = a.N >> 1;
     float2* out = a.cart8 + ((size_t)grp * (G / 2) * G + (size_t)col * G) * kProjInterleave;
+    if constexpr (C::ROUNDS >= 2) {
+        // two rounds per pass: each thread transforms two adjacent slots and
+        // stores them as one 16-byte write
 #pragma unroll 1
-    for (int r = 0; r < C::ROUNDS; ++r) {
-        const int slot = r * C::SL + fid;
-        const int s = grp * kProjInterleave + slot;
-        const bool live = s < a.batch;
-        // loads first, branch-free: rows outside the crop (and slots past the
-        // batch) read a valid element and are replaced by zero
-        const float2* D = a.grid + (size_t)(live ? s : 0) * a.N * (G / 2);
+        for (int r = 0; r < C::ROUNDS; r += 2) {
+            // addresses are re-derived each pass from an opaque copy of the
+            // thread index rather than held in registers across passes
+            int j = j0;
+            asm volatile("" : "+v"(j));
+            const int slot = r * C::SL + 2 * fid;
+            float2 va[16], vb[16];
+            proj_col_transform<LOGG>(a, grp, col, slot, j, my, va);
+            __syncthreads();
+            proj_col_transform<LOGG>(a, grp, col, slot + 1, j, my, vb);
+            float4* o4 = reinterpret_cast<float4*>(out);
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                o4[BST_IDX(((size_t)(j + e * T) * kProjInterleave + slot) / 2, (size_t)G * kProjInterleave / 2, 1)] =
+                    make_float4(va[e].x, va[e].y, vb[e].x, vb[e].y);
+            __syncthreads();
+        }
+    } else {
+        const int slot = fid;
         float2 v[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int p = (j + e * T + half_n) & (G - 1);
-            const int pp = p < a.N ? p : 0;
-            v[e] = D[((size_t)(pp >> 3) * (G / 2) + col) * 8 + (pp & 7)];
-        }
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int p = (j + e * T + half_n) & (G - 1);
-            if (!(live && p < a.N)) v[e] = make_float2(0.f, 0.f);
-        }
-        fft<LOGG, -1>(v, my, j, a.tw);
+        proj_col_transform<LOGG>(a, grp, col, slot, j0, my, v);
 #pragma unroll
         for (int e = 0; e < 16; ++e)
-            out[BST_IDX((size_t)(j + e * T) * kProjInterleave + slot, (size_t)G * kProjInterleave, 1)] = v[e];
-        __syncthreads();
+            out[BST_IDX((size_t)(j0 + e * T) * kProjInterleave + slot, (size_t)G * kProjInterleave, 1)] = v[e];
     }
 }
 

@@ -438,6 +438,30 @@ PROJ_OPTION_CASES = [
 ]
 
 
+@pytest.mark.parametrize("N,V,filt,B,check", [
+    (1024, 64, "none", 17, (0, 16)),   # G = 2048: 4 slices per round, two passes of paired rounds
+    (2048, 32, "ramp", 1, (0,)),       # G = 4096: 2 slices per round, four passes
+])
+def test_project_large_grids_match_oracle(P, N, V, filt, B, check):
+    """The column kernel's multi-pass path (grids of 2048 and 4096 points per
+    side), with a ragged second slice group at 2048, against the oracle on
+    sampled slices."""
+    _say(f"[project-large] N={N} V={V} {filt} B={B}")
+    plan = P.Plan(N, V, filter=filt, max_batch=B, adjoint=True)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(N + V + B)
+    img = torch.randn(B, N, N, generator=g).to(DEV)
+    out = plan.project(img)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    prm = obst.Params(2, 2, filt)
+    for b in check:
+        ref = obst.project(img[b].double().cpu().numpy(), geom, prm)
+        err = rel_l2(out[b].cpu().numpy(), ref)
+        _say(f"   slice {b}: rel-L2 {err:.2e}")
+        assert err <= 1e-5
+
+
 @pytest.mark.parametrize("N,V,filt,P_r,P_c,interp,kind", PROJ_OPTION_CASES)
 def test_project_options_match_oracle(P, N, V, filt, P_r, P_c, interp, kind):
     """The projector for cubic radial interpolation and non-uniform angles

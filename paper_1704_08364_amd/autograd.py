@@ -88,14 +88,16 @@ def least_squares(plan: Plan, g: torch.Tensor, steps: int = 20, step: float = No
     if step is None:
         step = 1.0 / lipschitz(plan, shape)
     f = torch.zeros(shape, device=g.device, requires_grad=True)
+    # the losses stay on the device until the end: reading each one back
+    # would stall the stream once per step
     losses = []
     for _ in range(steps):
         r = project(f, plan) - g
         loss = (r * r).sum()
-        losses.append(float(loss))
+        losses.append(loss.detach())
         (grad,) = torch.autograd.grad(loss, f)
         with torch.no_grad():
-            f -= step * grad
+            f.add_(grad, alpha=-step)
     r = plan.project(f.detach()) - g
-    losses.append(float((r * r).sum()))
-    return f.detach(), losses
+    losses.append((r * r).sum())
+    return f.detach(), [float(x) for x in torch.stack(losses).cpu()]

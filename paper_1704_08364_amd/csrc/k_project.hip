@@ -99,16 +99,6 @@ struct ProjColCfg {
     static constexpr int WG = SL * T;
 };
 
-// One block per Cartesian column a and group of kProjInterleave slices: the
-// group's slices are transformed SL at a time, and each result is stored
-// straight into the interleaved layout [group][a * G + b][slot] that the
-// transposed gather reads. Each thread takes two adjacent slots per pass, so
-// the SL threads that hold point b write 2 * SL adjacent slots of one
-// 128-byte line, and the block completes each of its lines within a few
-// passes, so the partial writes meet in L2. Logical
-// blocks are spread XCD-contiguously, so neighbouring columns (which share
-// the input tiles' lines) share an L2. Slots past the batch are written as
-// zeros.
 // Column transform of one slot of the group (zeros past the batch).
 template <int LOGG>
 __device__ __forceinline__ void proj_col_transform(const ProjColArgs& a, int grp, int col, int slot, int j,
@@ -135,6 +125,17 @@ __device__ __forceinline__ void proj_col_transform(const ProjColArgs& a, int grp
     fft<LOGG, -1>(v, my, j, a.tw);
 }
 
+// One block per Cartesian column a and group of kProjInterleave slices: the
+// group's slices are transformed SL at a time, and each result is stored
+// straight into the interleaved layout [group][a * G + b][slot] that the
+// transposed gather reads. Where the group takes two or more rounds, each
+// thread takes two adjacent slots per pass, so the SL threads that hold
+// point b write 2 * SL adjacent slots of one 128-byte line, and the block
+// completes each of its lines within a few passes, so the partial writes
+// meet in L2 (small grids transform the whole group in one round). Logical
+// blocks are spread XCD-contiguously, so neighbouring columns (which share
+// the input tiles' lines) share an L2. Slots past the batch are written as
+// zeros.
 template <int LOGG>
 __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs a) {
     using C = ProjColCfg<LOGG>;

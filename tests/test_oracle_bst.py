@@ -153,6 +153,65 @@ def test_kaiser_bessel_with_zero_beta_is_no_taper():
     assert abs(w[g.n // 2] - 1.0) < 1e-15 and np.all(np.diff(w[g.n // 2:]) < 0)
 
 
+def _i0_series(x):
+    """I0(x) = sum_k (x/2)^(2k) / (k!)^2, summed term by term (independent of
+    the library routine the oracle calls)."""
+    return math.fsum((x / 2.0) ** (2 * k) / math.factorial(k) ** 2 for k in range(80))
+
+
+def test_kaiser_bessel_taper_closed_form():
+    # P1 option: w(t) = I0(beta sqrt(1 - t^2)) / I0(beta); at the detector edge
+    # t = -1 (bin 0) it is 1 / I0(beta), at t = 0 it is 1, and in between the
+    # square root sits inside the Bessel argument (not 1 - t^2 itself)
+    beta = 6.0
+    g = Geometry(64, 16, 64)
+    w = bst.taper(g, bst.Params(2, 2, "ramp", "kb", beta))
+    t = g.t()
+    assert t[0] == -1.0
+    assert abs(w[0] - 1.0 / _i0_series(beta)) <= 1e-14
+    assert abs(w[g.n // 2] - 1.0) <= 1e-15
+    for i in (3, 17, 29, 50):
+        expect = _i0_series(beta * math.sqrt(1.0 - t[i] ** 2)) / _i0_series(beta)
+        assert abs(w[i] - expect) <= 1e-13 * expect, (i, w[i], expect)
+    # the wrong reading I0(beta (1 - t^2)) differs by far more than that
+    i = 17
+    wrong = _i0_series(beta * (1.0 - t[i] ** 2)) / _i0_series(beta)
+    assert abs(w[i] - wrong) > 1e-3
+
+
+# A(x) at x = sigma / sigma_Nyquist = 0, 1/3, 1/2, 1, written out from the
+# window definitions: Shepp-Logan sin(pi x/2)/(pi x/2), Hann (1 + cos pi x)/2,
+# cosine cos(pi x/2).
+_WINDOW_VALUES = {
+    "ramlak": (1.0, 1.0, 1.0, 1.0),
+    "shepp": (1.0, 3.0 / math.pi, 2.0 * math.sqrt(2.0) / math.pi, 2.0 / math.pi),
+    "hann": (1.0, 0.75, 0.5, 0.0),
+    "cosine": (1.0, math.sqrt(3.0) / 2.0, math.sqrt(2.0) / 2.0, 0.0),
+}
+
+
+@pytest.mark.parametrize("apod", sorted(_WINDOW_VALUES))
+def test_apodization_windows_closed_form(apod):
+    x = np.array([0.0, 1.0 / 3.0, 0.5, 1.0])
+    got = bst.apodization(x, apod)
+    assert np.max(np.abs(got - np.array(_WINDOW_VALUES[apod]))) <= 1e-15
+
+
+@pytest.mark.parametrize("apod", sorted(_WINDOW_VALUES))
+@pytest.mark.parametrize("filt", ["ramp", "none"])
+def test_radial_weights_carry_the_window(apod, filt):
+    # P4: K[m] A(2m/M); RAMP K = 1, plain B K = 1/sigma_m = M dt / m, K[0] = 0
+    # there, and the Nyquist sample M/2 is dropped in both modes
+    M, dt = 96, 2.0 / 48
+    K = bst.radial_weights(M, dt, filt, apod)
+    A = _WINDOW_VALUES[apod]
+    for m, a in ((M // 6, A[1]), (M // 4, A[2])):
+        base = 1.0 if filt == "ramp" else M * dt / m
+        assert abs(K[m] - base * a) <= 1e-14 * base
+    assert K[M // 2] == 0.0
+    assert K[0] == (1.0 if filt == "ramp" else 0.0)
+
+
 def test_fbp_of_uniform_disk_level():
     N = 128
     sg = synth.Geometry(N, N, N)

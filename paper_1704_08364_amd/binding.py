@@ -57,6 +57,7 @@ SIGNATURES = {
     "bst_workspace_size": (C.c_int, [_P, _I, C.POINTER(_S)]),
     "bst_backproject": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
     "bst_backproject_timed": (C.c_int, [_P, _P, _P, _I, _P, _S, _P, C.POINTER(_P)]),
+    "bst_backproject_noalloc": (C.c_int, [_P, _P, _P, _I, _P]),
     "bst_backproject_counts": (C.c_int, [_P, _P, _P, _P, _P, _I, _P, _S, _P]),
     "bst_backproject_bruteforce": (C.c_int, [_P, _P, _P, _I, _P]),
     "bst_project": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
@@ -189,6 +190,30 @@ def _dev_tensor(t, name: str, dtype, shape_tail):
     return t
 
 
+def _out_tensor(out, name: str, shape, device):
+    """A caller-supplied output: float32, contiguous, exactly `shape`, on the
+    plan's device. The library writes shape-many elements and receives no size,
+    so anything smaller would be written past its end."""
+    import torch
+    _dev_tensor(out, name, torch.float32, shape[1:])
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(out.shape)}, expected {tuple(shape)}")
+    if out.device != device:
+        raise ValueError(f"{name} is on {out.device}, the plan's data on {device}")
+    return out
+
+
+def _keep_alive(stream, *tensors):
+    """Tensors the kernels use on `stream` while they may be freed or reused by
+    the caching allocator of another stream: tell the allocator."""
+    import torch
+    if stream is None or stream == torch.cuda.current_stream(stream.device):
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 class Event:
     """A HIP event made by the library (for per-kernel timing)."""
 
@@ -261,20 +286,22 @@ class Plan:
         B = s3.shape[0]
         if out is None:
             out = torch.empty(B, self.N, self.N, dtype=torch.float32, device=s3.device)
-        _dev_tensor(out, "out", torch.float32, (self.N, self.N))
+        o3 = _out_tensor(out if out.dim() == 3 or batched else out.unsqueeze(0), "out", (B, self.N, self.N),
+                         s3.device)
         if workspace is None:
             workspace = self.workspace(B)
+        _keep_alive(stream, s3, o3, workspace)
         sp = _stream_ptr(stream)
         if events is None:
-            st = lib().bst_backproject(self.handle, s3.data_ptr(), out.data_ptr(), B,
+            st = lib().bst_backproject(self.handle, s3.data_ptr(), o3.data_ptr(), B,
                                        workspace.data_ptr(), workspace.numel(), sp)
             _check(st, "bst_backproject")
         else:
             arr = (C.c_void_p * 4)(*[e.handle for e in events])
-            st = lib().bst_backproject_timed(self.handle, s3.data_ptr(), out.data_ptr(), B,
+            st = lib().bst_backproject_timed(self.handle, s3.data_ptr(), o3.data_ptr(), B,
                                              workspace.data_ptr(), workspace.numel(), sp, arr)
             _check(st, "bst_backproject_timed")
-        return out if batched else out[0]
+        return o3 if batched else o3[0]
 
     def backproject_counts(self, counts, flat, dark, out=None, workspace=None, stream=None):
         """BST of raw counts with per-slice flat/dark fields [B][n] (normalised on load)."""
@@ -287,13 +314,15 @@ class Plan:
             raise ValueError("flat and dark need one row of n values per slice")
         if out is None:
             out = torch.empty(B, self.N, self.N, dtype=torch.float32, device=c3.device)
-        _dev_tensor(out, "out", torch.float32, (self.N, self.N))
+        o3 = _out_tensor(out if out.dim() == 3 or batched else out.unsqueeze(0), "out", (B, self.N, self.N),
+                         c3.device)
         if workspace is None:
             workspace = self.workspace(B)
+        _keep_alive(stream, c3, flat, dark, o3, workspace)
         _check(lib().bst_backproject_counts(self.handle, c3.data_ptr(), flat.data_ptr(), dark.data_ptr(),
-                                            out.data_ptr(), B, workspace.data_ptr(), workspace.numel(),
+                                            o3.data_ptr(), B, workspace.data_ptr(), workspace.numel(),
                                             _stream_ptr(stream)), "bst_backproject_counts")
-        return out if batched else out[0]
+        return o3 if batched else o3[0]
 
     def bruteforce(self, sino, out=None, stream=None):
         import torch
@@ -301,10 +330,12 @@ class Plan:
         B = s3.shape[0]
         if out is None:
             out = torch.empty(B, self.N, self.N, dtype=torch.float32, device=s3.device)
-        _dev_tensor(out, "out", torch.float32, (self.N, self.N))
-        _check(lib().bst_backproject_bruteforce(self.handle, s3.data_ptr(), out.data_ptr(), B,
+        o3 = _out_tensor(out if out.dim() == 3 or batched else out.unsqueeze(0), "out", (B, self.N, self.N),
+                         s3.device)
+        _keep_alive(stream, s3, o3)
+        _check(lib().bst_backproject_bruteforce(self.handle, s3.data_ptr(), o3.data_ptr(), B,
                                                 _stream_ptr(stream)), "bst_backproject_bruteforce")
-        return out if batched else out[0]
+        return o3 if batched else o3[0]
 
     def debug_spectrum(self, sino, workspace=None, stream=None):
         """(complex64 [B][V][M/2] polar spectrum dt*K*Y, float32 [B][V] dt*Y[0])."""
@@ -315,6 +346,7 @@ class Plan:
         dc = torch.empty(B, self.V, dtype=torch.float32, device=s3.device)
         if workspace is None:
             workspace = self.workspace(B)
+        _keep_alive(stream, s3, spec, dc, workspace)
         _check(lib().bst_debug_spectrum(self.handle, s3.data_ptr(), spec.data_ptr(), dc.data_ptr(), B,
                                         workspace.data_ptr(), workspace.numel(), _stream_ptr(stream)),
                "bst_debug_spectrum")
@@ -327,11 +359,14 @@ class Plan:
         B = i3.shape[0]
         if out is None:
             out = torch.empty(B, self.V, self.n, dtype=torch.float32, device=i3.device)
+        o3 = _out_tensor(out if out.dim() == 3 or img.dim() == 3 else out.unsqueeze(0), "out",
+                         (B, self.V, self.n), i3.device)
         if workspace is None:
             workspace = self.workspace(B)
-        _check(lib().bst_project(self.handle, i3.data_ptr(), out.data_ptr(), B, workspace.data_ptr(),
+        _keep_alive(stream, i3, o3, workspace)
+        _check(lib().bst_project(self.handle, i3.data_ptr(), o3.data_ptr(), B, workspace.data_ptr(),
                                  workspace.numel(), _stream_ptr(stream)), "bst_project")
-        return out if img.dim() == 3 else out[0]
+        return o3 if img.dim() == 3 else o3[0]
 
 
 class Batch:

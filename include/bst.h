@@ -187,6 +187,20 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes);
 bst_status bst_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * bst_backproject, but the workspace is a static device array of the library,
+ * 256 MiB on every GPU the library runs on (held from the library's load until
+ * the process ends), so the call allocates nothing. The caller passes inputs
+ * and outputs as for bst_backproject. Batches whose workspace
+ * (bst_workspace_size) exceeds 256 MiB = 268435456 bytes are rejected with
+ * BST_E_WORKSPACE before any device work (at N = 2048, P_r = P_c = 2: up to 3
+ * slices per call; at N = 1024: up to 15; one slice at N = 4096 needs more). Every call on one GPU uses the same
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+bst_status bst_backproject_noalloc(bst_plan_t plan, const float* sino, float* img, int32_t batch,
+                                   void* stream);
+
 /* As bst_backproject, but the input is raw detector counts I [batch][V][n] with
  * per-slice flat (I0) and dark (D) fields [batch][n]; the spectrum kernel forms
  * y = -log((I - D) / (I0 - D)) as it loads (Section 1, "Normalization").

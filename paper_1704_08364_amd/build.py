@@ -33,7 +33,7 @@ SAN_LIB = os.path.join(SAN_DIR, "libbst_hostsan.so")
 CHECK_DIR = os.path.join(HERE, "_build_checked")
 CHECK_LIB = os.path.join(CHECK_DIR, "libbst_checked.so")
 
-SOURCES = ["bst_api.cpp", "plan_adjoint.cpp", "batch.cpp", "k_spectrum.hip", "k_gather_colifft.hip", "k_row_c2r.hip",
+SOURCES = ["bst_api.cpp", "plan_adjoint.cpp", "batch.cpp", "noalloc.hip", "k_spectrum.hip", "k_gather_colifft.hip", "k_row_c2r.hip",
            "k_bruteforce.hip", "k_project.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -696,6 +696,22 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
 
 }  // namespace
 
+namespace bst {
+size_t backproject_workspace_need(bst_plan_t plan, int32_t batch) {
+    if (!plan || batch <= 0) return 0;
+    return workspace_layout(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->prm.interp, plan->monopole,
+                            tent_sizes(plan))
+        .total;
+}
+
+bst_status backproject_in(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
+                          size_t ws_bytes, void* stream) {
+    return run_backproject(plan, sino, img, batch, ws, ws_bytes, stream, nullptr, false, nullptr, nullptr);
+}
+
+void set_last_error_text(const char* text) { g_last_error = text; }
+}  // namespace bst
+
 extern "C" {
 
 bst_status bst_backproject(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,

@@ -75,6 +75,13 @@ namespace bst {
 
 // record a HIP error for bst_last_error_string (calling thread)
 void set_last_error(hipError_t e);
+// record a message for bst_last_error_string (calling thread)
+void set_last_error_text(const char* text);
+// workspace bytes bst_backproject needs for `batch` slices (0 for batch <= 0)
+size_t backproject_workspace_need(bst_plan_t plan, int32_t batch);
+// bst_backproject with its argument checks, on a given workspace
+bst_status backproject_in(bst_plan_t plan, const float* sino, float* img, int32_t batch, void* ws,
+                          size_t ws_bytes, void* stream);
 
 struct WsLayout {
     size_t polar_off, dc_off, grid_off, mass_off;

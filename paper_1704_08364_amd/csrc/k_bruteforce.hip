@@ -5,99 +5,121 @@
 //   img[p][q] = sum_j w_j * sum_i y_j[i] Lambda(s - i),
 //   s = n/2 + ((q - N/2) cos theta_j + (p - N/2) sin theta_j) * d/dt.
 //
-// A block owns a 32x32 pixel tile; each thread four consecutive pixels of one
-// row. Angles are processed in chunks of 16: for each angle the block stages
-// in LDS the 64 detector samples that the tile's footprint can touch (zero
-// outside [0, n)), so the interpolation reads never leave LDS. The position
-// s is formed in FP64 once per thread and angle (s reaches ~n, where FP32
-// would leave ~1e-4 of error in the interpolation weight); the three
-// neighbouring pixels step from it in FP32 within a few units, where FP32
-// resolves the fraction to ~1e-7.
+// The kernel is bound by vector ALU issue (one interpolate-accumulate per
+// pixel and angle), so it is written to spend few instructions per pair:
+//   - a block owns a 64 x 32 pixel tile, each thread eight consecutive
+//     pixels of one row, so the per-angle position set-up (FP64) is shared by
+//     eight interpolations;
+//   - angles go in chunks of 16; for each angle the block stages in LDS the
+//     detector samples the tile's footprint can touch as pairs
+//     (w_j y[i], w_j (y[i+1] - y[i])) (zero outside [0, n)), so one 8-byte
+//     LDS read gives both the value and the slope, already weighted;
+//   - per pixel: position u = f + k cos (FP32, u > 0 by an offset of 8, so
+//     truncation is the floor), index and fraction, one LDS read, and
+//     acc += A + fract(u) D.
+// The position of the thread's first pixel is formed in FP64 (s reaches ~n,
+// where FP32 would leave ~1e-4 of error in the weight); the other seven step
+// from its fraction in FP32 within 16 units, where FP32 resolves the fraction
+// to ~1e-6.
 #include "bst_internal.h"
 
 namespace bst {
 
-constexpr int kTile = 32;
-constexpr int kChunk = 16;
-constexpr int kSeg = 64;
+constexpr int kTileX = 64;   // pixels per tile row (8 threads x 8 pixels)
+constexpr int kTileY = 32;   // tile rows
+constexpr int kPix = 8;      // consecutive pixels per thread
+constexpr int kChunk = 16;   // angles staged together
+// Detector samples staged per angle. The tile's positions s span at most
+// sqrt(63^2 + 31^2) < 70.3 bins (d/dt = 1: n_out == n_det), so floor(s) of
+// any pixel is at most 71 above floor(s_min); the segment starts kPix + 1
+// below floor(s_min) (the positions' offset, and FP32 rounding of the
+// first pixel's fraction to 1), so the entries read lie in [1, 81].
+constexpr int kSeg = 88;
 
 __global__ void __launch_bounds__(256) k_bruteforce(BfArgs a) {
-    __shared__ float seg[kChunk][kSeg];
+    __shared__ float2 seg[kChunk * kSeg];
     __shared__ int seg_start[kChunk];
+    __shared__ double2 dir[kChunk];  // (cos, sin) * d/dt of the chunk's angles
     const int tid = threadIdx.x;
     const int tx = tid & 7, ty = tid >> 3;
-    const int q0 = blockIdx.x * kTile, p0 = blockIdx.y * kTile;
+    const int q0 = blockIdx.x * kTileX, p0 = blockIdx.y * kTileY;
     const int s = blockIdx.z;
     const float* Y = a.sino + (size_t)s * a.V * a.n;
     const int half_n = a.N >> 1;
-    const double X0 = (double)(q0 + 4 * tx - half_n);
+    const double X0 = (double)(q0 + kPix * tx - half_n);
     const double Yp = (double)(p0 + ty - half_n);
-    const double cx0 = (double)(q0 - half_n), cx1 = (double)(q0 + kTile - 1 - half_n);
-    const double cy0 = (double)(p0 - half_n), cy1 = (double)(p0 + kTile - 1 - half_n);
+    const double cx0 = (double)(q0 - half_n), cx1 = (double)(q0 + kTileX - 1 - half_n);
+    const double cy0 = (double)(p0 - half_n), cy1 = (double)(p0 + kTileY - 1 - half_n);
     const double sc = 0.5 * (double)a.n;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    float acc[kPix];
+#pragma unroll
+    for (int k = 0; k < kPix; ++k) acc[k] = 0.f;
 
     for (int jc = 0; jc < a.V; jc += kChunk) {
         __syncthreads();
         if (tid < kChunk) {
             const int j = jc + tid;
             int st = 0;
+            double c = 0.0, sn = 0.0;
             if (j < a.V) {
-                const double c = a.c[j], sn = a.s[j];
+                c = a.c[j];
+                sn = a.s[j];
                 const double smin = sc + fmin(cx0 * c, cx1 * c) + fmin(cy0 * sn, cy1 * sn);
-                st = (int)floor(smin) - 2;
+                // kPix + 1 below the footprint: the positions carry an offset of kPix
+                st = (int)floor(smin) - 1 - kPix;
             }
             seg_start[tid] = st;
+            dir[tid] = make_double2(c, sn);
         }
         __syncthreads();
         for (int l = tid; l < kChunk * kSeg; l += 256) {
             const int c = l / kSeg, o = l - c * kSeg;
             const int j = jc + c;
             const int i = seg_start[c] + o;
-            seg[c][o] = (j < a.V && i >= 0 && i < a.n) ? Y[(size_t)j * a.n + i] : 0.f;
+            float y0 = 0.f, y1 = 0.f, w = 0.f;
+            if (j < a.V) {
+                w = a.w[j];
+                if (i >= 0 && i < a.n) y0 = Y[(size_t)j * a.n + i];
+                if (i + 1 >= 0 && i + 1 < a.n) y1 = Y[(size_t)j * a.n + i + 1];
+            }
+            seg[l] = make_float2(w * y0, w * (y1 - y0));
         }
         __syncthreads();
         const int cmax = min(kChunk, a.V - jc);
         for (int c = 0; c < cmax; ++c) {
-            const int j = jc + c;
-            const double cs = a.c[j], sn = a.s[j];
-            const float w = a.w[j];
-            const double sb = fma(X0, cs, fma(Yp, sn, sc));
+            const double2 cs = dir[c];
+            const double sb = fma(X0, cs.x, fma(Yp, cs.y, sc));
             const double fl = floor(sb);
-            const int ib = (int)fl - seg_start[c];
-            const float fb = (float)(sb - fl);
-            const float cf = (float)cs;
-            const float* row = seg[c];
-#define BST_BF_PIX(K, ACC)                                              \
-            {                                                           \
-                const float t = fmaf((float)(K), cf, fb);               \
-                const float ft = floorf(t);                             \
-                const int idx = ib + (int)ft;                           \
-                const float fr = t - ft;                                \
-                const float v0 = row[idx], v1 = row[idx + 1];           \
-                ACC = fmaf(w, fmaf(fr, v1 - v0, v0), ACC);              \
+            // this thread's entries: sample floor(s) of its first pixel sits at
+            // index base + kPix, pixel k's sample at base + (int)u
+            int base = c * kSeg + (int)fl - kPix - seg_start[c];
+            // formed once per angle (otherwise its terms are re-added per pixel)
+            asm volatile("" : "+v"(base));
+            const float fb = (float)(sb - fl) + (float)kPix;
+            const float cf = (float)cs.x;
+#pragma unroll
+            for (int k = 0; k < kPix; ++k) {
+                const float u = fmaf((float)k, cf, fb);  // in [1, 17)
+                const float2 e = seg[base + (int)u];
+                acc[k] += fmaf(__builtin_amdgcn_fractf(u), e.y, e.x);
             }
-            BST_BF_PIX(0, acc0)
-            BST_BF_PIX(1, acc1)
-            BST_BF_PIX(2, acc2)
-            BST_BF_PIX(3, acc3)
-#undef BST_BF_PIX
         }
     }
     const int p = p0 + ty;
-    const int q = q0 + 4 * tx;
     if (p < a.N) {
         float* o = a.img + ((size_t)s * a.N + p) * a.N;
-        if (q + 0 < a.N) o[q + 0] = acc0;
-        if (q + 1 < a.N) o[q + 1] = acc1;
-        if (q + 2 < a.N) o[q + 2] = acc2;
-        if (q + 3 < a.N) o[q + 3] = acc3;
+#pragma unroll
+        for (int k = 0; k < kPix; ++k) {
+            const int q = q0 + kPix * tx + k;
+            if (q < a.N) o[q] = acc[k];
+        }
     }
 }
 
 hipError_t launch_bruteforce(const bst_plan_s& p, const BfArgs& a, int batch, hipStream_t st) {
-    (void)p;
-    dim3 grid((a.N + kTile - 1) / kTile, (a.N + kTile - 1) / kTile, batch);
+    // the LDS segment length assumes one detector bin per pixel (d == dt)
+    if (p.n != p.N) return hipErrorInvalidValue;
+    dim3 grid((a.N + kTileX - 1) / kTileX, (a.N + kTileY - 1) / kTileY, batch);
     hipLaunchKernelGGL(k_bruteforce, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }

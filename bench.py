@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--input", choices=("phantom", "random"), default="phantom",
                     help="random: N(0,1) sinograms (for hardware-counter runs, where generating "
                          "phantoms with thousands of small kernels is slow)")
+    ap.add_argument("--gather-slices", type=int, default=0,
+                    help="slices per block of the gather kernel (0: the library's default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy a 1 GiB buffer first, to scale FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
@@ -296,7 +298,7 @@ def main():
         sino = synth.batch_sinograms(B, n, V, seed=170408366, device=dev)
     interp_kw = dict(taper="keys", interp="keys") if args.interp == "keys" else {}
     plan = P.Plan(n, V, max_batch=B, filter=args.filter, monopole_width=args.monopole, angular=args.angular,
-                  **interp_kw)
+                  gather_slices=args.gather_slices, **interp_kw)
     M, G = plan.M, plan.G
     ws = plan.workspace(B)
     img = torch.empty(B, N, N, dtype=torch.float32, device=dev)

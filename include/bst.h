@@ -133,6 +133,11 @@ typedef struct {
                                the transpose of bst_project). Adds a reduction kernel
                                and a [batch][64] float32 workspace array.                */
     int32_t angular;        /* bst_angular (step P5)                                     */
+    int32_t gather_slices;  /* slices each block of the step-P5/P6 gather kernel handles
+                               (its interpolation coordinates are computed once for
+                               them): 0 = the default (32), else a positive multiple
+                               of 2 up to 1024. Results do not depend on it (tuning
+                               and tests only); bst_batch_tune chooses it per class */
 } bst_params;
 
 typedef enum {
@@ -150,7 +155,8 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
 bst_status bst_validate(const bst_params* p);
 
 /* Workspace bytes for `batch` slices (host only, no plan needed).
- * bst_backproject: polar spectra [batch][V][M/2+2] complex64 ([batch][V][M/2+5]
+ * bst_backproject: polar spectra of whole groups of two slices, interleaved
+ * sample by sample, [ceil(batch/2)][V][M/2+2][2] complex64 ([..][V][M/2+5][2]
  * with BST_INTERP_KEYS: one leading and two more trailing slots), per-projection
  * DC terms [batch][V] float32, the half-transformed grid [batch][N][G/2]
  * complex64 and, with a monopole width, partial sinogram sums [batch][64]
@@ -264,9 +270,9 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
                             const int32_t* n_angles, bst_batch_t* out);
 bst_status bst_batch_workspace_size(bst_batch_t b, size_t* bytes);
 bst_status bst_batch_classes(bst_batch_t b, int32_t* n_classes);
-/* Time the gather kernel's variants (values per thread 8 or 16; 4 to 32 slices
- * per block) for every class on these inputs, keep the fastest, and drop any
- * captured graph. Synchronizes the stream. Outputs are overwritten. */
+/* Time the gather kernel's variants (4, 8, 16 or 32 slices per block) for
+ * every class on these inputs, keep the fastest, and drop any captured graph.
+ * Synchronizes the stream. Outputs are overwritten. */
 bst_status bst_batch_tune(bst_batch_t b, const float* sinos, const int64_t* sino_off, float* imgs,
                           const int64_t* img_off, void* ws, size_t ws_bytes, void* stream);
 bst_status bst_batch_backproject(bst_batch_t b, const float* sinos, const int64_t* sino_off, float* imgs,

@@ -45,6 +45,7 @@ class bst_params(C.Structure):
         ("max_batch", C.c_int32), ("device", C.c_int32), ("adjoint", C.c_int32),
         ("apodization", C.c_int32), ("center_shift", C.c_double),
         ("interp", C.c_int32), ("monopole_width", C.c_double), ("angular", C.c_int32),
+        ("gather_slices", C.c_int32),
     ]
 
 
@@ -124,13 +125,15 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
                 taper_beta: float = 8.0, max_batch: int = 1, device: int = 0,
                 angles: Optional[Sequence[float]] = None, adjoint: bool = False,
                 apodization: str = "ramlak", center_shift: float = 0.0, interp: str = "linear",
-                monopole_width: float = 0.0, angular: str = "linear"):
+                monopole_width: float = 0.0, angular: str = "linear", gather_slices: int = 0):
     """bst_params plus the ctypes array that backs `angles` (keep both alive).
     interp='keys' (cubic radial interpolation) pairs with taper='keys';
     monopole_width > 0 (filter='none' only) subtracts a Gaussian monopole of that
     width (units of t, detector in [-1, 1)) and adds its backprojection back;
     angular='tent' (uniform angles, linear interp) widens the angular kernel at
-    small radii, which makes plan.project a close Radon approximation."""
+    small radii, which makes plan.project a close Radon approximation.
+    gather_slices (0 = default) sets the slices per block of the gather kernel;
+    results do not depend on it."""
     p = bst_params()
     lib().bst_params_default(C.byref(p), n_det, n_angles, n_det if n_out is None else n_out)
     p.pad_radial = pad_radial
@@ -146,6 +149,7 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
     p.interp = INTERPS[interp] if isinstance(interp, str) else int(interp)
     p.monopole_width = monopole_width
     p.angular = ANGULARS[angular] if isinstance(angular, str) else int(angular)
+    p.gather_slices = int(gather_slices)
     keep = None
     if angles is not None:
         arr = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))

@@ -288,32 +288,26 @@ bst_status bst_batch_tune(bst_batch_t b, const float* sinos, const int64_t* sino
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return fail(e);
-    const int es[2] = {8, 16};
     const int slices[4] = {4, 8, 16, 32};
     for (auto& c : b->classes) {
         bst_plan_s& p = *c.plan;
         float best = 1e30f;
-        int best_e = p.gather_e, best_s = p.gather_slices;
-        for (int ei : es) {
-            for (int si : slices) {
-                p.gather_e = ei;
-                p.gather_slices = si;
-                e = launch_class(b, c, ws, s);  // warm
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventRecord(t0, s);
-                for (int r = 0; e == hipSuccess && r < 2; ++r) e = launch_class(b, c, ws, s);
-                if (e == hipSuccess) e = hipEventRecord(t1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(t1);
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                if (e != hipSuccess) break;
-                if (ms < best) {
-                    best = ms;
-                    best_e = ei;
-                    best_s = si;
-                }
+        int best_s = p.gather_slices;
+        for (int si : slices) {
+            p.gather_slices = si;
+            e = launch_class(b, c, ws, s);  // warm
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventRecord(t0, s);
+            for (int r = 0; e == hipSuccess && r < 2; ++r) e = launch_class(b, c, ws, s);
+            if (e == hipSuccess) e = hipEventRecord(t1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e != hipSuccess) break;
+            if (ms < best) {
+                best = ms;
+                best_s = si;
             }
         }
-        p.gather_e = best_e;
         p.gather_slices = best_s;
         if (e != hipSuccess) break;
     }

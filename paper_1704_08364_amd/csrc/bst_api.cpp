@@ -14,10 +14,6 @@
 #ifndef BST_GATHER_SLICES
 #define BST_GATHER_SLICES 32
 #endif
-// default values per thread of the gather kernel's column transform (8 or 16)
-#ifndef BST_GATHER_E
-#define BST_GATHER_E 8
-#endif
 
 namespace bst {
 #ifdef BST_CHECKED
@@ -102,7 +98,9 @@ WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int inte
     WsLayout L{};
     const size_t B = (size_t)batch;
     L.polar_off = 0;
-    const size_t polar = B * (size_t)V * (size_t)polar_stride(M, interp) * sizeof(float2);
+    // whole groups of kPolarSlices interleaved slices
+    const size_t BQ = (B + kPolarSlices - 1) / kPolarSlices * kPolarSlices;
+    const size_t polar = BQ * (size_t)V * (size_t)polar_stride(M, interp) * sizeof(float2);
     L.dc_off = up(L.polar_off + polar);
     const size_t dc = B * (size_t)V * sizeof(float);
     L.grid_off = up(L.dc_off + dc);
@@ -168,6 +166,7 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
     p->interp = BST_INTERP_LINEAR;
     p->monopole_width = 0.0;
     p->angular = BST_ANGULAR_LINEAR;
+    p->gather_slices = 0;
 }
 
 bst_status bst_validate(const bst_params* p) {
@@ -203,6 +202,8 @@ bst_status bst_validate(const bst_params* p) {
     }
     if (p->max_batch < 1) return BST_E_BATCH;
     if (p->device < 0) return BST_E_PARAM;
+    if (p->gather_slices < 0 || p->gather_slices > 1024 || p->gather_slices % bst::kPolarSlices != 0)
+        return BST_E_PARAM;
     if (p->angles) {
         double prev = -1.0;
         for (int j = 0; j < p->n_angles; ++j) {
@@ -312,8 +313,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->out_scale = (float)(pl->dk * pl->dk);
     pl->device = p->device;
     pl->adjoint = (p->adjoint != 0);
-    pl->gather_slices = BST_GATHER_SLICES;
-    pl->gather_e = BST_GATHER_E;
+    pl->gather_slices = p->gather_slices > 0 ? p->gather_slices : BST_GATHER_SLICES;
     pl->monopole = (p->monopole_width != 0.0);
     pl->tent = (p->angular == BST_ANGULAR_TENT);
 
@@ -629,9 +629,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
         if (e != hipSuccess) return device_fail(e);
     }
     if (spectrum_only) {
-        e = hipMemcpy2DAsync(spec_out, (plan->M / 2) * sizeof(float2), polar + plan->lead, plan->S * sizeof(float2),
-                             (plan->M / 2) * sizeof(float2), (size_t)batch * plan->V, hipMemcpyDeviceToDevice,
-                             s);
+        e = bst::launch_polar_extract(*plan, polar, static_cast<float2*>(spec_out), batch, s);
         if (e != hipSuccess) return device_fail(e);
         e = hipMemcpyAsync(dc_out, dc, (size_t)batch * plan->V * sizeof(float), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return device_fail(e);

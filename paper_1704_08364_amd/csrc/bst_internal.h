@@ -66,9 +66,8 @@ struct bst_plan_s {
     int2* tent_cols;     // [G/2]        (first slot of column a, B_a): rows |b| <= B_a are wide
     int4* tent_chunk;    // [chunks]     (slot, first tap j, last tap j, 0) in the continuation
     int* tent_coff;      // [tent_w + 1] chunk range of each slot
-    int gather_slices;   // slices per gather block (coordinates reused across them)
-    int gather_e;        // values per thread of the column transform, 8 or 16: fewer
-                         // values mean less per-thread state and more resident waves
+    int gather_slices;   // slices per gather block (coordinates reused across them),
+                         // a multiple of kPolarSlices
 };
 
 namespace bst {
@@ -93,6 +92,13 @@ struct WsLayout {
 struct TentSizes {
     size_t W = 0, rowsV = 0, C = 0;
 };
+// slices whose polar spectra are stored interleaved (sample by sample): the
+// gather reads all of them with every tap (2 or 4)
+#ifndef BST_POLAR_SLICES
+#define BST_POLAR_SLICES 2
+#endif
+constexpr int kPolarSlices = BST_POLAR_SLICES;
+static_assert(kPolarSlices == 2 || kPolarSlices == 4, "2 or 4 interleaved slices");
 // slices interleaved in the tent rule's radius-major copy
 constexpr int kTentSlices = 8;
 // slices interleaved in the projector's Cartesian spectra (and summed together
@@ -123,7 +129,7 @@ struct SpecArgs {
     const float* const* sino_list;  // or one pointer per slice (device array), if non-null
     const float* flat;      // [batch][n] or nullptr
     const float* dark;      // [batch][n]
-    float2* polar;
+    float2* polar;          // [ceil(batch/4)][V][S][4]: kPolarSlices slices interleaved per sample
     float* dc;
     const float* taper;
     const float2* kc;
@@ -149,7 +155,7 @@ struct MassArgs {           // partial sums of each slice's sinogram (monopole m
 };
 
 struct GatherArgs {
-    const float2* polar;
+    const float2* polar;     // [batch/4][V][S][4]: kPolarSlices slices interleaved per sample
     const float* dc;
     float2* grid;
     const float2* tw;
@@ -172,7 +178,7 @@ struct GatherArgs {
 };
 
 struct TentArgs {            // pre-gather of the wide points of the tent rule
-    const float2* polar;     // [batch][V][S]
+    const float2* polar;     // [batch/4][V][S][4] (kPolarSlices interleaved)
     float2* trans;           // [batch/8][rows][V][8]: the first rows radial samples,
                              // radius-major, 8 slices interleaved
     float2* patch;           // [batch][W]
@@ -255,6 +261,8 @@ hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int ba
 
 hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st);
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st);
+// copy the interleaved polar spectra out as [batch][V][M/2] complex64 (diagnostics)
+hipError_t launch_polar_extract(const bst_plan_s& p, const float2* polar, float2* out, int batch, hipStream_t st);
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st);
 hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStream_t st);
 hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipStream_t st);

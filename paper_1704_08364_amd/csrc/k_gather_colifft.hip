@@ -9,21 +9,31 @@
 // angle row, consecutive radii). Columns go to XCDs in contiguous ranges so
 // neighbouring columns share an L2.
 //
-// Each thread keeps the interpolation coordinates of its E points (8 by
-// default) in three registers each and reuses them for every slice of its
-// chunk. They are exact
-// to FP32 rounding although radius and angle indices reach a few thousand:
+// The polar spectra of kPolarSlices (Q = 2 or 4) consecutive slices are
+// stored interleaved, sample by sample, so one tap of one point reads the Q
+// slices' values of two radial samples as 16 Q contiguous bytes: the lines a
+// wave touches serve Q slices instead of one (simulated over the 2048 x 4096
+// gather points of N = 2048 with two columns per block: 9.9 (Q = 2) or 6.6
+// (Q = 4) instead of 16.4 distinct 128-byte lines per wave and slice). A
+// block therefore gathers Q slices at a time. Their column transforms run
+// one after the other; two of the gathered columns wait in LDS (two
+// transform regions), with Q = 4 the other two in registers (E = 16 points
+// per thread and 512-thread blocks, for the registers).
+//
+// Each thread keeps the interpolation coordinates of its E points in
+// three registers each and reuses them for every slice of its chunk. They
+// are exact to FP32 rounding although radius and angle indices reach a few
+// thousand:
 //   radius index r = |(a,b)| P_r/P_c from an FP64 square root;
 //   angle index: an FP32 atan2 picks the interval [theta_j0, theta_j0+1), then
 //   the offset inside it is atan2(cross, dot) of the point direction against
 //   (cos theta_j0, sin theta_j0) from an FP64 table (cross and dot in FP64,
 //   the small angle in FP32), so the fraction f carries no cancellation.
-// Per slice, the column is gathered straight into the registers the FFT
-// starts from, inverse-transformed along b, and only the N rows that survive
-// the crop are written, to a grid laid out [N/8][GT][8] (complex, GT >= G/2
-// columns per tile row): the 8 rows
-// of a tile and neighbouring columns form contiguous runs, and the row kernel
-// reads each 8-row tile contiguously.
+// Per slice, the column is inverse-transformed along b, and only the N rows
+// that survive the crop are written, to a grid laid out [N/8][GT][8]
+// (complex, GT >= G/2 columns per tile row): the 8 rows of a tile and
+// neighbouring columns form contiguous runs, and the row kernel reads each
+// 8-row tile contiguously.
 //
 // Gather rules (bilinear in (r, q)):
 //   b >= 0: theta = atan2(b, a), sample as stored; b < 0: theta + pi, conjugate
@@ -42,55 +52,37 @@ namespace bst {
 #define BST_GATHER_THREADS 1024
 #endif
 
-// Groups of points whose sample reads are issued together (the E points of a
-// thread split into this many): uniform angles with linear radial taps issue
-// all reads first (1 group); cubic taps, non-uniform angles and the tent rule
-// read one point at a time (E groups), which measured faster for the first
-// two -- 3.7 instead of 5.5 ms for cubic taps at 64 x 2048^2: a point's four
-// reads share cache lines, and fewer reads in flight keep them in L1 -- and
-// leaves the tent variant the registers of its wide-point mask.
-#ifndef BST_GATHER_GROUPS_LINEAR
-#define BST_GATHER_GROUPS_LINEAR 1
-#endif
-#ifndef BST_GATHER_GROUPS_OTHER
-#define BST_GATHER_GROUPS_OTHER 16
-#endif
-
 // waves per SIMD the register allocation must leave room for
 #ifndef BST_GATHER_WAVES
 #define BST_GATHER_WAVES 4
 #endif
 
-// two adjacent complex samples; 8-byte aligned, read with one 16-byte load
-struct __attribute__((aligned(8))) Pair8 {
-    float x0, y0, x1, y1;
-};
-
 // Word 3 of a CDNA buffer resource for plain dword data (32-bit data format,
 // no swizzle, raw offsets).
 constexpr int kBufferWord3 = 0x00020000;
 
-// One slice's polar block as a buffer resource: loads take a 32-bit byte
-// offset in one VGPR against a base held in SGPRs, and read 0 past the end.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t polar_rsrc(const float2* base, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), 0, bytes, kBufferWord3);
+// One slice group's polar block as a buffer resource: loads take a 32-bit
+// byte offset in one VGPR against a base held in SGPRs, and read 0 past the
+// end. The block holds at most 16384 x 4101 x 32 bytes (< 2^32).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t polar_rsrc(const float2* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), 0, (int)bytes, kBufferWord3);
 }
 
-__device__ __forceinline__ Pair8 load_pair(__amdgpu_buffer_rsrc_t r, unsigned off) {
+__device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t r, unsigned off) {
     const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-    return Pair8{__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3])};
+    return make_float4(__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3]));
 }
 
-template <int LOGG, int EV>
+template <int LOGG>
 struct GatherCfg {
     static constexpr int G = 1 << LOGG;
-    static constexpr int E = EV;
+    static constexpr int Q = kPolarSlices;
+    static constexpr int E = Q == 4 ? 16 : 8;            // points (values) per thread
     static constexpr int T = G / E;
-    // 16 values per thread need about twice the registers: two waves per
-    // SIMD, so blocks of at most 512 threads
-    static constexpr int CAP = E == 8 ? BST_GATHER_THREADS : 512;
+    static constexpr int CAP = Q == 4 ? 512 : BST_GATHER_THREADS;
+    static constexpr int WAVES = Q == 4 ? 2 : BST_GATHER_WAVES;  // per SIMD, for the registers
     static constexpr int MAXT = CAP > T ? CAP : T;
-    static constexpr int FL = 16384 / G;                 // LDS: about 140 KB of transforms
+    static constexpr int FL = 16384 / G;                 // LDS: two regions of about 70 KB
     static constexpr int F1 = FL < G / 2 ? FL : G / 2;   // no more columns than exist
     static constexpr int F2 = MAXT / T;
     static constexpr int F = F1 < F2 ? F1 : F2;          // columns per block
@@ -98,6 +90,7 @@ struct GatherCfg {
     // transform stride in LDS: padded length plus 8 float2, so that F regions
     // start 16 banks apart and lanes of different columns do not collide
     static constexpr int STRIDE = FftShape<LOGG>::LDS + 8;
+    static constexpr int REGION = F * STRIDE;            // one slice's F transforms
 };
 
 template <int WG>
@@ -117,26 +110,28 @@ __device__ float block_sum(float x, float* red) {
 }
 
 // Interpolation stencil of one Cartesian point, fixed for all slices:
-//   o0      byte offset (inside one slice's polar block) of the sample pair
-//           (j0, m0..m0+1); the pair (j1, m0..m0+1) is one polar row further,
-//           or, when j1 wraps to angle 0, (V-1) rows back. Bit 31 flips the
-//           conjugation of the j0 pair (non-uniform angles, below theta_0,
-//           where the j0 neighbour is the image theta_{V-1} - pi);
+//   o0      sample index (j0 S + m0: one unit is the kPolarSlices values of
+//           one sample, 32 bytes) of the first radial tap of angle j0; the
+//           taps of j1 are one polar row further, or, when j1 wraps to angle
+//           0, (V-1) rows back. Bit 31 flips the conjugation of the j0 taps
+//           (non-uniform angles, below theta_0, where the j0 neighbour is the
+//           image theta_{V-1} - pi);
 //   g       radial fraction, its sign bit set when j1 wraps;
-//   w1      angular weight f of the j1 pair, negative when that pair is
-//           conjugated. The j0 pair has weight 1 - f and is conjugated for
+//   w1      angular weight f of the j1 taps, negative when they are
+//           conjugated. The j0 taps have weight 1 - f and are conjugated for
 //           the lower half-plane b < 0 (known at compile time from the
 //           point's slot in the thread), unless bit 31 of o0 flips it.
 // Points outside the radial data (and the origin, which the DC rule sets
-// afterwards) point at the two zero slots that end rows 0 and 1, so every
-// point runs the same branch-free code.
+// afterwards) point at the zero slots that end rows 0 and 1, so every point
+// runs the same branch-free code.
 struct Stencil {
     unsigned o0;
     float g, w1;
 };
 constexpr unsigned kOffsetMask = 0x7FFFFFFFu;
+constexpr unsigned kSampleBytes = kPolarSlices * sizeof(float2);  // 32
 
-// conjugation of the j0 pair of point e: the lower half-plane, flipped by bit
+// conjugation of the j0 taps of point e: the lower half-plane, flipped by bit
 // e of `flips` (bit 31 of the point's o0, collected once per block)
 template <bool NU>
 __device__ __forceinline__ bool lower_j0(unsigned flips, int e, bool lower) {
@@ -146,18 +141,17 @@ __device__ __forceinline__ bool lower_j0(unsigned flips, int e, bool lower) {
 
 // Stencil of Cartesian point (col, bs); bs signed. NU: non-uniform angles.
 // TENT: a wide point of the tent rule (|bs| <= B_col) gets bit 31 of o0 and
-// its patch slot's byte offset in the low bits; its polar reads go to the
-// zero slots.
+// its patch slot in the low bits; its polar reads go to the zero slots.
 template <bool NU, bool TENT>
 __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a) {
     Stencil st;
-    st.o0 = (unsigned)a.zero_slot * sizeof(float2);
+    st.o0 = (unsigned)a.zero_slot;
     st.g = st.w1 = 0.f;
     if (col == 0 && bs == 0) return st;
     if constexpr (TENT) {
         const int2 tc = a.tent_cols[col];
         if (bs >= -tc.y && bs <= tc.y) {
-            st.o0 = ((unsigned)(tc.x + bs + tc.y) * sizeof(float2)) | 0x80000000u;
+            st.o0 = (unsigned)(tc.x + bs + tc.y) | 0x80000000u;
             return st;
         }
     }
@@ -217,7 +211,7 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
     // neighbours of a point below theta_0 are already in place)
     const bool wrap = (j0 + 1 == a.V);
     const bool conj1 = lower != (wrap && !flip0);
-    st.o0 = ((unsigned)(j0 * a.S + m0) * sizeof(float2)) | ((unsigned)flip0 << 31);
+    st.o0 = (unsigned)(j0 * a.S + m0) | ((unsigned)flip0 << 31);
     st.g = __uint_as_float(__float_as_uint((float)(r - mf)) | ((unsigned)wrap << 31));
     st.w1 = conj1 ? -f : f;
     return st;
@@ -225,28 +219,28 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
 
 // Grid stores are non-temporal: the row kernel reads them only after this
 // kernel ends, and 2 GB of them per 64 slices would otherwise evict the polar
-// lines the gather reuses (measured: 2.93 -> 2.89 ms at 64 x 2048^2; the same
-// stores in the spectrum and row kernels cost them 9 %, so they stay plain).
+// lines the gather reuses.
 __device__ __forceinline__ void store_streaming(float2* p, float2 v) {
     typedef float f2v __attribute__((ext_vector_type(2)));
     const f2v t = {v.x, v.y};
     __builtin_nontemporal_store(t, reinterpret_cast<f2v*>(p));
 }
 
-// Radial value of one row from its two (linear) or four (cubic) samples.
-__device__ __forceinline__ float2 radial2(const Pair8& p, float g) {
-    return make_float2(fmaf(g, p.x1 - p.x0, p.x0), fmaf(g, p.y1 - p.y0, p.y0));
+// Slice k of a tap's sample: its 16-byte parts hold slices (0, 1), (2, 3).
+__device__ __forceinline__ float2 slice_of(const float4* q, int k) {
+    const float4& h = q[k >> 1];
+    return (k & 1) ? make_float2(h.z, h.w) : make_float2(h.x, h.y);
 }
 // Keys cubic convolution (a = -1/2) over samples m0-1 .. m0+2 at fraction g:
 // the Catmull-Rom weights.
-__device__ __forceinline__ float2 radial4(const Pair8& p, const Pair8& q, float g) {
+__device__ __forceinline__ float2 keys4(float2 sm, float2 s0, float2 s1, float2 s2, float g) {
     const float g2 = g * g, g3 = g2 * g;
     const float wm = 0.5f * (-g3 + 2.f * g2 - g);
     const float w0 = 0.5f * (3.f * g3 - 5.f * g2 + 2.f);
     const float w1 = 0.5f * (-3.f * g3 + 4.f * g2 + g);
     const float w2 = 0.5f * (g3 - g2);
-    return make_float2(fmaf(w2, q.x1, fmaf(w1, q.x0, fmaf(w0, p.x1, wm * p.x0))),
-                       fmaf(w2, q.y1, fmaf(w1, q.y0, fmaf(w0, p.y1, wm * p.y0))));
+    return make_float2(fmaf(w2, s2.x, fmaf(w1, s1.x, fmaf(w0, s0.x, wm * sm.x))),
+                       fmaf(w2, s2.y, fmaf(w1, s1.y, fmaf(w0, s0.y, wm * sm.y))));
 }
 // Angular (linear) combination of the two rows' radial values: weight
 // 1 - |w1| for the j0 row, conjugated in the lower half-plane, and w1 (sign =
@@ -257,16 +251,49 @@ __device__ __forceinline__ float2 angular(float2 u0, float2 u1, float w1, bool l
     return make_float2(fmaf(fabsf(w1), u1.x, a0 * u0.x), fmaf(w1, u1.y, w0 * u0.y));
 }
 
-template <int LOGG, int EV, int TAPS, bool NU, bool TENT>
-__global__ void __launch_bounds__((GatherCfg<LOGG, EV>::WG))
-__attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather_colifft(GatherArgs a) {
-    using C = GatherCfg<LOGG, EV>;
+// One polar row's taps for the Q slices: linear taps read the samples m0,
+// m0+1 (16 Q bytes), cubic taps m0-1 .. m0+2 (32 Q bytes); then their radial
+// values.
+constexpr int kParts = kPolarSlices / 2;  // 16-byte parts per sample
+template <int TAPS>
+__device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t P, unsigned off, float4 (&q)[TAPS * kParts]) {
+#pragma unroll
+    for (int i = 0; i < TAPS * kParts; ++i) q[i] = load16(P, off + 16u * i);
+}
+template <int TAPS>
+__device__ __forceinline__ void radial_row(const float4 (&q)[TAPS * kParts], float g, float2 (&u)[kPolarSlices]) {
+    constexpr int H = kParts;
+#pragma unroll
+    for (int k = 0; k < kPolarSlices; ++k) {
+        if constexpr (TAPS == 2) {
+            const float2 x0 = slice_of(q, k), x1 = slice_of(q + H, k);
+            u[k] = make_float2(fmaf(g, x1.x - x0.x, x0.x), fmaf(g, x1.y - x0.y, x0.y));
+        } else {
+            u[k] = keys4(slice_of(q, k), slice_of(q + H, k), slice_of(q + 2 * H, k), slice_of(q + 3 * H, k), g);
+        }
+    }
+}
+
+// Points of a thread whose reads are issued together. Uniform angles with
+// linear radial taps issue several points' reads before using any; cubic
+// taps, non-uniform angles and the tent rule read one point at a time, which
+// measured faster for the first two (a point's reads share cache lines, and
+// fewer reads in flight keep them in L1) and leaves the tent variant the
+// registers of its wide-point mask.
+#ifndef BST_GATHER_INFLIGHT
+#define BST_GATHER_INFLIGHT 2
+#endif
+
+template <int LOGG, int TAPS, bool NU, bool TENT>
+__global__ void __launch_bounds__((GatherCfg<LOGG>::WG))
+__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft(GatherArgs a) {
+    using C = GatherCfg<LOGG>;
     constexpr int G = C::G, T = C::T, F = C::F, E = C::E;
-    __shared__ float2 lds[F * C::STRIDE];
+    constexpr int Q = kPolarSlices;
+    __shared__ float2 lds[2 * C::REGION];  // two regions: one slice's F transforms each
     __shared__ float red[(C::WG + 63) / 64];
     const int fid = threadIdx.x % F;
     const int j = threadIdx.x / F;
-    float2* my = lds + fid * C::STRIDE;
     const int lblock = xcd_contiguous(blockIdx.x, gridDim.x);
     const int col = lblock * F + fid;
     const bool live = col < G / 2;
@@ -278,7 +305,7 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
     constexpr int CH = E == 8 ? 2 : 4;
     constexpr int NW = 3;  // words per stencil
     Stencil pt[E];
-    static_assert(C::F * C::STRIDE * 2 >= C::WG * CH * NW, "stencil staging needs LDS");
+    static_assert(2 * C::REGION * 2 >= C::WG * CH * NW, "stencil staging needs LDS");
     unsigned* stage = reinterpret_cast<unsigned*>(lds);
 #pragma unroll
     for (int c0 = 0; c0 < E; c0 += CH) {
@@ -300,161 +327,162 @@ __attribute__((amdgpu_waves_per_eu(EV == 8 ? BST_GATHER_WAVES : 1, 8))) k_gather
             pt[c0 + h].w1 = __uint_as_float(d[2 * C::WG]);
         }
     }
-    __syncthreads();  // the transform reuses this LDS
-    // non-uniform angles: the j0 conjugation flips move to one bit mask, so
-    // the offsets are held once, already masked
-    unsigned flips = 0u;
-    if constexpr (NU) {
+    __syncthreads();  // the transforms reuse this LDS
+    // non-uniform angles: the j0 conjugation flips move to one bit mask; the
+    // tent rule: wide points likewise (their o0 keeps the patch slot)
+    unsigned flips = 0u, wide = 0u;
+    if constexpr (NU || TENT) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            flips |= (pt[e].o0 >> 31) << e;
+            (NU ? flips : wide) |= (pt[e].o0 >> 31) << e;
             pt[e].o0 &= kOffsetMask;
         }
     }
-    // tent rule: wide points as a bit mask; their o0 keeps the patch offset
-    // and their polar reads go to the zero slots (zoff)
-    unsigned wide = 0u;
-    const unsigned zoff = (unsigned)a.zero_slot * sizeof(float2);
-    if constexpr (TENT) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            wide |= (pt[e].o0 >> 31) << e;
-            pt[e].o0 &= kOffsetMask;
-        }
-    }
+    const unsigned zoff = (unsigned)a.zero_slot * kSampleBytes;
 
-    const int s_begin = blockIdx.y * a.slices_per_block;
+    const int s_begin = blockIdx.y * a.slices_per_block;  // a multiple of Q
     const int s_end = min(a.batch, s_begin + a.slices_per_block);
     const int half_n = a.N >> 1;
-    const int slice_bytes = a.V * a.S * (int)sizeof(float2);
-    const unsigned row_bytes = (unsigned)a.S * sizeof(float2);
+    const unsigned group_bytes = (unsigned)a.V * (unsigned)a.S * kSampleBytes;
+    const unsigned row_bytes = (unsigned)a.S * kSampleBytes;
     const unsigned wrap_bytes = 0u - (unsigned)(a.V - 1) * row_bytes;  // back to row 0
-    for (int s = s_begin; s < s_end; ++s) {
-        // Re-derive the lane's row index each slice: otherwise every address
+    float2* R0 = lds + fid * C::STRIDE;
+    float2* R1 = R0 + C::REGION;
+    for (int s0 = s_begin; s0 < s_end; s0 += Q) {
+        const int nq = min(Q, s_end - s0);  // slices of this group in the batch
+        // Re-derive the lane's row index each group: otherwise every address
         // that depends on it (LDS passes, grid stores) is hoisted out of the
         // loop and held in registers, which spills.
         int jv = j;
         asm volatile("" : "+v"(jv));
-        const __amdgpu_buffer_rsrc_t P = polar_rsrc(a.polar + (size_t)s * a.V * a.S, slice_bytes);
-        float2 v[E];
-        float dcv = 0.f;
-        // rows b = j + e*T with e >= E/2 are the lower half-plane (b - G < 0)
-        constexpr int GROUPS0 = (TAPS == 2 && !NU && !TENT) ? BST_GATHER_GROUPS_LINEAR : BST_GATHER_GROUPS_OTHER;
-        constexpr int GROUPS = GROUPS0 < E ? GROUPS0 : E;
-        if constexpr (GROUPS == 1 && TAPS == 2) {
-            // all 2E sample-pair loads are issued before any is used
-            Pair8 pa[E], pb[E];
+        const __amdgpu_buffer_rsrc_t P = polar_rsrc(a.polar + (size_t)(s0 / Q) * a.V * a.S * Q, group_bytes);
+        float dcv[Q];
+        if (lblock == 0) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const bool wrap = __float_as_uint(pt[e].g) >> 31;
-                const unsigned o0 = BST_IDX((TENT && ((wide >> e) & 1u)) ? zoff : pt[e].o0,
-                                            (unsigned)slice_bytes - 15u, 0);
-                pa[e] = load_pair(P, o0);
-                pb[e] = load_pair(P, BST_IDX(o0 + (wrap ? wrap_bytes : row_bytes), (unsigned)slice_bytes - 15u, 0));
-            }
-            if (lblock == 0) {
+            for (int k = 0; k < Q; ++k) {
                 float acc = 0.f;
-                for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)s * a.V + i];
-                dcv = block_sum<C::WG>(acc, red) * a.dc_scale;
-            }
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const float g = fabsf(pt[e].g);
-                v[e] = angular(radial2(pa[e], g), radial2(pb[e], g), pt[e].w1, 2 * e >= E);
-            }
-        } else {
-            if (lblock == 0) {
-                float acc = 0.f;
-                for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)s * a.V + i];
-                dcv = block_sum<C::WG>(acc, red) * a.dc_scale;
-            }
-            // two (linear) or four (cubic: samples m0-1 .. m0+2) 16-byte reads per
-            // point, issued for a group of points at a time to bound the registers
-            // in flight
-            constexpr int H = E / GROUPS;
-#pragma unroll
-            for (int h0 = 0; h0 < E; h0 += H) {
-                Pair8 pa[H], qa[H], pb[H], qb[H];
-#pragma unroll
-                for (int i = 0; i < H; ++i) {
-                    const Stencil& st = pt[h0 + i];
-                    const unsigned o0 = BST_IDX((TENT && ((wide >> (h0 + i)) & 1u)) ? zoff : st.o0,
-                                                (unsigned)slice_bytes - (TAPS == 4 ? 31u : 15u), 0);
-                    const unsigned o1 = BST_IDX(o0 + ((__float_as_uint(st.g) >> 31) ? wrap_bytes : row_bytes),
-                                                (unsigned)slice_bytes - (TAPS == 4 ? 31u : 15u), 0);
-                    pa[i] = load_pair(P, o0);
-                    pb[i] = load_pair(P, o1);
-                    if constexpr (TAPS == 4) {
-                        qa[i] = load_pair(P, o0 + 16u);
-                        qb[i] = load_pair(P, o1 + 16u);
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < H; ++i) {
-                    const int e = h0 + i;
-                    const float g = fabsf(pt[e].g);
-                    float2 u0, u1;
-                    if constexpr (TAPS == 4) {
-                        u0 = radial4(pa[i], qa[i], g);
-                        u1 = radial4(pb[i], qb[i], g);
-                    } else {
-                        u0 = radial2(pa[i], g);
-                        u1 = radial2(pb[i], g);
-                    }
-                    v[e] = angular(u0, u1, pt[e].w1, lower_j0<NU>(flips, e, 2 * e >= E));
-                }
-                asm volatile("" ::: "memory");
+                if (k < nq)
+                    for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)(s0 + k) * a.V + i];
+                dcv[k] = block_sum<C::WG>(acc, red) * a.dc_scale;
             }
         }
-        if constexpr (TENT) {
-            // wide points: the value pre-gathered over their tent of angles
-            if (wide) {
-                const float2* Pt = a.patch + (size_t)s * a.tent_w;
+        // gather: slices 0 and 1 of the group wait in the two LDS regions,
+        // slices 2 and 3 (Q = 4) in registers
+        constexpr int NH = Q > 2 ? E : 1;
+        float2 hold0[NH], hold1[NH];
+        constexpr int H = (TAPS == 2 && !NU && !TENT) ? BST_GATHER_INFLIGHT : 1;
+        static_assert(E % H == 0, "whole groups of points");
 #pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if ((wide >> e) & 1u) v[e] = Pt[BST_IDX(pt[e].o0 / (unsigned)sizeof(float2), (unsigned)a.tent_w, 1)];
+        for (int h0 = 0; h0 < E; h0 += H) {
+            float4 qa[H][TAPS * kParts], qb[H][TAPS * kParts];
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const Stencil& st = pt[h0 + i];
+                const bool wrap = __float_as_uint(st.g) >> 31;
+                constexpr unsigned kLast = TAPS * kSampleBytes - 1u;  // bytes read past the offset
+                const unsigned o0 = BST_IDX((TENT && ((wide >> (h0 + i)) & 1u)) ? zoff : st.o0 * kSampleBytes,
+                                            group_bytes - kLast, 0);
+                const unsigned o1 = BST_IDX(o0 + (wrap ? wrap_bytes : row_bytes), group_bytes - kLast, 0);
+                load_row<TAPS>(P, o0, qa[i]);
+                load_row<TAPS>(P, o1, qb[i]);
             }
-        }
-        // origin: column 0, row 0 is thread j = 0's first point
-        if (col == 0 && jv == 0) v[0] = make_float2(dcv, 0.f);
-
-        FftTwiddles<LOGG, +1, E> twl = tw;
-        twl.pin();
-        fft<LOGG, +1, E>(v, my, jv, twl);
-
-        if (live) {
-            float2* D = a.grid + (size_t)s * a.N * a.GT;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int y = jv + e * T;
-                const int p = (y + half_n) & (G - 1);
-                if (p < a.N)
-                    store_streaming(&D[BST_IDX(((size_t)(p >> 3) * a.GT + col) * 8 + (p & 7), (size_t)a.N * a.GT, 2)],
-                                    v[e]);
+            for (int i = 0; i < H; ++i) {
+                const int e = h0 + i;
+                const Stencil& st = pt[e];
+                const float g = fabsf(st.g);
+                float2 u0[Q], u1[Q], val[Q];
+                radial_row<TAPS>(qa[i], g, u0);
+                radial_row<TAPS>(qb[i], g, u1);
+#pragma unroll
+                for (int k = 0; k < Q; ++k) val[k] = angular(u0[k], u1[k], st.w1, lower_j0<NU>(flips, e, 2 * e >= E));
+                if constexpr (TENT) {
+                    // wide points: the value pre-gathered over their tent of angles
+                    if ((wide >> e) & 1u) {
+#pragma unroll
+                        for (int k = 0; k < Q; ++k) {
+                            const int sk = min(s0 + k, a.batch - 1);
+                            val[k] = a.patch[(size_t)sk * a.tent_w + BST_IDX(st.o0, (unsigned)a.tent_w, 1)];
+                        }
+                    }
+                }
+                // origin: column 0, row 0 is thread j = 0's first point
+                if (e == 0 && col == 0 && jv == 0) {
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) val[k] = make_float2(dcv[k], 0.f);
+                }
+                R0[lds_pad(jv + e * T)] = val[0];
+                R1[lds_pad(jv + e * T)] = val[1];
+                if constexpr (Q > 2) {
+                    hold0[e] = val[2];
+                    hold1[e] = val[3];
+                }
+            }
+            asm volatile("" ::: "memory");
+        }
+        __syncthreads();
+
+        // One transform per iteration, the loop kept rolled: unrolled, the
+        // transforms share address arithmetic that then stays live across
+        // all of them and spills. Slices 0, 1 come from their LDS region,
+        // slices 2, 3 from registers (moved up one place per turn).
+#pragma unroll 1
+        for (int k = 0; k < nq; ++k) {
+            int jk = jv;
+            asm volatile("" : "+v"(jk));
+            float2* Rk = (k & 1) ? R1 : R0;
+            float2 v[E];
+            if (k < 2) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = Rk[lds_pad(jk + e * T)];
+                __syncthreads();  // every lane has its inputs before the first pass writes
+            } else if constexpr (Q > 2) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    v[e] = hold0[e];
+                    hold0[e] = hold1[e];
+                }
+            }
+            FftTwiddles<LOGG, +1, E> twl = tw;
+            twl.pin();
+            fft<LOGG, +1, E>(v, Rk, jk, twl);
+            if (live) {
+                float2* D = a.grid + (size_t)(s0 + k) * a.N * a.GT;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int y = jk + e * T;
+                    const int p = (y + half_n) & (G - 1);
+                    if (p < a.N)
+                        store_streaming(&D[BST_IDX(((size_t)(p >> 3) * a.GT + col) * 8 + (p & 7),
+                                                   (size_t)a.N * a.GT, 2)], v[e]);
+                }
             }
         }
     }
 }
 
-template <int LOGG, int EV, int TAPS>
+template <int LOGG, int TAPS>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
-    using C = GatherCfg<LOGG, EV>;
+    using C = GatherCfg<LOGG>;
     const int cols = C::G / 2;
+    if (a.slices_per_block <= 0 || a.slices_per_block % kPolarSlices != 0) return hipErrorInvalidValue;
     const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
     dim3 grid((cols + C::F - 1) / C::F, chunks);
     if (a.tent_cols) {
         // tent rule: uniform angles and linear radial taps only (checked by the plan)
         if constexpr (TAPS == 2)
-            hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, false, true>), grid, dim3(C::WG), 0, st, a);
+            hipLaunchKernelGGL((k_gather_colifft<LOGG, TAPS, false, true>), grid, dim3(C::WG), 0, st, a);
         else
             return hipErrorInvalidValue;
     } else if (a.uniform) {
-        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, false, false>), grid, dim3(C::WG), 0, st, a);
+        hipLaunchKernelGGL((k_gather_colifft<LOGG, TAPS, false, false>), grid, dim3(C::WG), 0, st, a);
     } else {
-        hipLaunchKernelGGL((k_gather_colifft<LOGG, EV, TAPS, true, false>), grid, dim3(C::WG), 0, st, a);
+        hipLaunchKernelGGL((k_gather_colifft<LOGG, TAPS, true, false>), grid, dim3(C::WG), 0, st, a);
     }
     return hipGetLastError();
 }
+
+static_assert(kTentSlices % kPolarSlices == 0, "a tent group spans whole polar groups");
 
 // Tent rule, step 1: the first `rows` radial samples of every angle,
 // radius-major with kTentSlices slices interleaved ([group][m][j][slice]), so
@@ -467,14 +495,19 @@ __global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a, int batch) {
     __shared__ float2 tile[kTentSlices][8][33];
     const int grp = blockIdx.z;
     const int m0 = blockIdx.x * 32, j0 = blockIdx.y * 8;
+    // reads follow the interleaved polar layout: the Q slices of one sample,
+    // then consecutive samples (32 Q values contiguous per angle)
+    constexpr int Q = kPolarSlices, NG = kTentSlices / kPolarSlices;
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
         const int idx = it * 256 + threadIdx.x;
-        const int m = idx & 31, j = (idx >> 5) & 7, k = idx >> 8;
+        const int k4 = idx % Q, m = (idx / Q) & 31, kh = (idx / (32 * Q)) % NG, j = idx / 256;
+        const int k = kh * Q + k4;
         const int s = grp * kTentSlices + k;
         float2 v = make_float2(0.f, 0.f);
         if (s < batch && j0 + j < a.V && m0 + m < a.rows)
-            v = a.polar[((size_t)s * a.V + j0 + j) * a.S + BST_IDX(a.lead + m0 + m, a.S, 3)];
+            v = a.polar[(((size_t)(s / kPolarSlices) * a.V + j0 + j) * a.S + BST_IDX(a.lead + m0 + m, a.S, 3)) *
+                            kPolarSlices + k4];
         tile[k][j][m] = v;
     }
     __syncthreads();
@@ -598,27 +631,19 @@ hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStr
     return hipGetLastError();
 }
 
-// values per thread e (8 or 16) for linear radial taps; cubic taps use 8
-template <int LOGG>
-static hipError_t launch_gather_e(const GatherArgs& a, int e, int taps, hipStream_t st) {
-    if (taps == 4) return launch_gather_t<LOGG, 8, 4>(a, st);
-    if (e == 16) return launch_gather_t<LOGG, 16, 2>(a, st);
-    return launch_gather_t<LOGG, 8, 2>(a, st);
-}
-
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st) {
-    const int e = p.gather_e, t = p.taps;
+    const bool cubic = p.taps == 4;
     switch (p.logG) {
-        case 4: return launch_gather_e<4>(a, e, t, st);
-        case 5: return launch_gather_e<5>(a, e, t, st);
-        case 6: return launch_gather_e<6>(a, e, t, st);
-        case 7: return launch_gather_e<7>(a, e, t, st);
-        case 8: return launch_gather_e<8>(a, e, t, st);
-        case 9: return launch_gather_e<9>(a, e, t, st);
-        case 10: return launch_gather_e<10>(a, e, t, st);
-        case 11: return launch_gather_e<11>(a, e, t, st);
-        case 12: return launch_gather_e<12>(a, e, t, st);
-        case 13: return launch_gather_e<13>(a, e, t, st);
+        case 4: return cubic ? launch_gather_t<4, 4>(a, st) : launch_gather_t<4, 2>(a, st);
+        case 5: return cubic ? launch_gather_t<5, 4>(a, st) : launch_gather_t<5, 2>(a, st);
+        case 6: return cubic ? launch_gather_t<6, 4>(a, st) : launch_gather_t<6, 2>(a, st);
+        case 7: return cubic ? launch_gather_t<7, 4>(a, st) : launch_gather_t<7, 2>(a, st);
+        case 8: return cubic ? launch_gather_t<8, 4>(a, st) : launch_gather_t<8, 2>(a, st);
+        case 9: return cubic ? launch_gather_t<9, 4>(a, st) : launch_gather_t<9, 2>(a, st);
+        case 10: return cubic ? launch_gather_t<10, 4>(a, st) : launch_gather_t<10, 2>(a, st);
+        case 11: return cubic ? launch_gather_t<11, 4>(a, st) : launch_gather_t<11, 2>(a, st);
+        case 12: return cubic ? launch_gather_t<12, 4>(a, st) : launch_gather_t<12, 2>(a, st);
+        case 13: return cubic ? launch_gather_t<13, 4>(a, st) : launch_gather_t<13, 2>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -10,6 +10,9 @@
 // sigma_m beta dt) (K = 1/sigma for plain B, 1 for FBP, 0 at m = M/2; A the
 // apodising window; beta a known rotation-axis offset). With raw counts the
 // load forms y = -log((I - D)/(I0 - D)) first (flat/dark normalisation).
+// The polar spectra of kPolarSlices consecutive slices are stored interleaved
+// (sample m of projection j of the group's slices in 8 kPolarSlices
+// contiguous bytes), because the gather reads all of them at every tap.
 // Output rows hold m = 0..M/2-1 followed by zero slots, so the gather may read
 // past the last sample without a bound test: two for linear radial
 // interpolation (samples m0, m0+1), four plus a leading conj Yh[1] (the
@@ -27,16 +30,17 @@
 #ifndef BST_SPEC_WAVES
 #define BST_SPEC_WAVES 4
 #endif
-// projection-pair groups per block: the next group's detector data is read
-// while the current group is transformed
+// projection pairs per block in turn: the next pair's detector data is read
+// while the current one is transformed
 #ifndef BST_SPEC_PAIRS
 #define BST_SPEC_PAIRS 2
 #endif
 
 namespace bst {
 
-// Groups per block: the prefetch needs registers for one more group's data
-// slots, which only the P_r >= 2 plain-input variants have to spare.
+// Projection pairs per block in turn: the prefetch needs registers for one
+// more pair's data slots, which only the P_r >= 2 plain-input variants have
+// to spare.
 template <int LOGP, bool COUNTS, bool MONO>
 constexpr int spec_pairs() { return (LOGP >= 1 && !COUNTS && !MONO) ? BST_SPEC_PAIRS : 1; }
 
@@ -92,34 +96,48 @@ __global__ void __launch_bounds__(kMassThreads) k_mass(MassArgs a) {
 template <int LOGM>
 struct SpecCfg {
     static constexpr int M = 1 << LOGM;
-    static constexpr int T = M / 16;
-    static constexpr int F = T >= 256 ? 1 : 256 / T;   // transforms (projection pairs) per block
-    static constexpr int WG = F * T;
+    static constexpr int T = M / 16;                     // threads per transform
+    static constexpr int TP = kPolarSlices * T;          // per projection pair: one transform per slice
+    static constexpr int FP = TP >= 512 ? 1 : 512 / TP;  // projection pairs per block
+    static constexpr int WG = FP * TP;
+    static constexpr int MV = (M / 2) / TP;              // output samples per thread and pair
 };
 
 // LOGP = log2(P_r). Thread j's padded positions k = j + e*T hold data only for
 // e < E0 or e >= 16 - E0 (E0 = 8 / P_r): the middle of every line is padding,
 // known at compile time, so it is never loaded. COUNTS: the input is raw
 // counts with per-slice flat and dark fields.
-// Unpadded raw counts with the monopole hold the most per-thread state (16
-// data slots and their flat and dark values): they get room for 3 waves per
-// SIMD instead of spilling.
+// Unpadded raw counts with the monopole hold the most per-thread state: they
+// get room for 3 waves per SIMD instead of spilling.
 template <int LOGP, bool COUNTS, bool MONO>
 constexpr int spec_waves() { return (MONO && COUNTS && LOGP == 0) ? 3 : BST_SPEC_WAVES; }
 
+// One block: FP projection pairs (PAIRS of them in turn) of one group of
+// kPolarSlices slices, one complex transform per slice and pair (so every
+// slice's result is independent of the other slices). The epilogue separates
+// the two real spectra of every transform and writes, for every sample m of
+// each of the two projections, the group's slices' values side by side
+// (8 kPolarSlices contiguous bytes), so the polar rows come out interleaved
+// as the gather reads them:
+//   polar[((g V + j) S + lead + m) kPolarSlices + s mod kPolarSlices].
+// Slices of the last group past the batch read zeros.
 // MONO: monopole subtraction, y[i] - m phi[i] (m from the partial sums).
 template <int LOGM, int LOGP, bool COUNTS, bool MONO>
 __global__ void __launch_bounds__(SpecCfg<LOGM>::WG)
-__attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spectrum(SpecArgs a) {
+__attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spectrum(SpecArgs a, int batch) {
     using C = SpecCfg<LOGM>;
-    constexpr int M = C::M, T = C::T;
+    constexpr int M = C::M, T = C::T, TP = C::TP;
     constexpr int E0 = 8 >> LOGP;
     constexpr int NQ = 2 * E0;  // data slots per thread
-    __shared__ float2 lds[C::F * FftShape<LOGM>::LDS];
-    const int fid = threadIdx.x / T;
-    const int j = threadIdx.x - fid * T;
-    float2* my = lds + fid * FftShape<LOGM>::LDS;
-    const int s = blockIdx.y;
+    constexpr int Q = kPolarSlices;
+    __shared__ float2 lds[Q * C::FP * FftShape<LOGM>::LDS];
+    const int u = threadIdx.x / T;        // transform: pair u / Q, slice u % Q
+    const int j = threadIdx.x - u * T;
+    const int pl = u / Q, k = u % Q;
+    float2* my = lds + u * FftShape<LOGM>::LDS;
+    const int g = blockIdx.y;
+    const int s = g * Q + k;
+    const bool vs = s < batch;
     const int h = a.n >> 1;
     constexpr int PAIRS = spec_pairs<LOGP, COUNTS, MONO>();
     const int npairs = (a.V + 1) >> 1;
@@ -127,16 +145,17 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
     // detector bin of data slot q: positions e = q (q < E0) and e = 16 - 2*E0 + q (q >= E0)
     auto bin_of = [&](int q) {
         const int e = q < E0 ? q : 16 - 2 * E0 + q;
-        const int k = j + e * T;
-        return k < h ? k + h : k - M + h;
+        const int kk = j + e * T;
+        return kk < h ? kk + h : kk - M + h;
     };
+    const int sc = vs ? s : 0;  // a slice past the batch reads slice 0, dropped below
+    const float* base = a.sino_list ? a.sino_list[sc] : a.sino + (size_t)sc * a.V * a.n;
 
     // Every global read of the thread is issued up front with no branch in
-    // between: the data slots of both lines of the first group (a missing
-    // line -- an odd V, or a group past the end -- reads line 0 and is
+    // between: the data slots of both lines of the first pair (a missing
+    // line -- an odd V, or a pair past the end -- reads line 0 and is
     // dropped by a select), the taper, flat and dark, the epilogue weights and
-    // the twiddle anchors; these last are the same for every group.
-    const float* base = a.sino_list ? a.sino_list[s] : a.sino + (size_t)s * a.V * a.n;
+    // the twiddle anchors; these last are the same for every pair.
     auto load_lines = [&](int pair, float (&ra)[NQ], float (&rb)[NQ]) {
         const int ja = 2 * pair, jb = 2 * pair + 1;
         const float* ya = base + (size_t)(ja < a.V ? ja : 0) * a.n;
@@ -149,14 +168,14 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
         }
     };
     float ra[NQ], rb[NQ], w[NQ];
-    const int pair0 = blockIdx.x * PAIRS * C::F + fid;
+    const int pair0 = blockIdx.x * PAIRS * C::FP + pl;
     load_lines(pair0 < npairs ? pair0 : 0, ra, rb);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) w[q] = a.taper[bin_of(q)];
     float dk[COUNTS ? NQ : 1], fl[COUNTS ? NQ : 1];
     if constexpr (COUNTS) {
-        const float* fs = a.flat + (size_t)s * a.n;
-        const float* ds = a.dark + (size_t)s * a.n;
+        const float* fs = a.flat + (size_t)sc * a.n;
+        const float* ds = a.dark + (size_t)sc * a.n;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int i = bin_of(q);
@@ -166,23 +185,25 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
     }
     float mph[MONO ? NQ : 1];  // m phi at the thread's bins
     if constexpr (MONO) {
-        const float m = monopole_mass(a.mono_part, s, a.mono_inv);
+        const float m = monopole_mass(a.mono_part, sc, a.mono_inv);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) mph[q] = m * a.mono_phi[bin_of(q)];
     }
-    float2 kc[8];
+    // epilogue: thread q of its pair handles samples m = q + i*TP
+    const int qp = threadIdx.x - pl * TP;
+    float2 kc[C::MV];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) kc[e] = a.kc[j + e * T];
+    for (int i = 0; i < C::MV; ++i) kc[i] = a.kc[qp + i * TP];
     const FftTwiddles<LOGM, -1, 16> tw(j, a.tw);
 
 #pragma unroll
     for (int it = 0; it < PAIRS; ++it) {
-        const int pair = pair0 + it * C::F;
+        const int pair = pair0 + it * C::FP;
         const int ja = 2 * pair, jb = 2 * pair + 1;
-        const bool va = ja < a.V, vb = jb < a.V;
+        const bool va = ja < a.V && vs, vb = jb < a.V && vs;
         float na[NQ], nb[NQ];
         if (it + 1 < PAIRS) {
-            const int nx = pair + C::F;
+            const int nx = pair + C::FP;
             load_lines(nx < npairs ? nx : 0, na, nb);
         }
 
@@ -205,8 +226,8 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
             v[q < E0 ? q : 16 - 2 * E0 + q] = make_float2(va ? w[q] * xa : 0.f, vb ? w[q] * xb : 0.f);
         }
 
-        // fresh copies per group, so that nothing derived from them is
-        // computed once and held across both transforms (that spills)
+        // fresh copies per pair, so that nothing derived from them is
+        // computed once and held across the transforms (that spills)
         FftTwiddles<LOGM, -1, 16> twl = tw;
         twl.pin();
         int jv = j;
@@ -215,38 +236,57 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
 
 #pragma unroll
         for (int e = 0; e < 16; ++e) my[lds_pad(jv + e * T)] = v[e];
+        if (jv == 0) {
+            if (va) a.dc[(size_t)s * a.V + BST_IDX(ja, a.V, 3)] = a.dt * v[0].x;
+            if (vb) a.dc[(size_t)s * a.V + BST_IDX(jb, a.V, 3)] = a.dt * v[0].y;
+        }
         __syncthreads();
 
-        float2* pa = a.polar + ((size_t)s * a.V + ja) * a.S;
-        float2* pb = pa + a.S;
+        // separate the two real spectra of every slice's transform and store
+        // rows ja and jb with the group's slices interleaved
+        const bool wa = ja < a.V, wb = jb < a.V;
+        const float2* z0 = lds + (Q * pl) * FftShape<LOGM>::LDS;
+        float4* rowa = reinterpret_cast<float4*>(a.polar + (((size_t)g * a.V + (wa ? ja : 0)) * a.S) * Q);
+        float4* rowb = reinterpret_cast<float4*>(a.polar + (((size_t)g * a.V + (wb ? jb : 0)) * a.S) * Q);
+        constexpr int H = Q / 2;  // 16-byte parts per sample
+        int qv = qp;
+        asm volatile("" : "+v"(qv));
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int m = jv + e * T;  // 0 .. M/2-1
-            const float2 z = my[lds_pad(m)];
-            const float2 zc = my[lds_pad((M - m) & (M - 1))];
-            const float2 ya2 = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[e]);
-            const float2 yb2 = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[e]);
+        for (int i = 0; i < C::MV; ++i) {
+            const int m = qv + i * TP;  // 0 .. M/2-1
+            const int mc = (M - m) & (M - 1);
             const int slot = BST_IDX(a.lead + m, a.S, 2);
-            if (va) pa[slot] = ya2;
-            if (vb) pb[slot] = yb2;
-            // the sample before 0 (cubic radial taps): Yh(-sigma) = conj Yh(sigma)
-            if (a.lead && m == 1) {
-                if (va) pa[0] = make_float2(ya2.x, -ya2.y);
-                if (vb) pb[0] = make_float2(yb2.x, -yb2.y);
+#pragma unroll
+            for (int t = 0; t < H; ++t) {
+                float2 ya[2], yb[2];
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const float2* zt = z0 + (2 * t + d) * FftShape<LOGM>::LDS;
+                    const float2 z = zt[lds_pad(m)], zc = zt[lds_pad(mc)];
+                    ya[d] = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[i]);
+                    yb[d] = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[i]);
+                }
+                if (wa) {
+                    rowa[H * slot + t] = make_float4(ya[0].x, ya[0].y, ya[1].x, ya[1].y);
+                    // the sample before 0 (cubic radial taps): Yh(-sigma) = conj Yh(sigma)
+                    if (a.lead && m == 1) rowa[t] = make_float4(ya[0].x, -ya[0].y, ya[1].x, -ya[1].y);
+                }
+                if (wb) {
+                    rowb[H * slot + t] = make_float4(yb[0].x, yb[0].y, yb[1].x, yb[1].y);
+                    if (a.lead && m == 1) rowb[t] = make_float4(yb[0].x, -yb[0].y, yb[1].x, -yb[1].y);
+                }
             }
         }
-        for (int z = jv; z < a.tail; z += T) {
+        for (int z = qv; z < a.tail; z += TP) {
             const int slot = BST_IDX(a.lead + M / 2 + z, a.S, 2);
-            if (va) pa[slot] = make_float2(0.f, 0.f);
-            if (vb) pb[slot] = make_float2(0.f, 0.f);
-        }
-        if (jv == 0) {
-            const float2 z0 = my[0];
-            if (va) a.dc[(size_t)s * a.V + BST_IDX(ja, a.V, 3)] = a.dt * z0.x;
-            if (vb) a.dc[(size_t)s * a.V + BST_IDX(jb, a.V, 3)] = a.dt * z0.y;
+#pragma unroll
+            for (int t = 0; t < H; ++t) {
+                if (wa) rowa[H * slot + t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (wb) rowb[H * slot + t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
         if (it + 1 < PAIRS) {
-            __syncthreads();  // the next transform overwrites this LDS
+            __syncthreads();  // the next transforms overwrite this LDS
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 ra[q] = na[q];
@@ -257,23 +297,22 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
 }
 
 template <int LOGM, int LOGP, bool COUNTS, bool MONO>
-static void launch_spec_k(const SpecArgs& a, int groups, int batch, hipStream_t st) {
+static void launch_spec_k(const SpecArgs& a, int blocks, int batch, hipStream_t st) {
     using C = SpecCfg<LOGM>;
-    constexpr int P = spec_pairs<LOGP, COUNTS, MONO>();
-    hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, COUNTS, MONO>), dim3((groups + P - 1) / P, batch), dim3(C::WG), 0,
-                       st, a);
+    const int groups = (batch + kPolarSlices - 1) / kPolarSlices;
+    hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, COUNTS, MONO>), dim3(blocks, groups), dim3(C::WG), 0, st, a, batch);
 }
 
 template <int LOGM, int LOGP>
 static hipError_t launch_spec_t(const SpecArgs& a, int batch, hipStream_t st) {
     using C = SpecCfg<LOGM>;
-    const int pairs = (a.V + 1) / 2;
-    const int groups = (pairs + C::F - 1) / C::F;
     const bool counts = a.flat != nullptr, mono = a.mono_part != nullptr;
-    if (counts && mono) launch_spec_k<LOGM, LOGP, true, true>(a, groups, batch, st);
-    else if (counts) launch_spec_k<LOGM, LOGP, true, false>(a, groups, batch, st);
-    else if (mono) launch_spec_k<LOGM, LOGP, false, true>(a, groups, batch, st);
-    else launch_spec_k<LOGM, LOGP, false, false>(a, groups, batch, st);
+    const int pairs = (a.V + 1) / 2;
+    auto blocks = [&](int per) { return (pairs + C::FP * per - 1) / (C::FP * per); };
+    if (counts && mono) launch_spec_k<LOGM, LOGP, true, true>(a, blocks(spec_pairs<LOGP, true, true>()), batch, st);
+    else if (counts) launch_spec_k<LOGM, LOGP, true, false>(a, blocks(spec_pairs<LOGP, true, false>()), batch, st);
+    else if (mono) launch_spec_k<LOGM, LOGP, false, true>(a, blocks(spec_pairs<LOGP, false, true>()), batch, st);
+    else launch_spec_k<LOGM, LOGP, false, false>(a, blocks(spec_pairs<LOGP, false, false>()), batch, st);
     return hipGetLastError();
 }
 
@@ -289,6 +328,23 @@ static hipError_t launch_spec_p(const SpecArgs& a, int pr, int batch, hipStream_
         if (pr == 4) return launch_spec_t<LOGM, 2>(a, batch, st);
     }
     return hipErrorInvalidValue;
+}
+
+// out[s][j][m] = polar sample m of projection j of slice s (diagnostics copy)
+__global__ void __launch_bounds__(256) k_polar_extract(const float2* polar, float2* out, int V, int S, int lead,
+                                                       int half_m) {
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y, s = blockIdx.z;
+    if (m >= half_m) return;
+    const int g = s / kPolarSlices, k = s % kPolarSlices;
+    out[((size_t)s * V + j) * half_m + m] = polar[(((size_t)g * V + j) * S + lead + m) * kPolarSlices + k];
+}
+
+hipError_t launch_polar_extract(const bst_plan_s& p, const float2* polar, float2* out, int batch, hipStream_t st) {
+    const int half_m = p.M / 2;
+    hipLaunchKernelGGL(k_polar_extract, dim3((half_m + 255) / 256, p.V, batch), dim3(256), 0, st, polar, out, p.V,
+                       p.S, p.lead, half_m);
+    return hipGetLastError();
 }
 
 hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st) {

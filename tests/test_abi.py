@@ -48,6 +48,7 @@ def test_defaults_validate():
     ("n_angles", 1, 2), ("n_angles", 20000, 2),
     ("pad_radial", 3, 4), ("pad_cart", 8, 4), ("filter", 2, 4), ("taper", 7, 4),
     ("max_batch", 0, 9), ("device", -1, 4), ("interp", 2, 4), ("interp", -1, 4),
+    ("gather_slices", 3, 4), ("gather_slices", -2, 4), ("gather_slices", 1026, 4),
 ])
 def test_validation_codes(field, value, code):
     p, _ = _params()
@@ -104,10 +105,14 @@ def test_workspace_size_is_exact_and_monotone():
     sizes = [P.query_workspace(p, b) for b in (0, 1, 2, 7, 64)]
     assert sizes[0] == 0
     assert all(a < b for a, b in zip(sizes, sizes[1:]))
-    # polar [V][M/2+2] c64 + dc [V] f32 + grid [N][G/2] c64 per slice, 256-byte aligned blocks
-    per = 2048 * (2048 + 2) * 8 + 2048 * 4 + 2048 * 2048 * 8
-    assert abs(sizes[1] - per) < 3 * 256
-    assert abs(sizes[4] - 64 * per) < 3 * 256
+    # polar [V][M/2+2] c64 per slice, for whole groups of 2 interleaved slices,
+    # + dc [V] f32 + grid [N][G/2] c64 per slice, 256-byte aligned blocks
+    polar = 2048 * (2048 + 2) * 8
+    per = 2048 * 4 + 2048 * 2048 * 8
+    assert abs(sizes[1] - (2 * polar + per)) < 3 * 256
+    assert abs(sizes[2] - 2 * (polar + per)) < 3 * 256
+    assert abs(sizes[3] - (8 * polar + 7 * per)) < 3 * 256
+    assert abs(sizes[4] - 64 * (polar + per)) < 3 * 256
     with pytest.raises(P.BstError):
         P.query_workspace(p, 65)
     with pytest.raises(P.BstError):
@@ -169,8 +174,9 @@ def test_batch_create_validates_before_device_work():
 def test_keys_interpolation_validates_and_sizes_its_rows():
     p, _ = _params(n=2048, V=2048, max_batch=4, taper="keys", interp="keys")
     assert _validate(p) == 0
-    # keys rows: one leading slot and four trailing zeros, [V][M/2 + 5]
-    per = 2048 * (2048 + 5) * 8 + 2048 * 4 + 2048 * 2048 * 8
+    # keys rows: one leading slot and four trailing zeros, [V][M/2 + 5], for
+    # whole groups of 2 interleaved slices
+    per = 2 * 2048 * (2048 + 5) * 8 + 2048 * 4 + 2048 * 2048 * 8
     assert abs(P.query_workspace(p, 1) - per) < 3 * 256
     lin, _ = _params(n=2048, V=2048, max_batch=4)
     assert P.query_workspace(p, 4) > P.query_workspace(lin, 4)

@@ -41,6 +41,19 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def assert_parity(got, ref, tol=1e-5, elem=1e-4):
+    """The parity bar: relative L2 within tol, and no element further than
+    elem * max|ref| from the reference (so a local defect cannot hide in the
+    global norm)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    err = rel_l2(got, ref)
+    worst = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    assert err <= tol, f"rel-L2 {err:.3e} > {tol}"
+    assert worst <= elem, f"max |difference| {worst:.3e} of max |ref| > {elem}"
+    return err, worst
+
+
 @pytest.fixture(scope="module")
 def P():
     import paper_1704_08364_amd as mod
@@ -105,9 +118,8 @@ def test_backproject_matches_oracle(P, N, V, filt, P_r, P_c, taper):
     prm = obst.Params(P_r, P_c, filt, taper if taper != "kaiser" else "kb", 8.0)
     for b in range(B):
         ref = obst.backproject(sino[b].double().cpu().numpy(), geom, prm)
-        err = rel_l2(img[b].cpu().numpy(), ref)
-        _say(f"   slice {b}: rel-L2 {err:.2e}")
-        assert err <= 1e-5
+        err, worst = assert_parity(img[b].cpu().numpy(), ref)
+        _say(f"   slice {b}: rel-L2 {err:.2e}, max {worst:.2e}")
 
 
 def test_config1_head_phantom(P):
@@ -139,9 +151,8 @@ def test_full_batch_2048(P):
     for b in (0, B - 1):
         _say(f"[full 2048] oracle slice {b}")
         ref = obst.backproject(sino[b].double().cpu().numpy(), geom, obst.Params())
-        err = rel_l2(img[b].cpu().numpy(), ref)
-        _say(f"   rel-L2 {err:.2e}")
-        assert err <= 1e-5
+        err, worst = assert_parity(img[b].cpu().numpy(), ref)
+        _say(f"   rel-L2 {err:.2e}, max {worst:.2e}")
     _say("[full 2048] brute force")
     bf = plan.bruteforce(sino[:8])
     torch.cuda.synchronize()
@@ -151,6 +162,34 @@ def test_full_batch_2048(P):
     ref = obf.backproject_pixels(sino[7].double().cpu().numpy(), geom, rows, cols)
     got = bf[7].cpu().numpy()[rows, cols]
     assert rel_l2(got, ref) <= 1e-5
+
+
+# Every slices-per-block value the batch tuner may pick (and the smallest and
+# largest others), each checked in full on slices of the benchmark's plan: the
+# chunking of slices over blocks must not change a result.
+@pytest.mark.parametrize("spb", [2, 4, 8, 16, 32, 64])
+def test_gather_slices_per_block_variants(P, spb):
+    N, V, B = 2048, 2048, 10
+    sino = synth.batch_sinograms(B, N, V, seed=170408366, device=DEV)
+    plan = P.Plan(N, V, max_batch=B, gather_slices=spb)
+    img = plan.backproject(sino)
+    torch.cuda.synchronize()
+    geom = Geometry(N, V, N)
+    # the first slice, and the last (ragged) slice of the batch
+    for b in (0, B - 1):
+        ref = obst.backproject(sino[b].double().cpu().numpy(), geom, obst.Params())
+        err, worst = assert_parity(img[b].cpu().numpy(), ref)
+        _say(f"[spb {spb}] slice {b}: rel-L2 {err:.2e}, max {worst:.2e}")
+    # and bitwise the same as the default chunking, on every slice
+    ref_plan = P.Plan(N, V, max_batch=B)
+    assert torch.equal(img, ref_plan.backproject(sino))
+    small = P.Plan(256, 301, max_batch=5, gather_slices=spb, filter="none")
+    s2 = _sinos(5, 301, 256, 77)
+    got = small.backproject(s2)
+    g2 = Geometry(256, 301, 256)
+    for b in range(5):
+        assert_parity(got[b].cpu().numpy(), obst.backproject(s2[b].double().cpu().numpy(), g2,
+                                                              obst.Params(filter="none")))
 
 
 def test_largest_transform_4096(P):

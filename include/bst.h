@@ -228,6 +228,15 @@ bst_status bst_backproject_timed(bst_plan_t plan, const float* sino, float* img,
 bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float* img,
                                       int32_t batch, void* stream);
 
+/* Ramp filter of the brute-force FBP (the comparison's x = B F y, Section 1):
+ * the paper gives no discrete ramp, so this is the band-limited spatial kernel
+ * of Kak and Slaney sampled at the detector pitch, h[0] = 1/(4 dt^2),
+ * h[d odd] = -1/(pi^2 d^2 dt^2), h[d even] = 0, applied along each projection
+ * as a linear (not circular) convolution q[i] = dt sum_k h[i - k] y[k]
+ * (FP64 sums). sino, out: device float32 [batch][V][n], not overlapping.
+ * Feed `out` to bst_backproject_bruteforce for the brute-force FBP. */
+bst_status bst_ramp_filter(bst_plan_t plan, const float* sino, float* out, int32_t batch, void* stream);
+
 /* Projector R, the exact adjoint of bst_backproject: steps P8..P1 of Section 2
  * transposed one by one (crop -> zero-embed, C2R inverse FFT -> forward FFT,
  * gather (linear or cubic radial taps, any angle set) -> the same weights

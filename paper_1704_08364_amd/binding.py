@@ -62,6 +62,7 @@ SIGNATURES = {
     "bst_backproject_counts": (C.c_int, [_P, _P, _P, _P, _P, _I, _P, _S, _P]),
     "bst_backproject_bruteforce": (C.c_int, [_P, _P, _P, _I, _P]),
     "bst_project": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
+    "bst_ramp_filter": (C.c_int, [_P, _P, _P, _I, _P]),
     "bst_debug_spectrum": (C.c_int, [_P, _P, _P, _P, _I, _P, _S, _P]),
     "bst_destroy": (C.c_int, [_P]),
     "bst_status_string": (C.c_char_p, [C.c_int]),
@@ -339,6 +340,21 @@ class Plan:
         _keep_alive(stream, s3, o3)
         _check(lib().bst_backproject_bruteforce(self.handle, s3.data_ptr(), o3.data_ptr(), B,
                                                 _stream_ptr(stream)), "bst_backproject_bruteforce")
+        return o3 if batched else o3[0]
+
+    def ramp_filter(self, sino, out=None, stream=None):
+        """The brute-force FBP's ramp filter (Kak-Slaney kernel, linear
+        convolution) of float32 [B][V][n] sinograms."""
+        import torch
+        s3, batched = self._prep(sino)
+        B = s3.shape[0]
+        if out is None:
+            out = torch.empty_like(s3)
+        o3 = _out_tensor(out if out.dim() == 3 or batched else out.unsqueeze(0), "out", (B, self.V, self.n),
+                         s3.device)
+        _keep_alive(stream, s3, o3)
+        _check(lib().bst_ramp_filter(self.handle, s3.data_ptr(), o3.data_ptr(), B, _stream_ptr(stream)),
+               "bst_ramp_filter")
         return o3 if batched else o3[0]
 
     def debug_spectrum(self, sino, workspace=None, stream=None):

@@ -420,6 +420,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     const size_t o_gap = off;   off = up(off + V * sizeof(float));
     const size_t o_prow = off;  off = up(off + V * sizeof(float));
     const size_t o_mphi = off;  off = up(off + n * sizeof(float));
+    const size_t o_ramp = off;  off = up(off + n * sizeof(double));
     const size_t total = off;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
@@ -433,6 +434,12 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     std::memcpy(host.data() + o_gap, inv_gap.data(), V * sizeof(float));
     std::memcpy(host.data() + o_prow, proj_row.data(), V * sizeof(float));
     std::memcpy(host.data() + o_mphi, mono_phi.data(), n * sizeof(float));
+    // band-limited ramp of the brute-force comparison (Kak and Slaney): h[0] =
+    // 1/(4 dt^2), h[d odd] = -1/(pi^2 d^2 dt^2), h[d even] = 0, times dt
+    std::vector<double> ramp_h(n, 0.0);
+    ramp_h[0] = 1.0 / (4.0 * pl->dt);
+    for (int d = 1; d < n; d += 2) ramp_h[d] = -1.0 / (M_PI * M_PI * (double)d * (double)d * pl->dt);
+    std::memcpy(host.data() + o_ramp, ramp_h.data(), n * sizeof(double));
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -533,6 +540,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->inv_gap = reinterpret_cast<float*>(base + o_gap);
     pl->proj_row = reinterpret_cast<float*>(base + o_prow);
     pl->mono_phi = reinterpret_cast<float*>(base + o_mphi);
+    pl->ramp_h = reinterpret_cast<double*>(base + o_ramp);
     *out = pl;
     return BST_OK;
 }
@@ -759,6 +767,20 @@ bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float*
     const hipError_t e = bst::launch_bruteforce(*plan, a, batch, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_fail(e);
     return BST_OK;
+}
+
+bst_status bst_ramp_filter(bst_plan_t plan, const float* sino, float* out, int32_t batch, void* stream) {
+    if (!plan) return BST_E_NULL;
+    const size_t bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
+    size_t need = 0;
+    const bst_status st = check_call(plan, sino, bytes, out, bytes, batch, nullptr, 0, false, &need);
+    if (st != BST_OK || batch == 0) return st;
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return device_fail(guard.err);
+    const bst::RampArgs a{sino, out, plan->ramp_h, plan->n, plan->V};
+    bst::TraceRange tr("bst_ramp_filter");
+    const hipError_t e = bst::launch_ramp_filter(*plan, a, batch, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? BST_OK : device_fail(e);
 }
 
 bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t batch, void* ws,

@@ -55,6 +55,8 @@ struct bst_plan_s {
     size_t n_entries;
     float* proj_row;     // [V]          d^2 / (dt w_j): makes R the weighted adjoint of B
     float* mono_phi;     // [n]          phi(t_i - beta dt), monopole Gaussian (if enabled)
+    double* ramp_h;      // [n]          dt h[d], d = 0..n-1: the band-limited ramp kernel of the
+                         //              brute-force comparison (h[d] = h[-d])
     bool monopole;
     float mono_inv, mono_amp, mono_rho_px;
     // tent angular rule: small-radius ("wide") points, column by column
@@ -206,6 +208,13 @@ struct RowArgs {
     float mono_inv, mono_amp, mono_rho_px;
 };
 
+struct RampArgs {            // the brute-force comparison's ramp filter
+    const float* sino;       // [batch][V][n]
+    float* out;              // [batch][V][n]
+    const double* h;         // [n] dt h[d]
+    int n, V;
+};
+
 struct BfArgs {
     const float* sino;
     float* img;
@@ -267,5 +276,6 @@ hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipSt
 hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStream_t st);
 hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipStream_t st);
 hipError_t launch_bruteforce(const bst_plan_s& p, const BfArgs& a, int batch, hipStream_t st);
+hipError_t launch_ramp_filter(const bst_plan_s& p, const RampArgs& a, int batch, hipStream_t st);
 
 }  // namespace bst

@@ -116,6 +116,38 @@ __global__ void __launch_bounds__(256) k_bruteforce(BfArgs a) {
     }
 }
 
+// Ramp filter of the brute-force FBP: the band-limited spatial kernel of Kak
+// and Slaney sampled at the detector pitch, applied as a linear (not circular)
+// convolution, q[i] = dt sum_k h[i - k] y[k] over the n bins. Only d = 0 and
+// odd distances d carry weight. One block per projection; the row is staged
+// in LDS in FP64 and every output sums its terms in FP64 in a fixed order.
+constexpr int kRampThreads = 256;
+
+__global__ void __launch_bounds__(kRampThreads) k_ramp_filter(RampArgs a) {
+    extern __shared__ double row[];
+    const int j = blockIdx.x, s = blockIdx.y;
+    const float* y = a.sino + ((size_t)s * a.V + j) * a.n;
+    for (int i = threadIdx.x; i < a.n; i += kRampThreads) row[i] = (double)y[i];
+    __syncthreads();
+    float* q = a.out + ((size_t)s * a.V + j) * a.n;
+    for (int i = threadIdx.x; i < a.n; i += kRampThreads) {
+        double acc = a.h[0] * row[i];
+        // odd distances d: the samples i - d and i + d that exist
+        for (int d = 1; d < a.n; d += 2) {
+            const double l = i - d >= 0 ? row[i - d] : 0.0;
+            const double r = i + d < a.n ? row[i + d] : 0.0;
+            acc = fma(a.h[d], l + r, acc);
+        }
+        q[i] = (float)acc;
+    }
+}
+
+hipError_t launch_ramp_filter(const bst_plan_s& p, const RampArgs& a, int batch, hipStream_t st) {
+    (void)p;
+    hipLaunchKernelGGL(k_ramp_filter, dim3(a.V, batch), dim3(kRampThreads), a.n * sizeof(double), st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_bruteforce(const bst_plan_s& p, const BfArgs& a, int batch, hipStream_t st) {
     // the LDS segment length assumes one detector bin per pixel (d == dt)
     if (p.n != p.N) return hipErrorInvalidValue;

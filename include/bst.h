@@ -97,6 +97,17 @@ typedef enum {
                                [batch][that many] complex64 workspace array        */
 } bst_angular;
 
+/* Arithmetic of a plan. BST_F64 plans run plain double-precision kernels on
+ * double buffers (bst_backproject_f64, bst_project_f64): a path for checking
+ * gradients of least-squares objectives against finite differences and B, R
+ * against an FP64 reference, not for speed. They require n_det <= 512,
+ * uniform angles, BST_INTERP_LINEAR, BST_ANGULAR_LINEAR and no monopole
+ * (BST_E_UNSUPPORTED otherwise); every other parameter applies. */
+typedef enum {
+    BST_F32 = 0,
+    BST_F64 = 1
+} bst_dtype;
+
 typedef struct {
     int32_t n_det;          /* n: detector bins; power of two in [16, 4096]            */
     int32_t n_angles;       /* V: projections; [2, 16384]                               */
@@ -133,6 +144,8 @@ typedef struct {
                                the transpose of bst_project). Adds a reduction kernel
                                and a [batch][64] float32 workspace array.                */
     int32_t angular;        /* bst_angular (step P5)                                     */
+    int32_t dtype;          /* bst_dtype: BST_F32 (default) or BST_F64, the gradient-check
+                               path (bst_backproject_f64 / bst_project_f64 only)        */
     int32_t gather_slices;  /* slices each block of the step-P5/P6 gather kernel handles
                                (its interpolation coordinates are computed once for
                                them): 0 = the default (32), else a positive multiple
@@ -227,6 +240,20 @@ bst_status bst_backproject_timed(bst_plan_t plan, const float* sino, float* img,
  * angles (uniform or not) and weights w_j (pi/V, or half the neighbour gap). */
 bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float* img,
                                       int32_t batch, void* stream);
+
+/* FP64 gradient-check path (plans with dtype BST_F64; float entry points
+ * return BST_E_UNSUPPORTED for them, and these for BST_F32 plans): the same
+ * operators as bst_backproject and bst_project, in double precision,
+ * sino double [batch][V][n], img double [batch][N][N], workspace of
+ * bst_workspace_size bytes. B: steps P1-P8 of Section 2 with the plan's
+ * filter, taper, paddings, apodisation and centre shift; R: its exact adjoint
+ * under the weighted inner products (<R f, g> = <f, B g>, as bst_project).
+ * bst_project_f64 needs no adjoint tables (its transposed gather adds with
+ * FP64 atomics, so its last bits may vary between runs). */
+bst_status bst_backproject_f64(bst_plan_t plan, const double* sino, double* img, int32_t batch, void* ws,
+                               size_t ws_bytes, void* stream);
+bst_status bst_project_f64(bst_plan_t plan, const double* img, double* sino, int32_t batch, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /* Ramp filter of the brute-force FBP (the comparison's x = B F y, Section 1):
  * the paper gives no discrete ramp, so this is the band-limited spatial kernel

@@ -7,6 +7,7 @@ backward passes therefore are
     d/dsino of  <grad_img, B sino>  = B^T grad_img = R grad_img / c
     d/dimg  of  <grad_sino, R img>  = R^T grad_sino = c * B grad_sino
 and both run in the library's kernels (no torch arithmetic beyond the scalar c).
+Plans of dtype 'f64' take float64 tensors (the gradient-check path).
 """
 from __future__ import annotations
 
@@ -69,7 +70,7 @@ def lipschitz(plan: Plan, shape, iters: int = 8, seed: int = 0) -> float:
     """Largest eigenvalue of 2 R^T R by power iteration (for the step size)."""
     gen = torch.Generator(device=f"cuda:{plan.device}")
     gen.manual_seed(seed)
-    x = torch.randn(shape, device=f"cuda:{plan.device}", generator=gen)
+    x = torch.randn(shape, device=f"cuda:{plan.device}", generator=gen, dtype=plan.torch_dtype)
     lam = 1.0
     c = adjoint_scale(plan)
     for _ in range(iters):
@@ -87,7 +88,7 @@ def least_squares(plan: Plan, g: torch.Tensor, steps: int = 20, step: float = No
     shape = (B, plan.N, plan.N)
     if step is None:
         step = 1.0 / lipschitz(plan, shape)
-    f = torch.zeros(shape, device=g.device, requires_grad=True)
+    f = torch.zeros(shape, device=g.device, dtype=plan.torch_dtype, requires_grad=True)
     # the losses stay on the device until the end: reading each one back
     # would stall the stream once per step
     losses = []

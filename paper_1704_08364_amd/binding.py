@@ -29,6 +29,7 @@ TAPERS = {"deapod": 0, "none": 1, "kaiser": 2, "kb": 2, "keys": 3}
 INTERPS = {"linear": 0, "keys": 1}
 ANGULARS = {"linear": 0, "tent": 1}
 APODIZATIONS = {"ramlak": 0, "shepp": 1, "hann": 2, "cosine": 3}
+DTYPES = {"f32": 0, "f64": 1}
 
 # Every symbol include/bst.h declares, with its ctypes signature.
 _P = C.c_void_p
@@ -45,7 +46,7 @@ class bst_params(C.Structure):
         ("max_batch", C.c_int32), ("device", C.c_int32), ("adjoint", C.c_int32),
         ("apodization", C.c_int32), ("center_shift", C.c_double),
         ("interp", C.c_int32), ("monopole_width", C.c_double), ("angular", C.c_int32),
-        ("gather_slices", C.c_int32),
+        ("dtype", C.c_int32), ("gather_slices", C.c_int32),
     ]
 
 
@@ -63,6 +64,8 @@ SIGNATURES = {
     "bst_backproject_bruteforce": (C.c_int, [_P, _P, _P, _I, _P]),
     "bst_project": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
     "bst_ramp_filter": (C.c_int, [_P, _P, _P, _I, _P]),
+    "bst_backproject_f64": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
+    "bst_project_f64": (C.c_int, [_P, _P, _P, _I, _P, _S, _P]),
     "bst_debug_spectrum": (C.c_int, [_P, _P, _P, _P, _I, _P, _S, _P]),
     "bst_destroy": (C.c_int, [_P]),
     "bst_status_string": (C.c_char_p, [C.c_int]),
@@ -126,7 +129,8 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
                 taper_beta: float = 8.0, max_batch: int = 1, device: int = 0,
                 angles: Optional[Sequence[float]] = None, adjoint: bool = False,
                 apodization: str = "ramlak", center_shift: float = 0.0, interp: str = "linear",
-                monopole_width: float = 0.0, angular: str = "linear", gather_slices: int = 0):
+                monopole_width: float = 0.0, angular: str = "linear", gather_slices: int = 0,
+                dtype: str = "f32"):
     """bst_params plus the ctypes array that backs `angles` (keep both alive).
     interp='keys' (cubic radial interpolation) pairs with taper='keys';
     monopole_width > 0 (filter='none' only) subtracts a Gaussian monopole of that
@@ -134,7 +138,8 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
     angular='tent' (uniform angles, linear interp) widens the angular kernel at
     small radii, which makes plan.project a close Radon approximation.
     gather_slices (0 = default) sets the slices per block of the gather kernel;
-    results do not depend on it."""
+    results do not depend on it. dtype='f64' makes a plan of the FP64
+    gradient-check path (float64 sinograms and images)."""
     p = bst_params()
     lib().bst_params_default(C.byref(p), n_det, n_angles, n_det if n_out is None else n_out)
     p.pad_radial = pad_radial
@@ -151,6 +156,7 @@ def make_params(n_det: int, n_angles: int, n_out: Optional[int] = None, *, pad_r
     p.monopole_width = monopole_width
     p.angular = ANGULARS[angular] if isinstance(angular, str) else int(angular)
     p.gather_slices = int(gather_slices)
+    p.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     keep = None
     if angles is not None:
         arr = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
@@ -195,12 +201,13 @@ def _dev_tensor(t, name: str, dtype, shape_tail):
     return t
 
 
-def _out_tensor(out, name: str, shape, device):
-    """A caller-supplied output: float32, contiguous, exactly `shape`, on the
-    plan's device. The library writes shape-many elements and receives no size,
-    so anything smaller would be written past its end."""
+def _out_tensor(out, name: str, shape, device, dtype=None):
+    """A caller-supplied output: float32 (float64 for FP64 plans), contiguous,
+    exactly `shape`, on the plan's device. The library writes shape-many
+    elements and receives no size, so anything smaller would be written past
+    its end."""
     import torch
-    _dev_tensor(out, name, torch.float32, shape[1:])
+    _dev_tensor(out, name, dtype or torch.float32, shape[1:])
     if tuple(out.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(out.shape)}, expected {tuple(shape)}")
     if out.device != device:
@@ -242,7 +249,8 @@ class Event:
 
 class Plan:
     """A bst_plan on one device. Sinograms are float32 [B][V][n] (or [V][n]),
-    images float32 [B][N][N]."""
+    images float32 [B][N][N]; float64 for plans of dtype 'f64' (backproject
+    and project only)."""
 
     def __init__(self, n_det: int, n_angles: int, n_out: Optional[int] = None, **kw):
         self.params, self._angles_keep = make_params(n_det, n_angles, n_out, **kw)
@@ -253,9 +261,15 @@ class Plan:
         self.device = self.params.device
         self.M = (self.params.pad_radial or 2) * n_det
         self.G = (self.params.pad_cart or 2) * self.N
+        self.f64 = self.params.dtype == DTYPES["f64"]
         h = C.c_void_p()
         _check(lib().bst_plan(C.byref(self.params), C.byref(h)), "bst_plan")
         self.handle = h
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.f64 else torch.float32
 
     def close(self):
         if getattr(self, "handle", None):
@@ -278,26 +292,32 @@ class Plan:
         return torch.empty(max(self.workspace_size(batch), 1), dtype=torch.uint8,
                            device=f"cuda:{self.device}")
 
-    def _prep(self, sino):
+    def _prep(self, sino, dtype=None):
         import torch
-        sino = _dev_tensor(sino, "sino", torch.float32, (self.V, self.n))
+        sino = _dev_tensor(sino, "sino", dtype or torch.float32, (self.V, self.n))
         batched = sino.dim() == 3
         s3 = sino if batched else sino.unsqueeze(0)
         return s3, batched
 
     def backproject(self, sino, out=None, workspace=None, stream=None, events=None):
         import torch
-        s3, batched = self._prep(sino)
+        s3, batched = self._prep(sino, self.torch_dtype)
         B = s3.shape[0]
         if out is None:
-            out = torch.empty(B, self.N, self.N, dtype=torch.float32, device=s3.device)
+            out = torch.empty(B, self.N, self.N, dtype=self.torch_dtype, device=s3.device)
         o3 = _out_tensor(out if out.dim() == 3 or batched else out.unsqueeze(0), "out", (B, self.N, self.N),
-                         s3.device)
+                         s3.device, self.torch_dtype)
         if workspace is None:
             workspace = self.workspace(B)
         _keep_alive(stream, s3, o3, workspace)
         sp = _stream_ptr(stream)
-        if events is None:
+        if self.f64:
+            if events is not None:
+                raise ValueError("per-kernel events are for float32 plans")
+            st = lib().bst_backproject_f64(self.handle, s3.data_ptr(), o3.data_ptr(), B, workspace.data_ptr(),
+                                           workspace.numel(), sp)
+            _check(st, "bst_backproject_f64")
+        elif events is None:
             st = lib().bst_backproject(self.handle, s3.data_ptr(), o3.data_ptr(), B,
                                        workspace.data_ptr(), workspace.numel(), sp)
             _check(st, "bst_backproject")
@@ -374,18 +394,19 @@ class Plan:
 
     def project(self, img, out=None, workspace=None, stream=None):
         import torch
-        img = _dev_tensor(img, "img", torch.float32, (self.N, self.N))
+        img = _dev_tensor(img, "img", self.torch_dtype, (self.N, self.N))
         i3 = img if img.dim() == 3 else img.unsqueeze(0)
         B = i3.shape[0]
         if out is None:
-            out = torch.empty(B, self.V, self.n, dtype=torch.float32, device=i3.device)
+            out = torch.empty(B, self.V, self.n, dtype=self.torch_dtype, device=i3.device)
         o3 = _out_tensor(out if out.dim() == 3 or img.dim() == 3 else out.unsqueeze(0), "out",
-                         (B, self.V, self.n), i3.device)
+                         (B, self.V, self.n), i3.device, self.torch_dtype)
         if workspace is None:
             workspace = self.workspace(B)
         _keep_alive(stream, i3, o3, workspace)
-        _check(lib().bst_project(self.handle, i3.data_ptr(), o3.data_ptr(), B, workspace.data_ptr(),
-                                 workspace.numel(), _stream_ptr(stream)), "bst_project")
+        fn, name = (lib().bst_project_f64, "bst_project_f64") if self.f64 else (lib().bst_project, "bst_project")
+        _check(fn(self.handle, i3.data_ptr(), o3.data_ptr(), B, workspace.data_ptr(), workspace.numel(),
+                  _stream_ptr(stream)), name)
         return o3 if img.dim() == 3 else o3[0]
 
 

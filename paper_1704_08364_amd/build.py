@@ -34,7 +34,7 @@ CHECK_DIR = os.path.join(HERE, "_build_checked")
 CHECK_LIB = os.path.join(CHECK_DIR, "libbst_checked.so")
 
 SOURCES = ["bst_api.cpp", "plan_adjoint.cpp", "batch.cpp", "noalloc.hip", "k_spectrum.hip", "k_gather_colifft.hip", "k_row_c2r.hip",
-           "k_bruteforce.hip", "k_project.hip"]
+           "k_bruteforce.hip", "k_project.hip", "k_fp64.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ROCM_LIB = "/opt/rocm/lib"   # roctx (trace ranges)

@@ -168,6 +168,7 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
     if (!base || !n_det || !n_angles) return BST_E_NULL;
     if (count < 1) return BST_E_BATCH;
     if (base->angles) return BST_E_UNSUPPORTED;  // uniform angles only: V differs per instance
+    if (base->dtype != BST_F32) return BST_E_UNSUPPORTED;
     std::map<std::pair<int, int>, int> index;
     std::vector<std::pair<int, int>> keys;
     std::vector<std::vector<int>> members;

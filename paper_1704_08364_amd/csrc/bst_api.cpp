@@ -131,9 +131,23 @@ ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch) {
     return L;
 }
 
+F64WsLayout f64_workspace_layout(int V, int M, int G, int batch) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    F64WsLayout L{};
+    const size_t B = (size_t)batch;
+    L.polar_off = 0;
+    L.dc_off = up(B * (size_t)V * (size_t)(M / 2 + 2) * 16);
+    L.cart_off = up(L.dc_off + B * (size_t)V * 8);
+    L.polar_t_off = up(L.cart_off + B * (size_t)G * (size_t)(G / 2 + 1) * 16);
+    L.origin_off = up(L.polar_t_off + B * (size_t)V * (size_t)(M / 2 + 1) * 16);
+    L.total = up(L.origin_off + B * 8);
+    return L;
+}
+
 size_t workspace_bytes(int n, int V, int N, int M, int G, int batch, bool adjoint, int interp, bool monopole,
-                       const TentSizes& tent) {
+                       const TentSizes& tent, bool f64) {
     if (batch == 0) return 0;
+    if (f64) return f64_workspace_layout(V, M, G, batch).total;
     size_t need = workspace_layout(n, V, N, M, G, batch, interp, monopole, tent).total;
     if (adjoint) {
         const size_t pj = project_workspace_layout(V, N, M, G, batch).total;
@@ -167,6 +181,7 @@ void bst_params_default(bst_params* p, int32_t n_det, int32_t n_angles, int32_t 
     p->monopole_width = 0.0;
     p->angular = BST_ANGULAR_LINEAR;
     p->gather_slices = 0;
+    p->dtype = BST_F32;
 }
 
 bst_status bst_validate(const bst_params* p) {
@@ -204,6 +219,10 @@ bst_status bst_validate(const bst_params* p) {
     if (p->device < 0) return BST_E_PARAM;
     if (p->gather_slices < 0 || p->gather_slices > 1024 || p->gather_slices % bst::kPolarSlices != 0)
         return BST_E_PARAM;
+    if (p->dtype != BST_F32 && p->dtype != BST_F64) return BST_E_PARAM;
+    if (p->dtype == BST_F64 && (p->n_det > 512 || p->angles || p->interp != BST_INTERP_LINEAR ||
+                                p->angular != BST_ANGULAR_LINEAR || p->monopole_width != 0.0))
+        return BST_E_UNSUPPORTED;
     if (p->angles) {
         double prev = -1.0;
         for (int j = 0; j < p->n_angles; ++j) {
@@ -249,8 +268,8 @@ bst_status bst_query_workspace(const bst_params* p, int32_t batch, size_t* bytes
     if (batch < 0 || batch > p->max_batch) return BST_E_BATCH;
     const int M = pad_or_default(p->pad_radial) * p->n_det;
     const int G = pad_or_default(p->pad_cart) * p->n_out;
-    *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch,
-                                  p->adjoint != 0, p->interp, p->monopole_width != 0.0, params_tent_sizes(p, M, G));
+    *bytes = bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, batch, p->adjoint != 0, p->interp,
+                                  p->monopole_width != 0.0, params_tent_sizes(p, M, G), p->dtype == BST_F64);
     return BST_OK;
 }
 
@@ -264,8 +283,9 @@ bst_status bst_query_max_batch(const bst_params* p, size_t budget_bytes, int32_t
     const size_t io = ((size_t)p->n_angles * p->n_det + (size_t)p->n_out * p->n_out) * sizeof(float);
     const bst::TentSizes tw = params_tent_sizes(p, M, G);
     auto need = [&](int32_t q) {
-        return (size_t)q * io + bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, q, p->adjoint != 0,
-                                                     p->interp, p->monopole_width != 0.0, tw);
+        return (size_t)q * io * (p->dtype == BST_F64 ? 2 : 1) +
+               bst::workspace_bytes(p->n_det, p->n_angles, p->n_out, M, G, q, p->adjoint != 0, p->interp,
+                                    p->monopole_width != 0.0, tw, p->dtype == BST_F64);
     };
     // need(q) grows with q: binary search for the last q that fits
     int32_t lo = 0, hi = p->max_batch;
@@ -316,11 +336,14 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->gather_slices = p->gather_slices > 0 ? p->gather_slices : BST_GATHER_SLICES;
     pl->monopole = (p->monopole_width != 0.0);
     pl->tent = (p->angular == BST_ANGULAR_TENT);
+    pl->f64 = (p->dtype == BST_F64);
 
     // ---- FP64 tables ----
     const int n = pl->n, M = pl->M, G = pl->G, V = pl->V;
     const double dsig = 1.0 / (M * pl->dt);
     std::vector<float> taper(n), bf_w(V);
+    std::vector<double> taper64(n);
+    std::vector<double2> kc64(M / 2);
     std::vector<float2> kc(M / 2);
     std::vector<float2> twM(M), twG(G);
     std::vector<double> bf_c(V), bf_s(V), theta(V);
@@ -344,6 +367,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
             w = bessel_i0(p->taper_beta * std::sqrt(arg > 0.0 ? arg : 0.0)) / bessel_i0(p->taper_beta);
         }
         taper[i] = (float)w;
+        taper64[i] = w;
     }
     for (int m = 0; m < M / 2; ++m) {
         double K;
@@ -357,6 +381,7 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
         const double ph = 2.0 * M_PI * (double)m * p->center_shift / (double)M;
         const double wr = pl->dt * K * A;
         kc[m] = make_float2((float)(wr * std::cos(ph)), (float)(wr * std::sin(ph)));
+        kc64[m] = make_double2(K * A * std::cos(ph), K * A * std::sin(ph));
     }
     for (int k = 0; k < M; ++k) {
         const double a = -2.0 * M_PI * (double)k / (double)M;
@@ -421,6 +446,8 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     const size_t o_prow = off;  off = up(off + V * sizeof(float));
     const size_t o_mphi = off;  off = up(off + n * sizeof(float));
     const size_t o_ramp = off;  off = up(off + n * sizeof(double));
+    const size_t o_tap64 = off; off = up(off + n * sizeof(double));
+    const size_t o_kc64 = off;  off = up(off + (M / 2) * sizeof(double2));
     const size_t total = off;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_taper, taper.data(), n * sizeof(float));
@@ -440,6 +467,8 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     ramp_h[0] = 1.0 / (4.0 * pl->dt);
     for (int d = 1; d < n; d += 2) ramp_h[d] = -1.0 / (M_PI * M_PI * (double)d * (double)d * pl->dt);
     std::memcpy(host.data() + o_ramp, ramp_h.data(), n * sizeof(double));
+    std::memcpy(host.data() + o_tap64, taper64.data(), n * sizeof(double));
+    std::memcpy(host.data() + o_kc64, kc64.data(), (M / 2) * sizeof(double2));
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -541,6 +570,8 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->proj_row = reinterpret_cast<float*>(base + o_prow);
     pl->mono_phi = reinterpret_cast<float*>(base + o_mphi);
     pl->ramp_h = reinterpret_cast<double*>(base + o_ramp);
+    pl->taper64 = reinterpret_cast<double*>(base + o_tap64);
+    pl->kc64 = reinterpret_cast<double2*>(base + o_kc64);
     *out = pl;
     return BST_OK;
 }
@@ -549,7 +580,7 @@ bst_status bst_workspace_size(bst_plan_t plan, int32_t batch, size_t* bytes) {
     if (!plan || !bytes) return BST_E_NULL;
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
     *bytes = bst::workspace_bytes(plan->n, plan->V, plan->N, plan->M, plan->G, batch, plan->adjoint,
-                                  plan->prm.interp, plan->monopole, tent_sizes(plan));
+                                  plan->prm.interp, plan->monopole, tent_sizes(plan), plan->f64);
     return BST_OK;
 }
 
@@ -586,6 +617,7 @@ bst_status run_backproject(bst_plan_t plan, const float* sino, float* img, int32
                            const float* dark = nullptr, const float* const* sino_list = nullptr,
                            float* const* img_list = nullptr) {
     if (!plan) return BST_E_NULL;
+    if (plan->f64) return BST_E_UNSUPPORTED;  // bst_backproject_f64
     const size_t in_bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
     const size_t out_bytes = (size_t)batch * plan->N * plan->N * sizeof(float);
     size_t need = 0;
@@ -769,6 +801,71 @@ bst_status bst_backproject_bruteforce(bst_plan_t plan, const float* sino, float*
     return BST_OK;
 }
 
+namespace {
+// the FP64 path's call: checks, workspace carving, kernels (B or R)
+bst_status run_f64(bst_plan_t plan, const double* in, double* out, int32_t batch, void* ws, size_t ws_bytes,
+                   void* stream, bool project) {
+    if (!plan) return BST_E_NULL;
+    if (!plan->f64) return BST_E_UNSUPPORTED;
+    if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
+    if (batch == 0) return BST_OK;
+    if (!in || !out || !ws) return BST_E_NULL;
+    const bst::F64WsLayout L = bst::f64_workspace_layout(plan->V, plan->M, plan->G, batch);
+    if (ws_bytes < L.total) return BST_E_WORKSPACE;
+    const size_t sino_bytes = (size_t)batch * plan->V * plan->n * sizeof(double);
+    const size_t img_bytes = (size_t)batch * plan->N * plan->N * sizeof(double);
+    const Range ri{(uintptr_t)in, (uintptr_t)in + (project ? img_bytes : sino_bytes)};
+    const Range ro{(uintptr_t)out, (uintptr_t)out + (project ? sino_bytes : img_bytes)};
+    const Range rw{(uintptr_t)ws, (uintptr_t)ws + L.total};
+    if (overlap(ri, ro) || overlap(rw, ri) || overlap(rw, ro)) return BST_E_ALIAS;
+    DeviceGuard guard(plan->device);
+    if (guard.err != hipSuccess) return device_fail(guard.err);
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    bst::F64Args a{};
+    a.polar = reinterpret_cast<double2*>(w + L.polar_off);
+    a.dc = reinterpret_cast<double*>(w + L.dc_off);
+    a.cart = reinterpret_cast<double2*>(w + L.cart_off);
+    a.polar_t = reinterpret_cast<double2*>(w + L.polar_t_off);
+    a.origin = reinterpret_cast<double*>(w + L.origin_off);
+    a.taper = plan->taper64;
+    a.kc = plan->kc64;
+    a.n = plan->n;
+    a.V = plan->V;
+    a.N = plan->N;
+    a.M = plan->M;
+    a.G = plan->G;
+    a.dt = plan->dt;
+    a.dk2 = plan->dk * plan->dk;
+    a.rscale = plan->rscale;
+    a.dc_rule = plan->prm.filter == BST_FILTER_RAMP ? 1.0 : 4.0 * std::asinh(1.0) / plan->dk;
+    const double d = 2.0 / plan->N;
+    a.row_scale = d * d / (plan->dt * M_PI / plan->V);
+    hipError_t e;
+    if (project) {
+        a.img_in = in;
+        a.sino = out;
+        bst::TraceRange tr("bst_project_f64");
+        e = bst::launch_fp64_project(a, batch, static_cast<hipStream_t>(stream));
+    } else {
+        a.sino_in = in;
+        a.img = out;
+        bst::TraceRange tr("bst_backproject_f64");
+        e = bst::launch_fp64_backproject(a, batch, static_cast<hipStream_t>(stream));
+    }
+    return e == hipSuccess ? BST_OK : device_fail(e);
+}
+}  // namespace
+
+bst_status bst_backproject_f64(bst_plan_t plan, const double* sino, double* img, int32_t batch, void* ws,
+                               size_t ws_bytes, void* stream) {
+    return run_f64(plan, sino, img, batch, ws, ws_bytes, stream, false);
+}
+
+bst_status bst_project_f64(bst_plan_t plan, const double* img, double* sino, int32_t batch, void* ws,
+                           size_t ws_bytes, void* stream) {
+    return run_f64(plan, img, sino, batch, ws, ws_bytes, stream, true);
+}
+
 bst_status bst_ramp_filter(bst_plan_t plan, const float* sino, float* out, int32_t batch, void* stream) {
     if (!plan) return BST_E_NULL;
     const size_t bytes = (size_t)batch * plan->V * plan->n * sizeof(float);
@@ -791,7 +888,7 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
     if (batch < 0 || batch > plan->prm.max_batch) return BST_E_BATCH;
     if (batch == 0) return BST_OK;
     if (!img || !sino || !ws) return BST_E_NULL;
-    if (!plan->adjoint) return BST_E_UNSUPPORTED;
+    if (!plan->adjoint || plan->f64) return BST_E_UNSUPPORTED;
     const bst::ProjWsLayout L = bst::project_workspace_layout(plan->V, plan->N, plan->M, plan->G, batch);
     if (ws_bytes < L.total) return BST_E_WORKSPACE;
     const Range ri{(uintptr_t)img, (uintptr_t)img + in_bytes};

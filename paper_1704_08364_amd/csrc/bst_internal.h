@@ -55,6 +55,9 @@ struct bst_plan_s {
     size_t n_entries;
     float* proj_row;     // [V]          d^2 / (dt w_j): makes R the weighted adjoint of B
     float* mono_phi;     // [n]          phi(t_i - beta dt), monopole Gaussian (if enabled)
+    bool f64;            // dtype BST_F64: the FP64 gradient-check path (k_fp64.hip)
+    double* taper64;     // [n]          FP64 plans: P1 taper
+    double2* kc64;       // [M/2]        FP64 plans: K[m] A(sigma_m) exp(2 pi i sigma_m beta dt)
     double* ramp_h;      // [n]          dt h[d], d = 0..n-1: the band-limited ramp kernel of the
                          //              brute-force comparison (h[d] = h[-d])
     bool monopole;
@@ -125,6 +128,11 @@ struct ProjWsLayout {
     size_t grid_off, cart8_off, polar_off, total;
 };
 ProjWsLayout project_workspace_layout(int V, int N, int M, int G, int batch);
+
+struct F64WsLayout {
+    size_t polar_off, dc_off, cart_off, polar_t_off, origin_off, total;
+};
+F64WsLayout f64_workspace_layout(int V, int M, int G, int batch);
 
 struct SpecArgs {
     const float* sino;      // y, or raw counts when flat != nullptr; [batch][V][n]
@@ -208,6 +216,22 @@ struct RowArgs {
     float mono_inv, mono_amp, mono_rho_px;
 };
 
+struct F64Args {             // the FP64 gradient-check path (k_fp64.hip)
+    const double* sino_in;   // B: sinograms [B][V][n]
+    double* sino;            // R: sinograms out (B reads sino_in)
+    const double* img_in;    // R: images [B][N][N]
+    double* img;             // B: images out
+    double2* polar;          // [B][V][M/2 + 2]
+    double* dc;              // [B][V]
+    double2* cart;           // [B][G][G/2 + 1]
+    double2* polar_t;        // [B][V][M/2 + 1]
+    double* origin;          // [B]
+    const double* taper;     // [n]
+    const double2* kc;       // [M/2] K A phase (no dt)
+    int n, V, N, M, G;
+    double dt, dk2, rscale, dc_rule, row_scale;
+};
+
 struct RampArgs {            // the brute-force comparison's ramp filter
     const float* sino;       // [batch][V][n]
     float* out;              // [batch][V][n]
@@ -277,5 +301,7 @@ hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStr
 hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipStream_t st);
 hipError_t launch_bruteforce(const bst_plan_s& p, const BfArgs& a, int batch, hipStream_t st);
 hipError_t launch_ramp_filter(const bst_plan_s& p, const RampArgs& a, int batch, hipStream_t st);
+hipError_t launch_fp64_backproject(const F64Args& a, int batch, hipStream_t st);
+hipError_t launch_fp64_project(const F64Args& a, int batch, hipStream_t st);
 
 }  // namespace bst

@@ -283,6 +283,9 @@ __device__ __forceinline__ void radial_row(const float4 (&q)[TAPS * kParts], flo
 #ifndef BST_GATHER_INFLIGHT
 #define BST_GATHER_INFLIGHT 2
 #endif
+#ifndef BST_GATHER_INFLIGHT_OTHER
+#define BST_GATHER_INFLIGHT_OTHER 1
+#endif
 
 template <int LOGG, int TAPS, bool NU, bool TENT>
 __global__ void __launch_bounds__((GatherCfg<LOGG>::WG))
@@ -370,7 +373,7 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
         // slices 2 and 3 (Q = 4) in registers
         constexpr int NH = Q > 2 ? E : 1;
         float2 hold0[NH], hold1[NH];
-        constexpr int H = (TAPS == 2 && !NU && !TENT) ? BST_GATHER_INFLIGHT : 1;
+        constexpr int H = (TAPS == 2 && !NU && !TENT) ? BST_GATHER_INFLIGHT : BST_GATHER_INFLIGHT_OTHER;
         static_assert(E % H == 0, "whole groups of points");
 #pragma unroll
         for (int h0 = 0; h0 < E; h0 += H) {

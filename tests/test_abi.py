@@ -49,6 +49,7 @@ def test_defaults_validate():
     ("pad_radial", 3, 4), ("pad_cart", 8, 4), ("filter", 2, 4), ("taper", 7, 4),
     ("max_batch", 0, 9), ("device", -1, 4), ("interp", 2, 4), ("interp", -1, 4),
     ("gather_slices", 3, 4), ("gather_slices", -2, 4), ("gather_slices", 1026, 4),
+    ("dtype", 2, 4), ("dtype", -1, 4),
 ])
 def test_validation_codes(field, value, code):
     p, _ = _params()
@@ -309,3 +310,22 @@ def test_debug_check_in_the_ordinary_build():
     assert L.bst_debug_check(0, None) == 1
     if os.path.basename(binding.LIB_PATH) == "libbst.so":
         assert L.bst_debug_check(0, C.byref(flags)) == 8 and flags.value == 0
+
+
+def test_fp64_plans_validate_and_size():
+    # the FP64 gradient-check path: n <= 512, uniform angles, linear taps, no monopole
+    p, _ = _params(n=256, V=200, dtype="f64", max_batch=3)
+    assert _validate(p) == 0
+    size = P.query_workspace(p, 3)
+    # polar [V][M/2+2] + dc [V] + Cartesian [G][G/2+1] + polar^T [V][M/2+1] (16-byte complex) + origin
+    M = G = 512
+    expect = 3 * (200 * (M // 2 + 2) * 16 + 200 * 8 + G * (G // 2 + 1) * 16 + 200 * (M // 2 + 1) * 16 + 8)
+    assert abs(size - expect) < 6 * 256
+    for kw in (dict(n=1024, V=64), dict(n=256, V=64, interp="keys", taper="keys"),
+               dict(n=256, V=64, angular="tent"), dict(n=256, V=64, filter="none", monopole_width=0.4),
+               dict(n=64, V=4, angles=[0.1, 0.5, 1.0, 2.0])):
+        q, _keep = _params(dtype="f64", **kw)
+        assert _validate(q) == 8, kw
+    L = P.lib()
+    assert L.bst_backproject_f64(None, None, None, 1, None, 0, None) == 1
+    assert L.bst_project_f64(None, None, None, 1, None, 0, None) == 1

@@ -263,7 +263,7 @@ def ls_workload(args):
 def uneven_workload(args):
     """Uneven-size batch: 512 sinograms, N drawn from {256, 512, 1024, 2048},
     n_angles uniform in [N/2, 2N], random 2D ellipse phantoms, one graph
-    launch; the gather variant is tuned per size class first."""
+    launch; the persistent grid sizes are tuned per size class and stage first."""
     import numpy as np
     import torch
 

@@ -1,16 +1,27 @@
 // batch.cpp -- uneven-size batches: many sinograms of different sizes in one
-// graph launch (the paper processes blocks of Q sinograms at once, Section 2;
-// its pipeline tunes block sizes and queue lengths per stage, Section 3).
+// graph launch (the paper processes blocks of Q sinograms at once, Section 2,
+// and tunes its pipeline's block sizes and queues per stage, Section 3).
 //
-// Instances are grouped into classes of equal (n, V); each class gets its own
-// plan (tables for its angle count) and its own workspace region, so classes
-// can run concurrently. Kernels read the instances' sinograms and write their
-// images through per-slice pointer lists, so instances need not be contiguous
-// or ordered by class. The first call with a given workspace captures every
-// class's three launches into one hipGraph, forked over a few streams (all at
+// Instances are grouped into size classes of equal n (= N); the angle count V
+// may differ per instance. Each class has one plan (the FFT twiddles, taper,
+// radial weights of its n, built with the class's largest V) and one
+// workspace region laid out for its largest V, one slice per polar group (the
+// interleaving of ordinary batches pairs equal angle sets, which instances of
+// different V do not have). Per stage and class, one persistent kernel walks
+// a device work list of (slice, tile) items, every item carrying its slice's
+// own V (angle directions j pi / V formed on the fly): spectrum (P1-P4),
+// gather + column inverse FFT (P5-P6) and row C2R (P6-P8), plus a sinogram-sum
+// kernel with monopole subtraction. Kernels read the instances' sinograms and
+// write their images through per-slice pointer lists, so instances need not
+// be contiguous or ordered. The first call with a given workspace captures
+// every class's launches into one hipGraph, forked over a few streams (all at
 // default priority) and joined back; later calls update the pointer lists and
-// replay the graph. bst_batch_tune times the gather kernel's variants per
-// class on the caller's data and keeps the fastest before the capture.
+// replay it. bst_batch_tune times each stage's persistent grid size per class
+// on the caller's data and keeps the fastest.
+//
+// The tent angular rule pre-gathers its patches per angle set, so tent
+// batches keep classes of equal (n, V) run by the ordinary kernels (through
+// the same pointer lists), one class per pair.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -22,28 +33,53 @@
 
 namespace {
 
-struct Class {
-    int n, V;
+constexpr int kStreams = 4;
+constexpr int kStages = 3;  // spectrum, gather, row
+
+struct SizeClass {
+    int n = 0, Vmax = 0;
+    bool regular = false;      // equal (n, V), ordinary launches (tent rule)
     bst_plan_t plan = nullptr;
     std::vector<int> members;  // instance indices, in input order
     int list_base = 0;         // offset of this class's pointers in the lists
     size_t ws_off = 0, ws_bytes = 0;
+    // workspace layout (offsets inside the class region)
+    size_t polar_off = 0, dc_off = 0, grid_off = 0, mass_off = 0;
+    // device arrays (inside the batch's table block): V per slice, work lists
+    int* d_V = nullptr;
+    int2* d_items[kStages] = {};
+    int n_items[kStages] = {};
+    int row_tiles = 1;
+    int blocks[kStages] = {};  // persistent grid sizes (tuned)
 };
 
-constexpr int kStreams = 4;
+// Layout of a class region: polar [B][Vmax][S] complex64 (one slice per
+// group), DC terms [B][Vmax], grid [B][N][G/2], monopole sums [B][64].
+size_t class_layout(SizeClass& c) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const bst_plan_s& p = *c.plan;
+    const size_t B = c.members.size();
+    c.polar_off = 0;
+    c.dc_off = up(B * (size_t)c.Vmax * p.S * sizeof(float2));
+    c.grid_off = up(c.dc_off + B * (size_t)c.Vmax * sizeof(float));
+    c.mass_off = up(c.grid_off + B * (size_t)p.N * p.GT * sizeof(float2));
+    return up(c.mass_off + (p.monopole ? B * bst::kMassChunks * sizeof(float) : 0));
+}
 
 }  // namespace
 
 struct bst_batch_s {
     int device = 0;
     int count = 0;
-    std::vector<Class> classes;
+    int cus = 0;                          // compute units of the device
+    std::vector<SizeClass> classes;
     size_t ws_total = 0;
     void* d_lists = nullptr;              // device: [count] sinogram then [count] image pointers
     const float** d_sino_list = nullptr;
     float** d_img_list = nullptr;
     void* h_lists = nullptr;              // pinned host staging, 2 * count pointers
     hipEvent_t lists_done = nullptr;      // the staging may be rewritten after this
+    void* d_tables = nullptr;             // per-slice V and work lists of every class
     hipStream_t streams[kStreams] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t joins[kStreams] = {};
@@ -68,6 +104,7 @@ void release(bst_batch_s* b) {
     for (auto& c : b->classes)
         if (c.plan) (void)bst_destroy(c.plan);
     if (b->d_lists) (void)hipFree(b->d_lists);
+    if (b->d_tables) (void)hipFree(b->d_tables);
     if (b->h_lists) (void)hipHostFree(b->h_lists);
     if (b->lists_done) (void)hipEventDestroy(b->lists_done);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -79,8 +116,9 @@ void release(bst_batch_s* b) {
     delete b;
 }
 
-// Enqueue one class's spectrum, gather and row kernels on `st`.
-hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStream_t st) {
+// Enqueue a regular class (equal n and V) on `st`: the ordinary kernels, as
+// for a batch of one plan, reading and writing through the pointer lists.
+hipError_t launch_regular(const bst_batch_s* b, const SizeClass& c, void* ws, hipStream_t st) {
     const bst_plan_s& p = *c.plan;
     const int batch = (int)c.members.size();
     bst::TentSizes tent;
@@ -95,15 +133,15 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     float* dc = reinterpret_cast<float*>(w + L.dc_off);
     float2* grid = reinterpret_cast<float2*>(w + L.grid_off);
     float* mass = p.monopole ? reinterpret_cast<float*>(w + L.mass_off) : nullptr;
+    const float* const* sinos = b->d_sino_list + c.list_base;
     hipError_t e;
     if (p.monopole) {
-        const bst::MassArgs ma{nullptr, b->d_sino_list + c.list_base, nullptr, nullptr, mass, p.n, p.V};
+        const bst::MassArgs ma{nullptr, sinos, nullptr, nullptr, mass, p.n, p.V};
         e = bst::launch_mass(p, ma, batch, st);
         if (e != hipSuccess) return e;
     }
-    bst::SpecArgs sa{nullptr, b->d_sino_list + c.list_base, nullptr, nullptr, polar, dc, p.taper, p.kc,
-                     p.tw_M, p.n, p.V, p.S, p.lead, p.S - p.lead - p.M / 2, (float)p.dt,
-                     mass, p.mono_phi, p.mono_inv};
+    const bst::SpecArgs sa{nullptr, sinos, nullptr, nullptr, polar, dc, p.taper, p.kc, p.tw_M, p.n, p.V, p.S,
+                           p.lead, p.S - p.lead - p.M / 2, (float)p.dt, mass, p.mono_phi, p.mono_inv};
     e = bst::launch_spectrum(p, sa, batch, st);
     if (e != hipSuccess) return e;
     bst::GatherArgs ga{};
@@ -140,9 +178,64 @@ hipError_t launch_class(const bst_batch_s* b, const Class& c, void* ws, hipStrea
     }
     e = bst::launch_gather_colifft(p, ga, st);
     if (e != hipSuccess) return e;
-    bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.GT, p.out_scale, 0,
-                    mass, p.mono_inv, p.mono_amp, p.mono_rho_px};
+    const bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.GT, p.out_scale, 0,
+                          mass, p.mono_inv, p.mono_amp, p.mono_rho_px};
     return bst::launch_row_c2r(p, ra, batch, st);
+}
+
+// Enqueue one class's stages on `st`: the persistent spectrum, gather and row
+// kernels (and the monopole sums first).
+hipError_t launch_class(const bst_batch_s* b, const SizeClass& c, void* ws, hipStream_t st) {
+    if (c.regular) return launch_regular(b, c, ws, st);
+    const bst_plan_s& p = *c.plan;
+    const int batch = (int)c.members.size();
+    unsigned char* w = static_cast<unsigned char*>(ws) + c.ws_off;
+    float2* polar = reinterpret_cast<float2*>(w + c.polar_off);
+    float* dc = reinterpret_cast<float*>(w + c.dc_off);
+    float2* grid = reinterpret_cast<float2*>(w + c.grid_off);
+    float* mass = p.monopole ? reinterpret_cast<float*>(w + c.mass_off) : nullptr;
+    const float* const* sinos = b->d_sino_list + c.list_base;
+    hipError_t e;
+    if (p.monopole) {
+        bst::MassArgs ma{nullptr, sinos, nullptr, nullptr, mass, p.n, c.Vmax, c.d_V};
+        e = bst::launch_mass(p, ma, batch, st);
+        if (e != hipSuccess) return e;
+    }
+    bst::SpecArgs sa{nullptr, sinos, nullptr, nullptr, polar, dc, p.taper, p.kc, p.tw_M, p.n, c.Vmax, p.S, p.lead,
+                     p.S - p.lead - p.M / 2, (float)p.dt, mass, p.mono_phi, p.mono_inv};
+    sa.Vs = c.d_V;
+    sa.items = c.d_items[0];
+    sa.n_items = c.n_items[0];
+    e = bst::launch_spectrum_items(p, sa, batch, c.blocks[0], st);
+    if (e != hipSuccess) return e;
+    bst::GatherArgs ga{};
+    ga.polar = polar;
+    ga.dc = dc;
+    ga.grid = grid;
+    ga.tw = p.tw_G;
+    ga.V = c.Vmax;
+    ga.S = p.S;
+    ga.GT = p.GT;
+    ga.N = p.N;
+    ga.Mh = p.M / 2;
+    ga.zero_slot = p.M / 2 + p.lead;
+    ga.uniform = 1;
+    ga.batch = batch;
+    ga.slices_per_block = 1;
+    ga.rscale = p.rscale;
+    ga.dc_rule = p.dc_scale * (float)p.V;  // the plan's per-projection factor times its V
+    ga.Vs = c.d_V;
+    ga.items = c.d_items[1];
+    ga.n_items = c.n_items[1];
+    e = bst::launch_gather_items(p, ga, c.blocks[1], st);
+    if (e != hipSuccess) return e;
+    bst::RowArgs ra{grid, nullptr, b->d_img_list + c.list_base, p.tw_G, p.N, p.GT, p.out_scale, c.row_tiles,
+                    mass, p.mono_inv, p.mono_amp, p.mono_rho_px};
+    ra.V = p.V;
+    ra.Vs = c.d_V;
+    ra.items = c.d_items[2];
+    ra.n_items = c.n_items[2];
+    return bst::launch_row_items(p, ra, c.blocks[2], st);
 }
 
 struct Guard {
@@ -157,6 +250,11 @@ struct Guard {
     }
 };
 
+// the persistent grid of a stage: k blocks per compute unit, at most one per item
+int grid_blocks(const bst_batch_s* b, int items, int per_cu) {
+    return std::max(1, std::min(items, per_cu * b->cus));
+}
+
 }  // namespace
 
 extern "C" {
@@ -169,9 +267,9 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
     if (count < 1) return BST_E_BATCH;
     if (base->angles) return BST_E_UNSUPPORTED;  // uniform angles only: V differs per instance
     if (base->dtype != BST_F32) return BST_E_UNSUPPORTED;
-    std::map<std::pair<int, int>, int> index;
-    std::vector<std::pair<int, int>> keys;
-    std::vector<std::vector<int>> members;
+    const bool regular = base->angular == BST_ANGULAR_TENT;
+    std::map<std::pair<int, int>, int> index;  // (n, V or 0) -> class
+    std::vector<SizeClass> classes;
     for (int i = 0; i < count; ++i) {
         bst_params p = *base;
         p.n_det = n_det[i];
@@ -180,53 +278,108 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
         p.max_batch = 1;
         const bst_status st = bst_validate(&p);
         if (st != BST_OK) return st;
-        const auto key = std::make_pair(n_det[i], n_angles[i]);
+        const auto key = std::make_pair((int)n_det[i], regular ? (int)n_angles[i] : 0);
         auto it = index.find(key);
         if (it == index.end()) {
-            index.emplace(key, (int)keys.size());
-            keys.push_back(key);
-            members.emplace_back();
-            it = index.find(key);
+            it = index.emplace(key, (int)classes.size()).first;
+            classes.emplace_back();
+            classes.back().n = n_det[i];
+            classes.back().regular = regular;
         }
-        members[it->second].push_back(i);
+        SizeClass& c = classes[it->second];
+        c.members.push_back(i);
+        c.Vmax = std::max(c.Vmax, (int)n_angles[i]);
     }
     bst_batch_s* b = new (std::nothrow) bst_batch_s();
     if (!b) return BST_E_NOMEM;
     b->device = base->device;
     b->count = count;
+    b->classes = std::move(classes);
     Guard guard(b->device);
     if (guard.err != hipSuccess) {
         delete b;
         return fail(guard.err);
     }
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, b->device);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(e);
+    }
+    b->cus = prop.multiProcessorCount;
     int list_base = 0;
     size_t off = 0;
-    for (size_t k = 0; k < keys.size(); ++k) {
-        Class c;
-        c.n = keys[k].first;
-        c.V = keys[k].second;
-        c.members = members[k];
+    std::vector<std::vector<int2>> items;  // per class and stage
+    for (auto& c : b->classes) {
         bst_params p = *base;
         p.n_det = c.n;
         p.n_out = c.n;
-        p.n_angles = c.V;
+        p.n_angles = c.Vmax;
         p.max_batch = (int32_t)c.members.size();
         p.adjoint = 0;
         const bst_status st = bst_plan(&p, &c.plan);
         if (st != BST_OK) {
-            b->classes.push_back(c);
             release(b);
             return st;
         }
         c.list_base = list_base;
         list_base += (int)c.members.size();
-        (void)bst_workspace_size(c.plan, p.max_batch, &c.ws_bytes);
         c.ws_off = off;
-        off += (c.ws_bytes + 255) & ~(size_t)255;
-        b->classes.push_back(c);
+        if (c.regular) {
+            (void)bst_workspace_size(c.plan, p.max_batch, &c.ws_bytes);
+            off += (c.ws_bytes + 255) & ~(size_t)255;
+            for (int s = 0; s < kStages; ++s) items.emplace_back();
+            continue;
+        }
+        c.ws_bytes = class_layout(c);
+        off += c.ws_bytes;
+        // work lists: (slice, block) items of each stage, slice-major
+        const int B = (int)c.members.size();
+        const int groups = c.plan->N / 8;  // 8-row tiles per slice
+        c.row_tiles = std::max(1, std::min(16, (int)(((long long)groups * B) / 1024)));
+        for (int s = 0; s < kStages; ++s) {
+            std::vector<int2> list;
+            for (int i = 0; i < B; ++i) {
+                const int V = n_angles[c.members[i]];
+                const int nb = s == 0 ? bst::spectrum_blocks_per_slice(*c.plan, V)
+                                      : (s == 1 ? bst::gather_blocks_per_slice(*c.plan)
+                                                : bst::row_blocks_per_slice(*c.plan, c.row_tiles));
+                for (int k = 0; k < nb; ++k) list.push_back(make_int2(i, k));
+            }
+            c.n_items[s] = (int)list.size();
+            items.push_back(std::move(list));
+        }
+        c.blocks[0] = grid_blocks(b, c.n_items[0], 2);
+        c.blocks[1] = grid_blocks(b, c.n_items[1], 1);
+        c.blocks[2] = grid_blocks(b, c.n_items[2], 2);
     }
     b->ws_total = off;
-    hipError_t e = hipMalloc(&b->d_lists, 2 * (size_t)count * sizeof(void*));
+    // one device block: per class its V list, then its three work lists
+    size_t tbytes = 0;
+    std::vector<size_t> v_off(b->classes.size()), i_off(b->classes.size() * kStages);
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+        v_off[k] = tbytes;
+        tbytes += ((b->classes[k].members.size() * sizeof(int) + 15) / 16) * 16;
+        for (int s = 0; s < kStages; ++s) {
+            i_off[k * kStages + s] = tbytes;
+            tbytes += std::max<size_t>(items[k * kStages + s].size(), 1) * sizeof(int2);
+        }
+    }
+    std::vector<unsigned char> host(tbytes, 0);
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+        const SizeClass& c = b->classes[k];
+        for (size_t i = 0; i < c.members.size(); ++i) {
+            const int V = n_angles[c.members[i]];
+            std::memcpy(host.data() + v_off[k] + i * sizeof(int), &V, sizeof(int));
+        }
+        for (int s = 0; s < kStages; ++s) {
+            const auto& l = items[k * kStages + s];
+            if (!l.empty()) std::memcpy(host.data() + i_off[k * kStages + s], l.data(), l.size() * sizeof(int2));
+        }
+    }
+    e = hipMalloc(&b->d_tables, std::max<size_t>(tbytes, 16));
+    if (e == hipSuccess) e = hipMemcpy(b->d_tables, host.data(), tbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&b->d_lists, 2 * (size_t)count * sizeof(void*));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_lists, 2 * (size_t)count * sizeof(void*), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->lists_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
@@ -237,6 +390,12 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
     if (e != hipSuccess) {
         release(b);
         return fail(e);
+    }
+    unsigned char* tb = static_cast<unsigned char*>(b->d_tables);
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+        SizeClass& c = b->classes[k];
+        c.d_V = reinterpret_cast<int*>(tb + v_off[k]);
+        for (int s = 0; s < kStages; ++s) c.d_items[s] = reinterpret_cast<int2*>(tb + i_off[k * kStages + s]);
     }
     b->d_sino_list = static_cast<const float**>(b->d_lists);
     b->d_img_list = reinterpret_cast<float**>(static_cast<char*>(b->d_lists) + (size_t)count * sizeof(void*));
@@ -289,27 +448,34 @@ bst_status bst_batch_tune(bst_batch_t b, const float* sinos, const int64_t* sino
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return fail(e);
-    const int slices[4] = {4, 8, 16, 32};
+    // per class, stage by stage: the persistent grid (blocks per compute unit)
+    // with which the class's launches run fastest on these inputs
+    const int per_cu[4] = {1, 2, 4, 8};
     for (auto& c : b->classes) {
-        bst_plan_s& p = *c.plan;
-        float best = 1e30f;
-        int best_s = p.gather_slices;
-        for (int si : slices) {
-            p.gather_slices = si;
-            e = launch_class(b, c, ws, s);  // warm
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventRecord(t0, s);
-            for (int r = 0; e == hipSuccess && r < 2; ++r) e = launch_class(b, c, ws, s);
-            if (e == hipSuccess) e = hipEventRecord(t1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(t1);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-            if (e != hipSuccess) break;
-            if (ms < best) {
-                best = ms;
-                best_s = si;
+        for (int stage = 0; !c.regular && stage < kStages && e == hipSuccess; ++stage) {
+            float best = 1e30f;
+            int best_blocks = c.blocks[stage];
+            int tried = -1;
+            for (int k : per_cu) {
+                const int blocks = grid_blocks(b, c.n_items[stage], k);
+                if (blocks == tried) continue;  // capped by the item count
+                tried = blocks;
+                c.blocks[stage] = blocks;
+                e = launch_class(b, c, ws, s);  // warm
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventRecord(t0, s);
+                for (int r = 0; e == hipSuccess && r < 2; ++r) e = launch_class(b, c, ws, s);
+                if (e == hipSuccess) e = hipEventRecord(t1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess) break;
+                if (ms < best) {
+                    best = ms;
+                    best_blocks = blocks;
+                }
             }
+            c.blocks[stage] = best_blocks;
         }
-        p.gather_slices = best_s;
         if (e != hipSuccess) break;
     }
     (void)hipEventDestroy(t0);

@@ -153,6 +153,13 @@ struct SpecArgs {
     const float* mono_part; // [batch][kMassChunks]
     const float* mono_phi;  // [n] phi(t_i - beta dt)
     float mono_inv;         // 1 / (V sum_i phi_i)
+    // uneven batches: per-slice projection counts (nullptr: V for every slice;
+    // else V is the row count of the layout, the largest of them) and the
+    // work list of a persistent launch ((group, block) per item; nullptr: the
+    // launch grid is the work)
+    const int* Vs;
+    const int2* items;
+    int n_items;
 };
 
 struct MassArgs {           // partial sums of each slice's sinogram (monopole mass)
@@ -162,6 +169,7 @@ struct MassArgs {           // partial sums of each slice's sinogram (monopole m
     const float* dark;
     float* part;            // [batch][kMassChunks]
     int n, V;
+    const int* Vs;          // per-slice projection counts, or nullptr
 };
 
 struct GatherArgs {
@@ -185,6 +193,14 @@ struct GatherArgs {
     const int2* tent_cols;
     const float2* patch;
     int tent_w;
+    // uneven batches: per-slice projection counts (nullptr: V for all; else
+    // V is the layout's row count), the origin rule's factor (dc_scale =
+    // dc_rule / V of the slice; angles then come from sincospi, ang unused)
+    // and the work list of a persistent launch ((slice, column block) per item)
+    const int* Vs;
+    float dc_rule;
+    const int2* items;
+    int n_items;
 };
 
 struct TentArgs {            // pre-gather of the wide points of the tent rule
@@ -214,6 +230,13 @@ struct RowArgs {
     // rho = rho_px * ((p - N/2)^2 + (q - N/2)^2)
     const float* mono_part;     // [batch][kMassChunks]
     float mono_inv, mono_amp, mono_rho_px;
+    // uneven batches: per-slice projection counts for the monopole mass
+    // (mono_inv is for V), and the work list of a persistent launch
+    // ((slice, block) per item)
+    int V;
+    const int* Vs;
+    const int2* items;
+    int n_items;
 };
 
 struct F64Args {             // the FP64 gradient-check path (k_fp64.hip)
@@ -294,6 +317,15 @@ hipError_t launch_proj_polar(const bst_plan_s& p, const ProjPolarArgs& a, int ba
 
 hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStream_t st);
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st);
+// Persistent launches of uneven batches: one slice per polar group (no
+// interleaving), `blocks` blocks walking the work list in the arguments.
+hipError_t launch_spectrum_items(const bst_plan_s& p, const SpecArgs& a, int batch, int blocks, hipStream_t st);
+hipError_t launch_gather_items(const bst_plan_s& p, const GatherArgs& a, int blocks, hipStream_t st);
+hipError_t launch_row_items(const bst_plan_s& p, const RowArgs& a, int blocks, hipStream_t st);
+// blocks per slice and block shape of the stages (for building work lists)
+int spectrum_blocks_per_slice(const bst_plan_s& p, int V);  // one-slice groups
+int gather_blocks_per_slice(const bst_plan_s& p);
+int row_blocks_per_slice(const bst_plan_s& p, int tiles);
 // copy the interleaved polar spectra out as [batch][V][M/2] complex64 (diagnostics)
 hipError_t launch_polar_extract(const bst_plan_s& p, const float2* polar, float2* out, int batch, hipStream_t st);
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st);

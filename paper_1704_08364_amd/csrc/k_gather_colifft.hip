@@ -73,10 +73,10 @@ __device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t r, unsigned off)
     return make_float4(__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3]));
 }
 
-template <int LOGG>
+template <int LOGG, int QV = kPolarSlices>
 struct GatherCfg {
     static constexpr int G = 1 << LOGG;
-    static constexpr int Q = kPolarSlices;
+    static constexpr int Q = QV;                         // slices per polar group
     static constexpr int E = Q == 4 ? 16 : 8;            // points (values) per thread
     static constexpr int T = G / E;
     static constexpr int CAP = Q == 4 ? 512 : BST_GATHER_THREADS;
@@ -91,6 +91,7 @@ struct GatherCfg {
     // start 16 banks apart and lanes of different columns do not collide
     static constexpr int STRIDE = FftShape<LOGG>::LDS + 8;
     static constexpr int REGION = F * STRIDE;            // one slice's F transforms
+    static constexpr int NREG = Q < 2 ? Q : 2;           // LDS regions (parked slices)
 };
 
 template <int WG>
@@ -110,8 +111,8 @@ __device__ float block_sum(float x, float* red) {
 }
 
 // Interpolation stencil of one Cartesian point, fixed for all slices:
-//   o0      sample index (j0 S + m0: one unit is the kPolarSlices values of
-//           one sample, 32 bytes) of the first radial tap of angle j0; the
+//   o0      sample index (j0 S + m0: one unit is the Q slices' values of
+//           one sample, 8 Q bytes) of the first radial tap of angle j0; the
 //           taps of j1 are one polar row further, or, when j1 wraps to angle
 //           0, (V-1) rows back. Bit 31 flips the conjugation of the j0 taps
 //           (non-uniform angles, below theta_0, where the j0 neighbour is the
@@ -129,7 +130,20 @@ struct Stencil {
     float g, w1;
 };
 constexpr unsigned kOffsetMask = 0x7FFFFFFFu;
-constexpr unsigned kSampleBytes = kPolarSlices * sizeof(float2);  // 32
+
+// Angles of a slice: the plan's table, or (uneven batches, a count per
+// slice) j pi / V formed on the fly; V / pi in FP32.
+struct AngleView {
+    int V;
+    float vpi_f;
+    const double2* ang;  // (cos, sin) theta_j, or nullptr: uniform, from sincospi
+    __device__ __forceinline__ double2 dir(int j) const {
+        if (ang) return ang[j];
+        double s, c;
+        sincospi((double)j / (double)V, &s, &c);
+        return make_double2(c, s);
+    }
+};
 
 // conjugation of the j0 taps of point e: the lower half-plane, flipped by bit
 // e of `flips` (bit 31 of the point's o0, collected once per block)
@@ -143,7 +157,7 @@ __device__ __forceinline__ bool lower_j0(unsigned flips, int e, bool lower) {
 // TENT: a wide point of the tent rule (|bs| <= B_col) gets bit 31 of o0 and
 // its patch slot in the low bits; its polar reads go to the zero slots.
 template <bool NU, bool TENT>
-__device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a) {
+__device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a, const AngleView& av) {
     Stencil st;
     st.o0 = (unsigned)a.zero_slot;
     st.g = st.w1 = 0.f;
@@ -169,16 +183,16 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
     bool flip0 = false;
     if constexpr (!NU) {
         const float th = atan2f((float)y, (float)x);
-        j0 = (int)floorf(th * a.vpi_f);
-        j0 = j0 < 0 ? 0 : (j0 >= a.V ? a.V - 1 : j0);
-        const double2 cs = a.ang[j0];
+        j0 = (int)floorf(th * av.vpi_f);
+        j0 = j0 < 0 ? 0 : (j0 >= av.V ? av.V - 1 : j0);
+        const double2 cs = av.dir(j0);
         const double cross = (double)y * cs.x - (double)x * cs.y;
         const double dot = (double)x * cs.x + (double)y * cs.y;
-        f = atan2f((float)cross, (float)dot) * a.vpi_f;
+        f = atan2f((float)cross, (float)dot) * av.vpi_f;
         if (f < 0.f) {
             if (j0 > 0) { j0 -= 1; f += 1.f; } else { f = 0.f; }
         } else if (f >= 1.f) {
-            if (j0 < a.V - 1) { j0 += 1; f -= 1.f; } else { f = 1.f; }
+            if (j0 < av.V - 1) { j0 += 1; f -= 1.f; } else { f = 1.f; }
         }
     } else {
         // theta_j <= theta exactly when the cross product e_j x u is >= 0 (both
@@ -209,7 +223,7 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
     }
     // past theta_{V-1} the neighbour is theta_0 + pi: conjugated (both
     // neighbours of a point below theta_0 are already in place)
-    const bool wrap = (j0 + 1 == a.V);
+    const bool wrap = (j0 + 1 == av.V);
     const bool conj1 = lower != (wrap && !flip0);
     st.o0 = (unsigned)(j0 * a.S + m0) | ((unsigned)flip0 << 31);
     st.g = __uint_as_float(__float_as_uint((float)(r - mf)) | ((unsigned)wrap << 31));
@@ -226,11 +240,6 @@ __device__ __forceinline__ void store_streaming(float2* p, float2 v) {
     __builtin_nontemporal_store(t, reinterpret_cast<f2v*>(p));
 }
 
-// Slice k of a tap's sample: its 16-byte parts hold slices (0, 1), (2, 3).
-__device__ __forceinline__ float2 slice_of(const float4* q, int k) {
-    const float4& h = q[k >> 1];
-    return (k & 1) ? make_float2(h.z, h.w) : make_float2(h.x, h.y);
-}
 // Keys cubic convolution (a = -1/2) over samples m0-1 .. m0+2 at fraction g:
 // the Catmull-Rom weights.
 __device__ __forceinline__ float2 keys4(float2 sm, float2 s0, float2 s1, float2 s2, float g) {
@@ -254,22 +263,27 @@ __device__ __forceinline__ float2 angular(float2 u0, float2 u1, float w1, bool l
 // One polar row's taps for the Q slices: linear taps read the samples m0,
 // m0+1 (16 Q bytes), cubic taps m0-1 .. m0+2 (32 Q bytes); then their radial
 // values.
-constexpr int kParts = kPolarSlices / 2;  // 16-byte parts per sample
-template <int TAPS>
-__device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t P, unsigned off, float4 (&q)[TAPS * kParts]) {
+template <int TAPS, int Q>
+__device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t P, unsigned off, float4 (&q)[TAPS * Q / 2]) {
 #pragma unroll
-    for (int i = 0; i < TAPS * kParts; ++i) q[i] = load16(P, off + 16u * i);
+    for (int i = 0; i < TAPS * Q / 2; ++i) q[i] = load16(P, off + 16u * i);
 }
-template <int TAPS>
-__device__ __forceinline__ void radial_row(const float4 (&q)[TAPS * kParts], float g, float2 (&u)[kPolarSlices]) {
-    constexpr int H = kParts;
+// value of slice k at tap t: complex number t Q + k of the row's run
+template <int Q>
+__device__ __forceinline__ float2 tap(const float4* q, int t, int k) {
+    const int i = t * Q + k;
+    const float4& h = q[i >> 1];
+    return (i & 1) ? make_float2(h.z, h.w) : make_float2(h.x, h.y);
+}
+template <int TAPS, int Q>
+__device__ __forceinline__ void radial_row(const float4 (&q)[TAPS * Q / 2], float g, float2 (&u)[Q]) {
 #pragma unroll
-    for (int k = 0; k < kPolarSlices; ++k) {
+    for (int k = 0; k < Q; ++k) {
         if constexpr (TAPS == 2) {
-            const float2 x0 = slice_of(q, k), x1 = slice_of(q + H, k);
+            const float2 x0 = tap<Q>(q, 0, k), x1 = tap<Q>(q, 1, k);
             u[k] = make_float2(fmaf(g, x1.x - x0.x, x0.x), fmaf(g, x1.y - x0.y, x0.y));
         } else {
-            u[k] = keys4(slice_of(q, k), slice_of(q + H, k), slice_of(q + 2 * H, k), slice_of(q + 3 * H, k), g);
+            u[k] = keys4(tap<Q>(q, 0, k), tap<Q>(q, 1, k), tap<Q>(q, 2, k), tap<Q>(q, 3, k), g);
         }
     }
 }
@@ -287,18 +301,22 @@ __device__ __forceinline__ void radial_row(const float4 (&q)[TAPS * kParts], flo
 #define BST_GATHER_INFLIGHT_OTHER 1
 #endif
 
-template <int LOGG, int TAPS, bool NU, bool TENT>
-__global__ void __launch_bounds__((GatherCfg<LOGG>::WG))
-__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft(GatherArgs a) {
-    using C = GatherCfg<LOGG>;
+// One block's work: columns lblock * F .. + F - 1 for the slices
+// [s_begin, s_end) (whole groups of Q). The slices share one angle set: the
+// plan's, or (per-slice counts) that of slice s_begin.
+template <int LOGG, int TAPS, bool NU, bool TENT, int Q>
+__device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int s_begin, int s_end) {
+    using C = GatherCfg<LOGG, Q>;
     constexpr int G = C::G, T = C::T, F = C::F, E = C::E;
-    constexpr int Q = kPolarSlices;
-    __shared__ float2 lds[2 * C::REGION];  // two regions: one slice's F transforms each
+    constexpr unsigned kSampleBytes = Q * sizeof(float2);
+    __shared__ float2 lds[C::NREG * C::REGION];  // one region per parked slice
     __shared__ float red[(C::WG + 63) / 64];
     const int fid = threadIdx.x % F;
     const int j = threadIdx.x / F;
-    const int lblock = xcd_contiguous(blockIdx.x, gridDim.x);
     const int col = lblock * F + fid;
+    const int V = a.Vs ? a.Vs[s_begin] : a.V;  // this chunk's projections
+    const AngleView av{V, a.Vs ? (float)((double)V / M_PI) : a.vpi_f, a.Vs ? nullptr : a.ang};
+    const float dc_scale = a.Vs ? a.dc_rule / (float)V : a.dc_scale;
     const bool live = col < G / 2;
     const FftTwiddles<LOGG, +1, E> tw(j, a.tw);
 
@@ -308,7 +326,7 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
     constexpr int CH = E == 8 ? 2 : 4;
     constexpr int NW = 3;  // words per stencil
     Stencil pt[E];
-    static_assert(2 * C::REGION * 2 >= C::WG * CH * NW, "stencil staging needs LDS");
+    static_assert(C::NREG * C::REGION * 2 >= C::WG * CH * NW, "stencil staging needs LDS");
     unsigned* stage = reinterpret_cast<unsigned*>(lds);
 #pragma unroll
     for (int c0 = 0; c0 < E; c0 += CH) {
@@ -316,7 +334,7 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
         for (int h = 0; h < CH; ++h) {
             const int b = j + (c0 + h) * T;
             const int bs = b < G / 2 ? b : b - G;
-            const Stencil st = point_stencil<NU, TENT>(live ? col : 0, live ? bs : 0, a);
+            const Stencil st = point_stencil<NU, TENT>(live ? col : 0, live ? bs : 0, a, av);
             unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
             d[0] = st.o0;
             d[C::WG] = __float_as_uint(st.g);
@@ -343,14 +361,12 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
     }
     const unsigned zoff = (unsigned)a.zero_slot * kSampleBytes;
 
-    const int s_begin = blockIdx.y * a.slices_per_block;  // a multiple of Q
-    const int s_end = min(a.batch, s_begin + a.slices_per_block);
     const int half_n = a.N >> 1;
     const unsigned group_bytes = (unsigned)a.V * (unsigned)a.S * kSampleBytes;
     const unsigned row_bytes = (unsigned)a.S * kSampleBytes;
-    const unsigned wrap_bytes = 0u - (unsigned)(a.V - 1) * row_bytes;  // back to row 0
+    const unsigned wrap_bytes = 0u - (unsigned)(V - 1) * row_bytes;  // back to row 0
     float2* R0 = lds + fid * C::STRIDE;
-    float2* R1 = R0 + C::REGION;
+    float2* R1 = R0 + (C::NREG - 1) * C::REGION;
     for (int s0 = s_begin; s0 < s_end; s0 += Q) {
         const int nq = min(Q, s_end - s0);  // slices of this group in the batch
         // Re-derive the lane's row index each group: otherwise every address
@@ -365,8 +381,8 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
             for (int k = 0; k < Q; ++k) {
                 float acc = 0.f;
                 if (k < nq)
-                    for (int i = threadIdx.x; i < a.V; i += C::WG) acc += a.dc[(size_t)(s0 + k) * a.V + i];
-                dcv[k] = block_sum<C::WG>(acc, red) * a.dc_scale;
+                    for (int i = threadIdx.x; i < V; i += C::WG) acc += a.dc[(size_t)(s0 + k) * a.V + i];
+                dcv[k] = block_sum<C::WG>(acc, red) * dc_scale;
             }
         }
         // gather: slices 0 and 1 of the group wait in the two LDS regions,
@@ -377,7 +393,7 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
         static_assert(E % H == 0, "whole groups of points");
 #pragma unroll
         for (int h0 = 0; h0 < E; h0 += H) {
-            float4 qa[H][TAPS * kParts], qb[H][TAPS * kParts];
+            float4 qa[H][TAPS * Q / 2], qb[H][TAPS * Q / 2];
 #pragma unroll
             for (int i = 0; i < H; ++i) {
                 const Stencil& st = pt[h0 + i];
@@ -386,8 +402,8 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
                 const unsigned o0 = BST_IDX((TENT && ((wide >> (h0 + i)) & 1u)) ? zoff : st.o0 * kSampleBytes,
                                             group_bytes - kLast, 0);
                 const unsigned o1 = BST_IDX(o0 + (wrap ? wrap_bytes : row_bytes), group_bytes - kLast, 0);
-                load_row<TAPS>(P, o0, qa[i]);
-                load_row<TAPS>(P, o1, qb[i]);
+                load_row<TAPS, Q>(P, o0, qa[i]);
+                load_row<TAPS, Q>(P, o1, qb[i]);
             }
 #pragma unroll
             for (int i = 0; i < H; ++i) {
@@ -395,8 +411,8 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
                 const Stencil& st = pt[e];
                 const float g = fabsf(st.g);
                 float2 u0[Q], u1[Q], val[Q];
-                radial_row<TAPS>(qa[i], g, u0);
-                radial_row<TAPS>(qb[i], g, u1);
+                radial_row<TAPS, Q>(qa[i], g, u0);
+                radial_row<TAPS, Q>(qb[i], g, u1);
 #pragma unroll
                 for (int k = 0; k < Q; ++k) val[k] = angular(u0[k], u1[k], st.w1, lower_j0<NU>(flips, e, 2 * e >= E));
                 if constexpr (TENT) {
@@ -415,7 +431,7 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
                     for (int k = 0; k < Q; ++k) val[k] = make_float2(dcv[k], 0.f);
                 }
                 R0[lds_pad(jv + e * T)] = val[0];
-                R1[lds_pad(jv + e * T)] = val[1];
+                if constexpr (Q > 1) R1[lds_pad(jv + e * T)] = val[1];
                 if constexpr (Q > 2) {
                     hold0[e] = val[2];
                     hold1[e] = val[3];
@@ -461,6 +477,31 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft
                 }
             }
         }
+    }
+}
+
+template <int LOGG, int TAPS, bool NU, bool TENT>
+__global__ void __launch_bounds__((GatherCfg<LOGG>::WG))
+__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft(GatherArgs a) {
+    const int s_begin = blockIdx.y * a.slices_per_block;  // a multiple of Q
+    gather_body<LOGG, TAPS, NU, TENT, kPolarSlices>(a, xcd_contiguous(blockIdx.x, gridDim.x), s_begin,
+                                                    min(a.batch, s_begin + a.slices_per_block));
+}
+
+// Persistent launch of uneven batches (one slice per group, uniform angles):
+// every block walks the work list (slice, column block) in steps of the grid,
+// the blocks of one XCD taking contiguous items (the neighbouring columns of
+// one slice, which read the same polar lines).
+template <int LOGG, int TAPS>
+__global__ void __launch_bounds__((GatherCfg<LOGG, 1>::WG))
+__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG, 1>::WAVES, 8))) k_gather_items(GatherArgs a) {
+    const int local = xcd_contiguous(blockIdx.x, gridDim.x);
+    for (int base = 0; base < a.n_items; base += gridDim.x) {
+        const int it = base + local;
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        __syncthreads();  // the previous item's LDS reads are done
+        gather_body<LOGG, TAPS, false, false, 1>(a, w.y, w.x, w.x + 1);
     }
 }
 
@@ -632,6 +673,53 @@ hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStr
                            0, st, a, batch);
     hipLaunchKernelGGL(k_tent_reduce, dim3((a.W + 255) / 256, batch), dim3(256), 0, st, a);
     return hipGetLastError();
+}
+
+template <int LOGG>
+static hipError_t launch_gather_items_t(const GatherArgs& a, int taps, int blocks, hipStream_t st) {
+    using C = GatherCfg<LOGG, 1>;
+    if (taps == 4) hipLaunchKernelGGL((k_gather_items<LOGG, 4>), dim3(blocks), dim3(C::WG), 0, st, a);
+    else hipLaunchKernelGGL((k_gather_items<LOGG, 2>), dim3(blocks), dim3(C::WG), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_items(const bst_plan_s& p, const GatherArgs& a, int blocks, hipStream_t st) {
+    if (a.tent_cols || !a.Vs) return hipErrorInvalidValue;
+    switch (p.logG) {
+        case 4: return launch_gather_items_t<4>(a, p.taps, blocks, st);
+        case 5: return launch_gather_items_t<5>(a, p.taps, blocks, st);
+        case 6: return launch_gather_items_t<6>(a, p.taps, blocks, st);
+        case 7: return launch_gather_items_t<7>(a, p.taps, blocks, st);
+        case 8: return launch_gather_items_t<8>(a, p.taps, blocks, st);
+        case 9: return launch_gather_items_t<9>(a, p.taps, blocks, st);
+        case 10: return launch_gather_items_t<10>(a, p.taps, blocks, st);
+        case 11: return launch_gather_items_t<11>(a, p.taps, blocks, st);
+        case 12: return launch_gather_items_t<12>(a, p.taps, blocks, st);
+        case 13: return launch_gather_items_t<13>(a, p.taps, blocks, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LOGG>
+static int gather_cols_t() {
+    using C = GatherCfg<LOGG, 1>;
+    return (C::G / 2 + C::F - 1) / C::F;
+}
+
+int gather_blocks_per_slice(const bst_plan_s& p) {
+    switch (p.logG) {
+        case 4: return gather_cols_t<4>();
+        case 5: return gather_cols_t<5>();
+        case 6: return gather_cols_t<6>();
+        case 7: return gather_cols_t<7>();
+        case 8: return gather_cols_t<8>();
+        case 9: return gather_cols_t<9>();
+        case 10: return gather_cols_t<10>();
+        case 11: return gather_cols_t<11>();
+        case 12: return gather_cols_t<12>();
+        case 13: return gather_cols_t<13>();
+        default: return 0;
+    }
 }
 
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st) {

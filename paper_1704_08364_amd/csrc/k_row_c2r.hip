@@ -44,8 +44,9 @@ struct RowCfg {
 
 // MONO: adds m b_phi(u), the closed-form backprojection of the subtracted
 // monopole, to every output pixel.
+// Block (bx, s): row-pair groups bx * tiles .. of slice s.
 template <int LOGG, bool MONO>
-__global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
+__device__ __forceinline__ void row_body(const RowArgs& a, int bx, int s) {
     using C = RowCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
     // regions 8 float2 (16 banks) apart, so interleaved lanes of different row
@@ -57,13 +58,15 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     const int fid = threadIdx.x % C::F;
     const int j = threadIdx.x / C::F;
     float2* my = lds + fid * STRIDE;
-    const int s = blockIdx.y;
     const int groups = a.N / (2 * C::F);             // row-pair groups (tiles) per slice
-    const int g0 = blockIdx.x * a.tiles;
+    const int g0 = bx * a.tiles;
     float* const img_s = a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N;
     const FftTwiddles<LOGG, +1, 16> tw(j, a.tw);
     float mamp = 0.f;
-    if constexpr (MONO) mamp = monopole_mass(a.mono_part, s, a.mono_inv) * a.mono_amp;
+    if constexpr (MONO) {
+        const float inv = a.Vs ? a.mono_inv * (float)a.V / (float)a.Vs[s] : a.mono_inv;
+        mamp = monopole_mass(a.mono_part, s, inv) * a.mono_amp;
+    }
 
     // Thread j's slots e < 8 are k = j + e*T < G/2: the block reads every
     // stored column once (all loads first, no branch between them) and puts
@@ -138,6 +141,25 @@ __global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
     }
 }
 
+template <int LOGG, bool MONO>
+__global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_c2r(RowArgs a) {
+    row_body<LOGG, MONO>(a, blockIdx.x, blockIdx.y);
+}
+
+// Persistent launch of uneven batches: every block walks the work list
+// (slice, block) in steps of the grid.
+template <int LOGG, bool MONO>
+__global__ void __launch_bounds__(RowCfg<LOGG>::WG) k_row_items(RowArgs a) {
+    const int local = xcd_contiguous(blockIdx.x, gridDim.x);
+    for (int base = 0; base < a.n_items; base += gridDim.x) {
+        const int it = base + local;
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        __syncthreads();  // the previous item's LDS reads are done
+        row_body<LOGG, MONO>(a, w.y, w.x);
+    }
+}
+
 template <int LOGG>
 static hipError_t launch_row_t(const RowArgs& a0, int batch, hipStream_t st) {
     using C = RowCfg<LOGG>;
@@ -152,6 +174,55 @@ static hipError_t launch_row_t(const RowArgs& a0, int batch, hipStream_t st) {
     if (a.mono_part) hipLaunchKernelGGL((k_row_c2r<LOGG, true>), grid, dim3(C::WG), 0, st, a);
     else hipLaunchKernelGGL((k_row_c2r<LOGG, false>), grid, dim3(C::WG), 0, st, a);
     return hipGetLastError();
+}
+
+template <int LOGG>
+static hipError_t launch_row_items_t(const RowArgs& a, int blocks, hipStream_t st) {
+    using C = RowCfg<LOGG>;
+    if (a.tiles < 1 || a.tiles > C::MAX_TILES) return hipErrorInvalidValue;
+    if (a.mono_part) hipLaunchKernelGGL((k_row_items<LOGG, true>), dim3(blocks), dim3(C::WG), 0, st, a);
+    else hipLaunchKernelGGL((k_row_items<LOGG, false>), dim3(blocks), dim3(C::WG), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_items(const bst_plan_s& p, const RowArgs& a, int blocks, hipStream_t st) {
+    switch (p.logG) {
+        case 4: return launch_row_items_t<4>(a, blocks, st);
+        case 5: return launch_row_items_t<5>(a, blocks, st);
+        case 6: return launch_row_items_t<6>(a, blocks, st);
+        case 7: return launch_row_items_t<7>(a, blocks, st);
+        case 8: return launch_row_items_t<8>(a, blocks, st);
+        case 9: return launch_row_items_t<9>(a, blocks, st);
+        case 10: return launch_row_items_t<10>(a, blocks, st);
+        case 11: return launch_row_items_t<11>(a, blocks, st);
+        case 12: return launch_row_items_t<12>(a, blocks, st);
+        case 13: return launch_row_items_t<13>(a, blocks, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LOGG>
+static int row_blocks_t(int N, int tiles) {
+    using C = RowCfg<LOGG>;
+    const int groups = N / (2 * C::F);
+    tiles = tiles < 1 ? 1 : (tiles > C::MAX_TILES ? C::MAX_TILES : tiles);
+    return (groups + tiles - 1) / tiles;
+}
+
+int row_blocks_per_slice(const bst_plan_s& p, int tiles) {
+    switch (p.logG) {
+        case 4: return row_blocks_t<4>(p.N, tiles);
+        case 5: return row_blocks_t<5>(p.N, tiles);
+        case 6: return row_blocks_t<6>(p.N, tiles);
+        case 7: return row_blocks_t<7>(p.N, tiles);
+        case 8: return row_blocks_t<8>(p.N, tiles);
+        case 9: return row_blocks_t<9>(p.N, tiles);
+        case 10: return row_blocks_t<10>(p.N, tiles);
+        case 11: return row_blocks_t<11>(p.N, tiles);
+        case 12: return row_blocks_t<12>(p.N, tiles);
+        case 13: return row_blocks_t<13>(p.N, tiles);
+        default: return 0;
+    }
 }
 
 hipError_t launch_row_c2r(const bst_plan_s& p, const RowArgs& a, int batch, hipStream_t st) {

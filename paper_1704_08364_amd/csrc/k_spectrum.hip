@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(kMassThreads) k_mass(MassArgs a) {
     __shared__ float red[kMassThreads / 64];
     const int c = blockIdx.x, s = blockIdx.y;
     const float* base = a.sino_list ? a.sino_list[s] : a.sino + (size_t)s * a.V * a.n;
-    const int lines = c < a.V ? (a.V - 1 - c) / kMassChunks + 1 : 0;
+    const int V = a.Vs ? a.Vs[s] : a.V;
+    const int lines = c < V ? (V - 1 - c) / kMassChunks + 1 : 0;
     const int logn = __ffs(a.n) - 1;  // n is a power of two
     const long long items = (long long)lines << logn;
     const float* fs = COUNTS ? a.flat + (size_t)s * a.n : nullptr;
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(kMassThreads) k_mass(MassArgs a) {
             const long long itc = ok ? it : 0;
             const int l = (int)(itc >> logn);
             const int i = (int)(itc & (a.n - 1));
-            float v = base[BST_IDX((size_t)(c + l * kMassChunks) * a.n + i, (size_t)a.V * a.n, 0)];
+            float v = base[BST_IDX((size_t)(c + l * kMassChunks) * a.n + i, (size_t)V * a.n, 0)];
             if constexpr (COUNTS) {
                 const float inv = 1.0f / (fs[i] - ds[i]);
                 v = -logf((v - ds[i]) * inv);
@@ -93,11 +94,11 @@ __global__ void __launch_bounds__(kMassThreads) k_mass(MassArgs a) {
     }
 }
 
-template <int LOGM>
+template <int LOGM, int Q>
 struct SpecCfg {
     static constexpr int M = 1 << LOGM;
     static constexpr int T = M / 16;                     // threads per transform
-    static constexpr int TP = kPolarSlices * T;          // per projection pair: one transform per slice
+    static constexpr int TP = Q * T;                     // per projection pair: one transform per slice
     static constexpr int FP = TP >= 512 ? 1 : 512 / TP;  // projection pairs per block
     static constexpr int WG = FP * TP;
     static constexpr int MV = (M / 2) / TP;              // output samples per thread and pair
@@ -122,25 +123,25 @@ constexpr int spec_waves() { return (MONO && COUNTS && LOGP == 0) ? 3 : BST_SPEC
 //   polar[((g V + j) S + lead + m) kPolarSlices + s mod kPolarSlices].
 // Slices of the last group past the batch read zeros.
 // MONO: monopole subtraction, y[i] - m phi[i] (m from the partial sums).
-template <int LOGM, int LOGP, bool COUNTS, bool MONO>
-__global__ void __launch_bounds__(SpecCfg<LOGM>::WG)
-__attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spectrum(SpecArgs a, int batch) {
-    using C = SpecCfg<LOGM>;
+// Q: slices per polar group (kPolarSlices for ordinary batches, 1 for the
+// persistent launches of uneven batches). Block (bx, g): pair blocks bx of
+// group g.
+template <int LOGM, int LOGP, bool COUNTS, bool MONO, int Q>
+__device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int bx, int g) {
+    using C = SpecCfg<LOGM, Q>;
     constexpr int M = C::M, T = C::T, TP = C::TP;
     constexpr int E0 = 8 >> LOGP;
     constexpr int NQ = 2 * E0;  // data slots per thread
-    constexpr int Q = kPolarSlices;
     __shared__ float2 lds[Q * C::FP * FftShape<LOGM>::LDS];
     const int u = threadIdx.x / T;        // transform: pair u / Q, slice u % Q
     const int j = threadIdx.x - u * T;
     const int pl = u / Q, k = u % Q;
     float2* my = lds + u * FftShape<LOGM>::LDS;
-    const int g = blockIdx.y;
     const int s = g * Q + k;
     const bool vs = s < batch;
     const int h = a.n >> 1;
     constexpr int PAIRS = spec_pairs<LOGP, COUNTS, MONO>();
-    const int npairs = (a.V + 1) >> 1;
+    const int npairs = (a.V + 1) >> 1;  // pairs of the layout's rows
 
     // detector bin of data slot q: positions e = q (q < E0) and e = 16 - 2*E0 + q (q >= E0)
     auto bin_of = [&](int q) {
@@ -150,6 +151,7 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
     };
     const int sc = vs ? s : 0;  // a slice past the batch reads slice 0, dropped below
     const float* base = a.sino_list ? a.sino_list[sc] : a.sino + (size_t)sc * a.V * a.n;
+    const int Vk = a.Vs ? a.Vs[sc] : a.V;  // this slice's projections
 
     // Every global read of the thread is issued up front with no branch in
     // between: the data slots of both lines of the first pair (a missing
@@ -158,8 +160,8 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
     // the twiddle anchors; these last are the same for every pair.
     auto load_lines = [&](int pair, float (&ra)[NQ], float (&rb)[NQ]) {
         const int ja = 2 * pair, jb = 2 * pair + 1;
-        const float* ya = base + (size_t)(ja < a.V ? ja : 0) * a.n;
-        const float* yb = base + (size_t)(jb < a.V ? jb : 0) * a.n;
+        const float* ya = base + (size_t)(ja < Vk ? ja : 0) * a.n;
+        const float* yb = base + (size_t)(jb < Vk ? jb : 0) * a.n;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int i = BST_IDX(bin_of(q), a.n, 1);
@@ -168,7 +170,7 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
         }
     };
     float ra[NQ], rb[NQ], w[NQ];
-    const int pair0 = blockIdx.x * PAIRS * C::FP + pl;
+    const int pair0 = bx * PAIRS * C::FP + pl;
     load_lines(pair0 < npairs ? pair0 : 0, ra, rb);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) w[q] = a.taper[bin_of(q)];
@@ -185,7 +187,7 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
     }
     float mph[MONO ? NQ : 1];  // m phi at the thread's bins
     if constexpr (MONO) {
-        const float m = monopole_mass(a.mono_part, sc, a.mono_inv);
+        const float m = monopole_mass(a.mono_part, sc, a.Vs ? a.mono_inv * (float)a.V / (float)Vk : a.mono_inv);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) mph[q] = m * a.mono_phi[bin_of(q)];
     }
@@ -200,7 +202,7 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
     for (int it = 0; it < PAIRS; ++it) {
         const int pair = pair0 + it * C::FP;
         const int ja = 2 * pair, jb = 2 * pair + 1;
-        const bool va = ja < a.V && vs, vb = jb < a.V && vs;
+        const bool va = ja < Vk && vs, vb = jb < Vk && vs;
         float na[NQ], nb[NQ];
         if (it + 1 < PAIRS) {
             const int nx = pair + C::FP;
@@ -246,9 +248,20 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
         // rows ja and jb with the group's slices interleaved
         const bool wa = ja < a.V, wb = jb < a.V;
         const float2* z0 = lds + (Q * pl) * FftShape<LOGM>::LDS;
-        float4* rowa = reinterpret_cast<float4*>(a.polar + (((size_t)g * a.V + (wa ? ja : 0)) * a.S) * Q);
-        float4* rowb = reinterpret_cast<float4*>(a.polar + (((size_t)g * a.V + (wb ? jb : 0)) * a.S) * Q);
-        constexpr int H = Q / 2;  // 16-byte parts per sample
+        float2* rowa = a.polar + (((size_t)g * a.V + (wa ? ja : 0)) * a.S) * Q;
+        float2* rowb = a.polar + (((size_t)g * a.V + (wb ? jb : 0)) * a.S) * Q;
+        // one sample of the Q slices: 8 Q bytes, as float2 (Q = 1) or float4 parts
+        auto put = [&](float2* row, int slot, const float2 (&y)[Q], bool conj) {
+            const float c = conj ? -1.f : 1.f;
+            if constexpr (Q == 1) {
+                row[slot] = make_float2(y[0].x, c * y[0].y);
+            } else {
+                float4* r4 = reinterpret_cast<float4*>(row + (size_t)slot * Q);
+#pragma unroll
+                for (int t = 0; t < Q / 2; ++t)
+                    r4[t] = make_float4(y[2 * t].x, c * y[2 * t].y, y[2 * t + 1].x, c * y[2 * t + 1].y);
+            }
+        };
         int qv = qp;
         asm volatile("" : "+v"(qv));
 #pragma unroll
@@ -256,34 +269,31 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
             const int m = qv + i * TP;  // 0 .. M/2-1
             const int mc = (M - m) & (M - 1);
             const int slot = BST_IDX(a.lead + m, a.S, 2);
+            float2 ya[Q], yb[Q];
 #pragma unroll
-            for (int t = 0; t < H; ++t) {
-                float2 ya[2], yb[2];
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    const float2* zt = z0 + (2 * t + d) * FftShape<LOGM>::LDS;
-                    const float2 z = zt[lds_pad(m)], zc = zt[lds_pad(mc)];
-                    ya[d] = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[i]);
-                    yb[d] = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[i]);
-                }
-                if (wa) {
-                    rowa[H * slot + t] = make_float4(ya[0].x, ya[0].y, ya[1].x, ya[1].y);
-                    // the sample before 0 (cubic radial taps): Yh(-sigma) = conj Yh(sigma)
-                    if (a.lead && m == 1) rowa[t] = make_float4(ya[0].x, -ya[0].y, ya[1].x, -ya[1].y);
-                }
-                if (wb) {
-                    rowb[H * slot + t] = make_float4(yb[0].x, yb[0].y, yb[1].x, yb[1].y);
-                    if (a.lead && m == 1) rowb[t] = make_float4(yb[0].x, -yb[0].y, yb[1].x, -yb[1].y);
-                }
+            for (int d = 0; d < Q; ++d) {
+                const float2* zt = z0 + d * FftShape<LOGM>::LDS;
+                const float2 z = zt[lds_pad(m)], zc = zt[lds_pad(mc)];
+                ya[d] = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[i]);
+                yb[d] = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[i]);
+            }
+            if (wa) {
+                put(rowa, slot, ya, false);
+                // the sample before 0 (cubic radial taps): Yh(-sigma) = conj Yh(sigma)
+                if (a.lead && m == 1) put(rowa, 0, ya, true);
+            }
+            if (wb) {
+                put(rowb, slot, yb, false);
+                if (a.lead && m == 1) put(rowb, 0, yb, true);
             }
         }
         for (int z = qv; z < a.tail; z += TP) {
             const int slot = BST_IDX(a.lead + M / 2 + z, a.S, 2);
+            float2 zero[Q];
 #pragma unroll
-            for (int t = 0; t < H; ++t) {
-                if (wa) rowa[H * slot + t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (wb) rowb[H * slot + t] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+            for (int d = 0; d < Q; ++d) zero[d] = make_float2(0.f, 0.f);
+            if (wa) put(rowa, slot, zero, false);
+            if (wb) put(rowb, slot, zero, false);
         }
         if (it + 1 < PAIRS) {
             __syncthreads();  // the next transforms overwrite this LDS
@@ -297,15 +307,36 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
 }
 
 template <int LOGM, int LOGP, bool COUNTS, bool MONO>
+__global__ void __launch_bounds__((SpecCfg<LOGM, kPolarSlices>::WG))
+__attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spectrum(SpecArgs a, int batch) {
+    spectrum_body<LOGM, LOGP, COUNTS, MONO, kPolarSlices>(a, batch, blockIdx.x, blockIdx.y);
+}
+
+// Persistent launch: every block walks the work list (group, pair block) in
+// steps of the grid, blocks of one XCD taking contiguous items.
+template <int LOGM, int LOGP, bool COUNTS, bool MONO>
+__global__ void __launch_bounds__((SpecCfg<LOGM, 1>::WG))
+__attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spectrum_items(SpecArgs a, int batch) {
+    const int local = xcd_contiguous(blockIdx.x, gridDim.x);
+    for (int base = 0; base < a.n_items; base += gridDim.x) {
+        const int it = base + local;
+        if (it >= a.n_items) break;
+        const int2 w = a.items[it];
+        __syncthreads();  // the previous item's LDS reads are done
+        spectrum_body<LOGM, LOGP, COUNTS, MONO, 1>(a, batch, w.y, w.x);
+    }
+}
+
+template <int LOGM, int LOGP, bool COUNTS, bool MONO>
 static void launch_spec_k(const SpecArgs& a, int blocks, int batch, hipStream_t st) {
-    using C = SpecCfg<LOGM>;
+    using C = SpecCfg<LOGM, kPolarSlices>;
     const int groups = (batch + kPolarSlices - 1) / kPolarSlices;
     hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, COUNTS, MONO>), dim3(blocks, groups), dim3(C::WG), 0, st, a, batch);
 }
 
 template <int LOGM, int LOGP>
 static hipError_t launch_spec_t(const SpecArgs& a, int batch, hipStream_t st) {
-    using C = SpecCfg<LOGM>;
+    using C = SpecCfg<LOGM, kPolarSlices>;
     const bool counts = a.flat != nullptr, mono = a.mono_part != nullptr;
     const int pairs = (a.V + 1) / 2;
     auto blocks = [&](int per) { return (pairs + C::FP * per - 1) / (C::FP * per); };
@@ -353,6 +384,76 @@ hipError_t launch_mass(const bst_plan_s& p, const MassArgs& a, int batch, hipStr
     if (a.flat != nullptr) hipLaunchKernelGGL(k_mass<true>, grid, dim3(kMassThreads), 0, st, a);
     else hipLaunchKernelGGL(k_mass<false>, grid, dim3(kMassThreads), 0, st, a);
     return hipGetLastError();
+}
+
+// ---- persistent launches (uneven batches: one slice per group) ----------------
+
+template <int LOGM, int LOGP>
+static hipError_t launch_spec_items_t(const SpecArgs& a, int batch, int blocks, hipStream_t st) {
+    using C = SpecCfg<LOGM, 1>;
+    if (a.mono_part)
+        hipLaunchKernelGGL((k_spectrum_items<LOGM, LOGP, false, true>), dim3(blocks), dim3(C::WG), 0, st, a, batch);
+    else
+        hipLaunchKernelGGL((k_spectrum_items<LOGM, LOGP, false, false>), dim3(blocks), dim3(C::WG), 0, st, a, batch);
+    return hipGetLastError();
+}
+
+template <int LOGM>
+static hipError_t launch_spec_items_p(const SpecArgs& a, int pr, int batch, int blocks, hipStream_t st) {
+    if constexpr (LOGM >= 4) {
+        if (pr == 1) return launch_spec_items_t<LOGM, 0>(a, batch, blocks, st);
+    }
+    if constexpr (LOGM >= 5) {
+        if (pr == 2) return launch_spec_items_t<LOGM, 1>(a, batch, blocks, st);
+    }
+    if constexpr (LOGM >= 6) {
+        if (pr == 4) return launch_spec_items_t<LOGM, 2>(a, batch, blocks, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_spectrum_items(const bst_plan_s& p, const SpecArgs& a, int batch, int blocks, hipStream_t st) {
+    if (a.flat) return hipErrorInvalidValue;  // raw counts are not batched
+    const int pr = p.prm.pad_radial;
+    switch (p.logM) {
+        case 4: return launch_spec_items_p<4>(a, pr, batch, blocks, st);
+        case 5: return launch_spec_items_p<5>(a, pr, batch, blocks, st);
+        case 6: return launch_spec_items_p<6>(a, pr, batch, blocks, st);
+        case 7: return launch_spec_items_p<7>(a, pr, batch, blocks, st);
+        case 8: return launch_spec_items_p<8>(a, pr, batch, blocks, st);
+        case 9: return launch_spec_items_p<9>(a, pr, batch, blocks, st);
+        case 10: return launch_spec_items_p<10>(a, pr, batch, blocks, st);
+        case 11: return launch_spec_items_p<11>(a, pr, batch, blocks, st);
+        case 12: return launch_spec_items_p<12>(a, pr, batch, blocks, st);
+        case 13: return launch_spec_items_p<13>(a, pr, batch, blocks, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LOGM>
+static int spec_blocks_t(int pr, bool mono, int V) {
+    using C = SpecCfg<LOGM, 1>;
+    const int per = (pr >= 2 && !mono) ? BST_SPEC_PAIRS : 1;  // as spec_pairs
+    const int pairs = (V + 1) / 2;
+    return (pairs + C::FP * per - 1) / (C::FP * per);
+}
+
+int spectrum_blocks_per_slice(const bst_plan_s& p, int V) {
+    const int pr = p.prm.pad_radial;
+    const bool mono = p.monopole;
+    switch (p.logM) {
+        case 4: return spec_blocks_t<4>(pr, mono, V);
+        case 5: return spec_blocks_t<5>(pr, mono, V);
+        case 6: return spec_blocks_t<6>(pr, mono, V);
+        case 7: return spec_blocks_t<7>(pr, mono, V);
+        case 8: return spec_blocks_t<8>(pr, mono, V);
+        case 9: return spec_blocks_t<9>(pr, mono, V);
+        case 10: return spec_blocks_t<10>(pr, mono, V);
+        case 11: return spec_blocks_t<11>(pr, mono, V);
+        case 12: return spec_blocks_t<12>(pr, mono, V);
+        case 13: return spec_blocks_t<13>(pr, mono, V);
+        default: return 0;
+    }
 }
 
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st) {

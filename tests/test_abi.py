@@ -168,6 +168,12 @@ def test_batch_create_validates_before_device_work():
     assert L.bst_batch_create(None, 3, n, v, C.byref(h)) == 1
     assert L.bst_batch_create(C.byref(p), 0, n, v, C.byref(h)) == 9
     assert L.bst_batch_create(C.byref(p), 3, n, v, C.byref(h)) == 2  # 100 is not a power of two
+    # per-instance angle counts exclude a shared angle list; FP64 runs one plan at a time
+    th = np.arange(256) * (np.pi / 256)
+    pa, _keep = _params(angles=th)
+    assert L.bst_batch_create(C.byref(pa), 3, n, v, C.byref(h)) == 8
+    pf, _ = _params(dtype="f64")
+    assert L.bst_batch_create(C.byref(pf), 3, n, v, C.byref(h)) == 8
     assert h.value is None
     assert L.bst_batch_destroy(None) == 0
 

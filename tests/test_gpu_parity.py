@@ -874,7 +874,7 @@ def _uneven(B_sizes, seed):
 def test_uneven_batch_matches_oracle_and_replays(P):
     sizes = [(64, 40), (128, 100), (64, 40), (256, 130), (128, 100), (64, 90), (256, 512), (128, 64)]
     batch, sinos, imgs = _uneven(sizes, 77)
-    assert batch.classes() == 6
+    assert batch.classes() == 3                  # one class per detector size
     ws = batch.workspace()
     batch.backproject(sinos, imgs, ws)           # captures the graph
     torch.cuda.synchronize()
@@ -891,6 +891,35 @@ def test_uneven_batch_matches_oracle_and_replays(P):
         batch.backproject(sinos, imgs, ws)
         torch.cuda.synchronize()
         assert torch.equal(imgs, first), f"replay {r}"
+
+
+def test_uneven_batch_of_64_distinct_angle_counts(P):
+    """64 instances over three detector sizes, no two with the same angle
+    count (odd and even, fewer and more angles than bins): each class's plan
+    is built for its largest V and every slice runs with its own V. Every
+    instance against the oracle, then a tuned run and replays against the
+    first."""
+    sizes = [((64, 128, 256)[i % 3], 24 + 7 * i) for i in range(64)]
+    assert len({v for _, v in sizes}) == 64
+    batch, sinos, imgs = _uneven(sizes, 1704)
+    assert batch.classes() == 3
+    ws = batch.workspace()
+    batch.backproject(sinos, imgs, ws)
+    torch.cuda.synchronize()
+    first = imgs.clone()
+    for i, (n, v) in enumerate(sizes):
+        _say(f"[uneven 64] instance {i}: n={n} V={v}")
+        ref = obst.backproject(batch.sino_view(sinos, i).double().cpu().numpy(), Geometry(n, v, n))
+        assert_parity(batch.img_view(first, i).cpu().numpy(), ref)
+    batch.tune(sinos, imgs, ws)
+    for r in range(3):
+        imgs.zero_()
+        _ = (sinos * 2.0).sum()
+        torch.cuda.synchronize()
+        batch.backproject(sinos, imgs, ws)
+        torch.cuda.synchronize()
+        # the tuned grid sizes change which block takes an item, not its arithmetic
+        assert torch.equal(imgs, first), f"tuned replay {r}"
 
 
 def test_uneven_batch_tuned(P):
@@ -983,7 +1012,7 @@ def test_monopole_narrows_the_gap_to_bruteforce(P):
 
 def test_monopole_in_an_uneven_batch(P):
     from paper_1704_08364_amd import Batch
-    sizes = [(64, 40), (128, 100), (64, 40)]
+    sizes = [(64, 40), (128, 100), (64, 57)]
     batch = Batch(sizes, filter="none", monopole_width=0.4)
     gen = torch.Generator(device="cpu")
     gen.manual_seed(5)

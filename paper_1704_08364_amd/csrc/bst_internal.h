@@ -104,6 +104,10 @@ struct TentSizes {
 #endif
 constexpr int kPolarSlices = BST_POLAR_SLICES;
 static_assert(kPolarSlices == 2 || kPolarSlices == 4, "2 or 4 interleaved slices");
+// Slices per polar group of an ordinary batch: cubic radial taps read four
+// samples per row, twice the bytes per slice, and run fastest one slice per
+// group (eight 16-byte reads per point otherwise pile up in flight).
+constexpr int polar_group(int taps) { return taps == 4 ? 1 : kPolarSlices; }
 // slices interleaved in the tent rule's radius-major copy
 constexpr int kTentSlices = 8;
 // slices interleaved in the projector's Cartesian spectra (and summed together

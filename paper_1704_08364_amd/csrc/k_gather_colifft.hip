@@ -481,11 +481,11 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
 }
 
 template <int LOGG, int TAPS, bool NU, bool TENT>
-__global__ void __launch_bounds__((GatherCfg<LOGG>::WG))
-__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG>::WAVES, 8))) k_gather_colifft(GatherArgs a) {
+__global__ void __launch_bounds__((GatherCfg<LOGG, polar_group(TAPS)>::WG))
+__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG, polar_group(TAPS)>::WAVES, 8))) k_gather_colifft(GatherArgs a) {
     const int s_begin = blockIdx.y * a.slices_per_block;  // a multiple of Q
-    gather_body<LOGG, TAPS, NU, TENT, kPolarSlices>(a, xcd_contiguous(blockIdx.x, gridDim.x), s_begin,
-                                                    min(a.batch, s_begin + a.slices_per_block));
+    gather_body<LOGG, TAPS, NU, TENT, polar_group(TAPS)>(a, xcd_contiguous(blockIdx.x, gridDim.x), s_begin,
+                                                         min(a.batch, s_begin + a.slices_per_block));
 }
 
 // Persistent launch of uneven batches (one slice per group, uniform angles):
@@ -507,9 +507,9 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG, 1>::WAVES, 8))) k_gather_item
 
 template <int LOGG, int TAPS>
 static hipError_t launch_gather_t(const GatherArgs& a, hipStream_t st) {
-    using C = GatherCfg<LOGG>;
+    using C = GatherCfg<LOGG, polar_group(TAPS)>;
     const int cols = C::G / 2;
-    if (a.slices_per_block <= 0 || a.slices_per_block % kPolarSlices != 0) return hipErrorInvalidValue;
+    if (a.slices_per_block <= 0 || a.slices_per_block % C::Q != 0) return hipErrorInvalidValue;
     const int chunks = (a.batch + a.slices_per_block - 1) / a.slices_per_block;
     dim3 grid((cols + C::F - 1) / C::F, chunks);
     if (a.tent_cols) {

@@ -306,10 +306,10 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
     }
 }
 
-template <int LOGM, int LOGP, bool COUNTS, bool MONO>
-__global__ void __launch_bounds__((SpecCfg<LOGM, kPolarSlices>::WG))
+template <int LOGM, int LOGP, bool COUNTS, bool MONO, int Q>
+__global__ void __launch_bounds__((SpecCfg<LOGM, Q>::WG))
 __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spectrum(SpecArgs a, int batch) {
-    spectrum_body<LOGM, LOGP, COUNTS, MONO, kPolarSlices>(a, batch, blockIdx.x, blockIdx.y);
+    spectrum_body<LOGM, LOGP, COUNTS, MONO, Q>(a, batch, blockIdx.x, blockIdx.y);
 }
 
 // Persistent launch: every block walks the work list (group, pair block) in
@@ -327,54 +327,64 @@ __attribute__((amdgpu_waves_per_eu(spec_waves<LOGP, COUNTS, MONO>(), 8))) k_spec
     }
 }
 
-template <int LOGM, int LOGP, bool COUNTS, bool MONO>
+template <int LOGM, int LOGP, bool COUNTS, bool MONO, int Q>
 static void launch_spec_k(const SpecArgs& a, int blocks, int batch, hipStream_t st) {
-    using C = SpecCfg<LOGM, kPolarSlices>;
-    const int groups = (batch + kPolarSlices - 1) / kPolarSlices;
-    hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, COUNTS, MONO>), dim3(blocks, groups), dim3(C::WG), 0, st, a, batch);
+    using C = SpecCfg<LOGM, Q>;
+    const int groups = (batch + Q - 1) / Q;
+    hipLaunchKernelGGL((k_spectrum<LOGM, LOGP, COUNTS, MONO, Q>), dim3(blocks, groups), dim3(C::WG), 0, st, a,
+                       batch);
 }
 
-template <int LOGM, int LOGP>
+template <int LOGM, int LOGP, int Q>
 static hipError_t launch_spec_t(const SpecArgs& a, int batch, hipStream_t st) {
-    using C = SpecCfg<LOGM, kPolarSlices>;
+    using C = SpecCfg<LOGM, Q>;
     const bool counts = a.flat != nullptr, mono = a.mono_part != nullptr;
     const int pairs = (a.V + 1) / 2;
     auto blocks = [&](int per) { return (pairs + C::FP * per - 1) / (C::FP * per); };
-    if (counts && mono) launch_spec_k<LOGM, LOGP, true, true>(a, blocks(spec_pairs<LOGP, true, true>()), batch, st);
-    else if (counts) launch_spec_k<LOGM, LOGP, true, false>(a, blocks(spec_pairs<LOGP, true, false>()), batch, st);
-    else if (mono) launch_spec_k<LOGM, LOGP, false, true>(a, blocks(spec_pairs<LOGP, false, true>()), batch, st);
-    else launch_spec_k<LOGM, LOGP, false, false>(a, blocks(spec_pairs<LOGP, false, false>()), batch, st);
+    if (counts && mono)
+        launch_spec_k<LOGM, LOGP, true, true, Q>(a, blocks(spec_pairs<LOGP, true, true>()), batch, st);
+    else if (counts)
+        launch_spec_k<LOGM, LOGP, true, false, Q>(a, blocks(spec_pairs<LOGP, true, false>()), batch, st);
+    else if (mono)
+        launch_spec_k<LOGM, LOGP, false, true, Q>(a, blocks(spec_pairs<LOGP, false, true>()), batch, st);
+    else
+        launch_spec_k<LOGM, LOGP, false, false, Q>(a, blocks(spec_pairs<LOGP, false, false>()), batch, st);
     return hipGetLastError();
 }
 
-template <int LOGM>
-static hipError_t launch_spec_p(const SpecArgs& a, int pr, int batch, hipStream_t st) {
+template <int LOGM, int Q>
+static hipError_t launch_spec_q(const SpecArgs& a, int pr, int batch, hipStream_t st) {
     if constexpr (LOGM >= 4) {
-        if (pr == 1) return launch_spec_t<LOGM, 0>(a, batch, st);
+        if (pr == 1) return launch_spec_t<LOGM, 0, Q>(a, batch, st);
     }
     if constexpr (LOGM >= 5) {
-        if (pr == 2) return launch_spec_t<LOGM, 1>(a, batch, st);
+        if (pr == 2) return launch_spec_t<LOGM, 1, Q>(a, batch, st);
     }
     if constexpr (LOGM >= 6) {
-        if (pr == 4) return launch_spec_t<LOGM, 2>(a, batch, st);
+        if (pr == 4) return launch_spec_t<LOGM, 2, Q>(a, batch, st);
     }
     return hipErrorInvalidValue;
 }
 
+template <int LOGM>
+static hipError_t launch_spec_p(const SpecArgs& a, int pr, int q, int batch, hipStream_t st) {
+    return q == 1 ? launch_spec_q<LOGM, 1>(a, pr, batch, st) : launch_spec_q<LOGM, kPolarSlices>(a, pr, batch, st);
+}
+
 // out[s][j][m] = polar sample m of projection j of slice s (diagnostics copy)
 __global__ void __launch_bounds__(256) k_polar_extract(const float2* polar, float2* out, int V, int S, int lead,
-                                                       int half_m) {
+                                                       int half_m, int q) {
     const int m = blockIdx.x * 256 + threadIdx.x;
     const int j = blockIdx.y, s = blockIdx.z;
     if (m >= half_m) return;
-    const int g = s / kPolarSlices, k = s % kPolarSlices;
-    out[((size_t)s * V + j) * half_m + m] = polar[(((size_t)g * V + j) * S + lead + m) * kPolarSlices + k];
+    const int g = s / q, k = s % q;
+    out[((size_t)s * V + j) * half_m + m] = polar[(((size_t)g * V + j) * S + lead + m) * q + k];
 }
 
 hipError_t launch_polar_extract(const bst_plan_s& p, const float2* polar, float2* out, int batch, hipStream_t st) {
     const int half_m = p.M / 2;
     hipLaunchKernelGGL(k_polar_extract, dim3((half_m + 255) / 256, p.V, batch), dim3(256), 0, st, polar, out, p.V,
-                       p.S, p.lead, half_m);
+                       p.S, p.lead, half_m, polar_group(p.taps));
     return hipGetLastError();
 }
 
@@ -458,17 +468,18 @@ int spectrum_blocks_per_slice(const bst_plan_s& p, int V) {
 
 hipError_t launch_spectrum(const bst_plan_s& p, const SpecArgs& a, int batch, hipStream_t st) {
     const int pr = p.prm.pad_radial;
+    const int q = polar_group(p.taps);
     switch (p.logM) {
-        case 4: return launch_spec_p<4>(a, pr, batch, st);
-        case 5: return launch_spec_p<5>(a, pr, batch, st);
-        case 6: return launch_spec_p<6>(a, pr, batch, st);
-        case 7: return launch_spec_p<7>(a, pr, batch, st);
-        case 8: return launch_spec_p<8>(a, pr, batch, st);
-        case 9: return launch_spec_p<9>(a, pr, batch, st);
-        case 10: return launch_spec_p<10>(a, pr, batch, st);
-        case 11: return launch_spec_p<11>(a, pr, batch, st);
-        case 12: return launch_spec_p<12>(a, pr, batch, st);
-        case 13: return launch_spec_p<13>(a, pr, batch, st);
+        case 4: return launch_spec_p<4>(a, pr, q, batch, st);
+        case 5: return launch_spec_p<5>(a, pr, q, batch, st);
+        case 6: return launch_spec_p<6>(a, pr, q, batch, st);
+        case 7: return launch_spec_p<7>(a, pr, q, batch, st);
+        case 8: return launch_spec_p<8>(a, pr, q, batch, st);
+        case 9: return launch_spec_p<9>(a, pr, q, batch, st);
+        case 10: return launch_spec_p<10>(a, pr, q, batch, st);
+        case 11: return launch_spec_p<11>(a, pr, q, batch, st);
+        case 12: return launch_spec_p<12>(a, pr, q, batch, st);
+        case 13: return launch_spec_p<13>(a, pr, q, batch, st);
         default: return hipErrorInvalidValue;
     }
 }

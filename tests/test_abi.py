@@ -181,10 +181,11 @@ def test_batch_create_validates_before_device_work():
 def test_keys_interpolation_validates_and_sizes_its_rows():
     p, _ = _params(n=2048, V=2048, max_batch=4, taper="keys", interp="keys")
     assert _validate(p) == 0
-    # keys rows: one leading slot and four trailing zeros, [V][M/2 + 5], for
-    # whole groups of 2 interleaved slices
-    per = 2 * 2048 * (2048 + 5) * 8 + 2048 * 4 + 2048 * 2048 * 8
+    # keys rows: one leading slot and four trailing zeros, [V][M/2 + 5], one
+    # slice per polar group (linear taps interleave two)
+    per = 2048 * (2048 + 5) * 8 + 2048 * 4 + 2048 * 2048 * 8
     assert abs(P.query_workspace(p, 1) - per) < 3 * 256
+    assert abs(P.query_workspace(p, 3) - 3 * per) < 4 * 256
     lin, _ = _params(n=2048, V=2048, max_batch=4)
     assert P.query_workspace(p, 4) > P.query_workspace(lin, 4)
     # the projector is the exact transpose of the cubic gather too

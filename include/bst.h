@@ -169,8 +169,9 @@ bst_status bst_validate(const bst_params* p);
 
 /* Workspace bytes for `batch` slices (host only, no plan needed).
  * bst_backproject: polar spectra of whole groups of two slices, interleaved
- * sample by sample, [ceil(batch/2)][V][M/2+2][2] complex64 (BST_INTERP_KEYS:
- * one slice per group, [batch][V][M/2+5], one leading and two more trailing
+ * sample by sample in tiles of 2 angles x 4 samples, [ceil(batch/2)]
+ * [ceil(V/2)][ceil((M/2+2)/4)][2][4][2] complex64 (BST_INTERP_KEYS: one slice
+ * per group, rows [batch][V][M/2+5], one leading and two more trailing
  * slots), per-projection
  * DC terms [batch][V] float32, the half-transformed grid [batch][N][G/2]
  * complex64 and, with a monopole width, partial sinogram sums [batch][64]

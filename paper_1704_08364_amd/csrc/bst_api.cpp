@@ -99,9 +99,9 @@ WsLayout workspace_layout(int n, int V, int N, int M, int G, int batch, int inte
     const size_t B = (size_t)batch;
     L.polar_off = 0;
     // whole groups of interleaved slices
-    const size_t Q = (size_t)polar_group(interp == BST_INTERP_KEYS ? 4 : 2);
-    const size_t BQ = (B + Q - 1) / Q * Q;
-    const size_t polar = BQ * (size_t)V * (size_t)polar_stride(M, interp) * sizeof(float2);
+    const int Q = polar_group(interp == BST_INTERP_KEYS ? 4 : 2);
+    const size_t pgroups = (B + Q - 1) / Q;
+    const size_t polar = pgroups * PolarTiles{Q, V, polar_stride(M, interp)}.group_elems() * sizeof(float2);
     L.dc_off = up(L.polar_off + polar);
     const size_t dc = B * (size_t)V * sizeof(float);
     L.grid_off = up(L.dc_off + dc);

@@ -108,6 +108,29 @@ static_assert(kPolarSlices == 2 || kPolarSlices == 4, "2 or 4 interleaved slices
 // samples per row, twice the bytes per slice, and run fastest one slice per
 // group (eight 16-byte reads per point otherwise pile up in flight).
 constexpr int polar_group(int taps) { return taps == 4 ? 1 : kPolarSlices; }
+
+// Layout of the polar spectra of one group of Q slices, S slots per angle.
+// Q = 2: tiles of 2 angles x 4 slots x 2 slices (128 bytes, one cache line),
+// ceil(V/2) rows of ceil(S/4) tiles. The four samples (j0, m0..m0+1) x (j0+1,
+// m0..m0+1) a linear-tap point reads mostly fall into one or two such lines,
+// where rows of single angles spread them over two to four. Other Q: rows
+// [V][S] of Q-slice samples.
+struct PolarTiles {
+    int Q, V, S;
+    __host__ __device__ int tiles_per_row() const { return (S + 3) >> 2; }
+    // complex values of one group
+    __host__ __device__ size_t group_elems() const {
+        if (Q == 2) return (size_t)((V + 1) >> 1) * (size_t)tiles_per_row() * 16u;
+        return (size_t)V * (size_t)S * (size_t)Q;
+    }
+    // index (in Q-slice samples, 8 Q bytes) of sample (j, slot) in its group
+    __host__ __device__ size_t sample(int j, int slot) const {
+        if (Q == 2)
+            return ((size_t)(j >> 1) * (size_t)tiles_per_row() + (size_t)(slot >> 2)) * 8u + (size_t)((j & 1) * 4) +
+                   (size_t)(slot & 3);
+        return (size_t)j * (size_t)S + (size_t)slot;
+    }
+};
 // slices interleaved in the tent rule's radius-major copy
 constexpr int kTentSlices = 8;
 // slices interleaved in the projector's Cartesian spectra (and summed together
@@ -143,7 +166,7 @@ struct SpecArgs {
     const float* const* sino_list;  // or one pointer per slice (device array), if non-null
     const float* flat;      // [batch][n] or nullptr
     const float* dark;      // [batch][n]
-    float2* polar;          // [ceil(batch/4)][V][S][4]: kPolarSlices slices interleaved per sample
+    float2* polar;          // groups of Q slices interleaved per sample (PolarTiles)
     float* dc;
     const float* taper;
     const float2* kc;
@@ -177,7 +200,7 @@ struct MassArgs {           // partial sums of each slice's sinogram (monopole m
 };
 
 struct GatherArgs {
-    const float2* polar;     // [batch/4][V][S][4]: kPolarSlices slices interleaved per sample
+    const float2* polar;     // groups of Q slices interleaved per sample (PolarTiles)
     const float* dc;
     float2* grid;
     const float2* tw;
@@ -208,7 +231,7 @@ struct GatherArgs {
 };
 
 struct TentArgs {            // pre-gather of the wide points of the tent rule
-    const float2* polar;     // [batch/4][V][S][4] (kPolarSlices interleaved)
+    const float2* polar;     // groups of kPolarSlices slices (PolarTiles)
     float2* trans;           // [batch/8][rows][V][8]: the first rows radial samples,
                              // radius-major, 8 slices interleaved
     float2* patch;           // [batch][W]

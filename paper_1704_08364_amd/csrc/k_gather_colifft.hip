@@ -111,10 +111,12 @@ __device__ float block_sum(float x, float* red) {
 }
 
 // Interpolation stencil of one Cartesian point, fixed for all slices:
-//   o0      sample index (j0 S + m0: one unit is the Q slices' values of
-//           one sample, 8 Q bytes) of the first radial tap of angle j0; the
-//           taps of j1 are one polar row further, or, when j1 wraps to angle
-//           0, (V-1) rows back. Bit 31 flips the conjugation of the j0 taps
+//   o0      sample index (one unit is the Q slices' values of one sample,
+//           8 Q bytes) of the first radial tap of angle j0; the taps of j1
+//           are one polar row further, or, when j1 wraps to angle 0, (V-1)
+//           rows back. In the tiled layout of two slices (PolarTiles) bit 29
+//           says the second radial tap starts the next tile (m0 = 3 mod 4) and
+//           bit 30 that j0 is odd (j1 in the next tile row). Bit 31 flips the conjugation of the j0 taps
 //           (non-uniform angles, below theta_0, where the j0 neighbour is the
 //           image theta_{V-1} - pi);
 //   g       radial fraction, its sign bit set when j1 wraps;
@@ -130,6 +132,7 @@ struct Stencil {
     float g, w1;
 };
 constexpr unsigned kOffsetMask = 0x7FFFFFFFu;
+constexpr unsigned kSampleMask = 0x1FFFFFFFu;  // o0 without its flag bits
 
 // Angles of a slice: the plan's table, or (uneven batches, a count per
 // slice) j pi / V formed on the fly; V / pi in FP32.
@@ -156,10 +159,19 @@ __device__ __forceinline__ bool lower_j0(unsigned flips, int e, bool lower) {
 // Stencil of Cartesian point (col, bs); bs signed. NU: non-uniform angles.
 // TENT: a wide point of the tent rule (|bs| <= B_col) gets bit 31 of o0 and
 // its patch slot in the low bits; its polar reads go to the zero slots.
-template <bool NU, bool TENT>
+template <bool TILED>
+__device__ __forceinline__ unsigned sample_code(const GatherArgs& a, int j, int m) {
+    if constexpr (TILED)
+        return (unsigned)PolarTiles{2, a.V, a.S}.sample(j, m) | ((unsigned)((m & 3) == 3) << 29) |
+               ((unsigned)(j & 1) << 30);
+    else
+        return (unsigned)(j * a.S + m);
+}
+
+template <bool NU, bool TENT, bool TILED>
 __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherArgs& a, const AngleView& av) {
     Stencil st;
-    st.o0 = (unsigned)a.zero_slot;
+    st.o0 = sample_code<TILED>(a, 0, a.zero_slot);
     st.g = st.w1 = 0.f;
     if (col == 0 && bs == 0) return st;
     if constexpr (TENT) {
@@ -225,7 +237,7 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
     // neighbours of a point below theta_0 are already in place)
     const bool wrap = (j0 + 1 == av.V);
     const bool conj1 = lower != (wrap && !flip0);
-    st.o0 = (unsigned)(j0 * a.S + m0) | ((unsigned)flip0 << 31);
+    st.o0 = sample_code<TILED>(a, j0, m0) | ((unsigned)flip0 << 31);
     st.g = __uint_as_float(__float_as_uint((float)(r - mf)) | ((unsigned)wrap << 31));
     st.w1 = conj1 ? -f : f;
     return st;
@@ -309,6 +321,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
     using C = GatherCfg<LOGG, Q>;
     constexpr int G = C::G, T = C::T, F = C::F, E = C::E;
     constexpr unsigned kSampleBytes = Q * sizeof(float2);
+    constexpr bool TILED = Q == 2 && TAPS == 2;  // the 2 x 4 x 2 tiles of PolarTiles
     __shared__ float2 lds[C::NREG * C::REGION];  // one region per parked slice
     __shared__ float red[(C::WG + 63) / 64];
     const int fid = threadIdx.x % F;
@@ -334,7 +347,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
         for (int h = 0; h < CH; ++h) {
             const int b = j + (c0 + h) * T;
             const int bs = b < G / 2 ? b : b - G;
-            const Stencil st = point_stencil<NU, TENT>(live ? col : 0, live ? bs : 0, a, av);
+            const Stencil st = point_stencil<NU, TENT, TILED>(live ? col : 0, live ? bs : 0, a, av);
             unsigned* d = stage + (h * NW) * C::WG + threadIdx.x;
             d[0] = st.o0;
             d[C::WG] = __float_as_uint(st.g);
@@ -359,12 +372,19 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
             pt[e].o0 &= kOffsetMask;
         }
     }
-    const unsigned zoff = (unsigned)a.zero_slot * kSampleBytes;
+    const unsigned zcode = sample_code<TILED>(a, 0, a.zero_slot);  // a zero sample
+    const unsigned zoff = (zcode & kSampleMask) * kSampleBytes;
 
     const int half_n = a.N >> 1;
-    const unsigned group_bytes = (unsigned)a.V * (unsigned)a.S * kSampleBytes;
+    const PolarTiles lay{Q, a.V, a.S};
+    const unsigned group_bytes = (unsigned)(lay.group_elems() * sizeof(float2));
     const unsigned row_bytes = (unsigned)a.S * kSampleBytes;
     const unsigned wrap_bytes = 0u - (unsigned)(V - 1) * row_bytes;  // back to row 0
+    // tiled: from angle j to j + 1 (j even: the tile's second half; j odd:
+    // the next tile row's first), and from angle V - 1 back to angle 0
+    const unsigned tile_row_bytes = (unsigned)lay.tiles_per_row() * 128u;
+    const unsigned tile_next = tile_row_bytes - 64u;
+    const unsigned tile_wrap = 0u - (unsigned)((V - 1) >> 1) * tile_row_bytes - (unsigned)((V - 1) & 1) * 64u;
     float2* R0 = lds + fid * C::STRIDE;
     float2* R1 = R0 + (C::NREG - 1) * C::REGION;
     for (int s0 = s_begin; s0 < s_end; s0 += Q) {
@@ -374,7 +394,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
         // loop and held in registers, which spills.
         int jv = j;
         asm volatile("" : "+v"(jv));
-        const __amdgpu_buffer_rsrc_t P = polar_rsrc(a.polar + (size_t)(s0 / Q) * a.V * a.S * Q, group_bytes);
+        const __amdgpu_buffer_rsrc_t P = polar_rsrc(a.polar + (size_t)(s0 / Q) * lay.group_elems(), group_bytes);
         float dcv[Q];
         if (lblock == 0) {
 #pragma unroll
@@ -398,12 +418,24 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
             for (int i = 0; i < H; ++i) {
                 const Stencil& st = pt[h0 + i];
                 const bool wrap = __float_as_uint(st.g) >> 31;
-                constexpr unsigned kLast = TAPS * kSampleBytes - 1u;  // bytes read past the offset
-                const unsigned o0 = BST_IDX((TENT && ((wide >> (h0 + i)) & 1u)) ? zoff : st.o0 * kSampleBytes,
-                                            group_bytes - kLast, 0);
-                const unsigned o1 = BST_IDX(o0 + (wrap ? wrap_bytes : row_bytes), group_bytes - kLast, 0);
-                load_row<TAPS, Q>(P, o0, qa[i]);
-                load_row<TAPS, Q>(P, o1, qb[i]);
+                const bool zero = TENT && ((wide >> (h0 + i)) & 1u);
+                if constexpr (TILED) {
+                    // (j0, m0) and (j0, m0 + 1): 16 bytes apart, or 80 across a tile edge
+                    const unsigned code = zero ? zcode : st.o0;
+                    const unsigned oa = BST_IDX((code & kSampleMask) * 16u, group_bytes - 15u, 0);
+                    const unsigned ob = BST_IDX(oa + (((code >> 29) & 1u) ? 80u : 16u), group_bytes - 15u, 0);
+                    const unsigned d1 = wrap ? tile_wrap : (((code >> 30) & 1u) ? tile_next : 64u);
+                    qa[i][0] = load16(P, oa);
+                    qa[i][1] = load16(P, ob);
+                    qb[i][0] = load16(P, BST_IDX(oa + d1, group_bytes - 15u, 0));
+                    qb[i][1] = load16(P, BST_IDX(ob + d1, group_bytes - 15u, 0));
+                } else {
+                    constexpr unsigned kLast = TAPS * kSampleBytes - 1u;  // bytes read past the offset
+                    const unsigned o0 = BST_IDX(zero ? zoff : st.o0 * kSampleBytes, group_bytes - kLast, 0);
+                    const unsigned o1 = BST_IDX(o0 + (wrap ? wrap_bytes : row_bytes), group_bytes - kLast, 0);
+                    load_row<TAPS, Q>(P, o0, qa[i]);
+                    load_row<TAPS, Q>(P, o1, qb[i]);
+                }
             }
 #pragma unroll
             for (int i = 0; i < H; ++i) {
@@ -540,7 +572,7 @@ __global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a, int batch) {
     const int grp = blockIdx.z;
     const int m0 = blockIdx.x * 32, j0 = blockIdx.y * 8;
     // reads follow the interleaved polar layout: the Q slices of one sample,
-    // then consecutive samples (32 Q values contiguous per angle)
+    // then consecutive samples (runs of 4 samples with Q = 2, 32 otherwise)
     constexpr int Q = kPolarSlices, NG = kTentSlices / kPolarSlices;
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
@@ -549,9 +581,11 @@ __global__ void __launch_bounds__(256) k_tent_transpose(TentArgs a, int batch) {
         const int k = kh * Q + k4;
         const int s = grp * kTentSlices + k;
         float2 v = make_float2(0.f, 0.f);
-        if (s < batch && j0 + j < a.V && m0 + m < a.rows)
-            v = a.polar[(((size_t)(s / kPolarSlices) * a.V + j0 + j) * a.S + BST_IDX(a.lead + m0 + m, a.S, 3)) *
-                            kPolarSlices + k4];
+        if (s < batch && j0 + j < a.V && m0 + m < a.rows) {
+            const PolarTiles lay{Q, a.V, a.S};
+            v = a.polar[(size_t)(s / Q) * lay.group_elems() +
+                        lay.sample(j0 + j, BST_IDX(a.lead + m0 + m, a.S, 3)) * Q + k4];
+        }
         tile[k][j][m] = v;
     }
     __syncthreads();

@@ -248,15 +248,17 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
         // rows ja and jb with the group's slices interleaved
         const bool wa = ja < a.V, wb = jb < a.V;
         const float2* z0 = lds + (Q * pl) * FftShape<LOGM>::LDS;
-        float2* rowa = a.polar + (((size_t)g * a.V + (wa ? ja : 0)) * a.S) * Q;
-        float2* rowb = a.polar + (((size_t)g * a.V + (wb ? jb : 0)) * a.S) * Q;
+        const PolarTiles lay{Q, a.V, a.S};
+        float2* grp = a.polar + (size_t)g * lay.group_elems();
+        const int rja = wa ? ja : 0, rjb = wb ? jb : 0;
         // one sample of the Q slices: 8 Q bytes, as float2 (Q = 1) or float4 parts
-        auto put = [&](float2* row, int slot, const float2 (&y)[Q], bool conj) {
+        auto put = [&](int row, int slot, const float2 (&y)[Q], bool conj) {
             const float c = conj ? -1.f : 1.f;
+            float2* at = grp + BST_IDX(lay.sample(row, slot), lay.group_elems() / Q, 2) * Q;
             if constexpr (Q == 1) {
-                row[slot] = make_float2(y[0].x, c * y[0].y);
+                *at = make_float2(y[0].x, c * y[0].y);
             } else {
-                float4* r4 = reinterpret_cast<float4*>(row + (size_t)slot * Q);
+                float4* r4 = reinterpret_cast<float4*>(at);
 #pragma unroll
                 for (int t = 0; t < Q / 2; ++t)
                     r4[t] = make_float4(y[2 * t].x, c * y[2 * t].y, y[2 * t + 1].x, c * y[2 * t + 1].y);
@@ -278,13 +280,13 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
                 yb[d] = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[i]);
             }
             if (wa) {
-                put(rowa, slot, ya, false);
+                put(rja, slot, ya, false);
                 // the sample before 0 (cubic radial taps): Yh(-sigma) = conj Yh(sigma)
-                if (a.lead && m == 1) put(rowa, 0, ya, true);
+                if (a.lead && m == 1) put(rja, 0, ya, true);
             }
             if (wb) {
-                put(rowb, slot, yb, false);
-                if (a.lead && m == 1) put(rowb, 0, yb, true);
+                put(rjb, slot, yb, false);
+                if (a.lead && m == 1) put(rjb, 0, yb, true);
             }
         }
         for (int z = qv; z < a.tail; z += TP) {
@@ -292,8 +294,8 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
             float2 zero[Q];
 #pragma unroll
             for (int d = 0; d < Q; ++d) zero[d] = make_float2(0.f, 0.f);
-            if (wa) put(rowa, slot, zero, false);
-            if (wb) put(rowb, slot, zero, false);
+            if (wa) put(rja, slot, zero, false);
+            if (wb) put(rjb, slot, zero, false);
         }
         if (it + 1 < PAIRS) {
             __syncthreads();  // the next transforms overwrite this LDS
@@ -378,7 +380,8 @@ __global__ void __launch_bounds__(256) k_polar_extract(const float2* polar, floa
     const int j = blockIdx.y, s = blockIdx.z;
     if (m >= half_m) return;
     const int g = s / q, k = s % q;
-    out[((size_t)s * V + j) * half_m + m] = polar[(((size_t)g * V + j) * S + lead + m) * q + k];
+    const PolarTiles lay{q, V, S};
+    out[((size_t)s * V + j) * half_m + m] = polar[g * lay.group_elems() + lay.sample(j, lead + m) * q + k];
 }
 
 hipError_t launch_polar_extract(const bst_plan_s& p, const float2* polar, float2* out, int batch, hipStream_t st) {

@@ -106,14 +106,15 @@ def test_workspace_size_is_exact_and_monotone():
     sizes = [P.query_workspace(p, b) for b in (0, 1, 2, 7, 64)]
     assert sizes[0] == 0
     assert all(a < b for a, b in zip(sizes, sizes[1:]))
-    # polar [V][M/2+2] c64 per slice, for whole groups of 2 interleaved slices,
-    # + dc [V] f32 + grid [N][G/2] c64 per slice, 256-byte aligned blocks
-    polar = 2048 * (2048 + 2) * 8
+    # polar spectra per group of 2 slices: ceil(V/2) rows of ceil((M/2+2)/4)
+    # tiles of 2 angles x 4 samples x 2 slices (128 bytes); + dc [V] f32 + grid
+    # [N][G/2] c64 per slice, 256-byte aligned blocks
+    group = 1024 * 513 * 128
     per = 2048 * 4 + 2048 * 2048 * 8
-    assert abs(sizes[1] - (2 * polar + per)) < 3 * 256
-    assert abs(sizes[2] - 2 * (polar + per)) < 3 * 256
-    assert abs(sizes[3] - (8 * polar + 7 * per)) < 3 * 256
-    assert abs(sizes[4] - 64 * (polar + per)) < 3 * 256
+    assert abs(sizes[1] - (group + per)) < 3 * 256
+    assert abs(sizes[2] - (group + 2 * per)) < 3 * 256
+    assert abs(sizes[3] - (4 * group + 7 * per)) < 3 * 256
+    assert abs(sizes[4] - (32 * group + 64 * per)) < 3 * 256
     with pytest.raises(P.BstError):
         P.query_workspace(p, 65)
     with pytest.raises(P.BstError):

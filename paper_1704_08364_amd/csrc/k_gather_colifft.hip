@@ -300,14 +300,14 @@ __device__ __forceinline__ void radial_row(const float4 (&q)[TAPS * Q / 2], floa
     }
 }
 
-// Points of a thread whose reads are issued together. Uniform angles with
-// linear radial taps issue several points' reads before using any; cubic
-// taps, non-uniform angles and the tent rule read one point at a time, which
-// measured faster for the first two (a point's reads share cache lines, and
-// fewer reads in flight keep them in L1) and leaves the tent variant the
-// registers of its wide-point mask.
+// Points of a thread whose reads are issued together. Every variant reads one
+// point at a time: a point's four 16-byte reads mostly share one or two cache
+// lines, and with fewer reads in flight the lines are still in L1 when the
+// next point of a neighbouring lane needs them (two points at a time measured
+// 2 % slower with the tiled layout, four 30 % slower, spilling; before the
+// tiling, interleaved rows of two slices ran fastest with two).
 #ifndef BST_GATHER_INFLIGHT
-#define BST_GATHER_INFLIGHT 2
+#define BST_GATHER_INFLIGHT 1
 #endif
 #ifndef BST_GATHER_INFLIGHT_OTHER
 #define BST_GATHER_INFLIGHT_OTHER 1

@@ -150,7 +150,7 @@ typedef struct {
                                (its interpolation coordinates are computed once for
                                them): 0 = the default (32), else a positive multiple
                                of 2 up to 1024. Results do not depend on it (tuning
-                               and tests only); bst_batch_tune chooses it per class */
+                               and tests only)                                          */
 } bst_params;
 
 typedef enum {
@@ -291,16 +291,23 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
 bst_status bst_debug_spectrum(bst_plan_t plan, const float* sino, void* spec, float* dc,
                               int32_t batch, void* ws, size_t ws_bytes, void* stream);
 
-/* ---- Uneven-size batches ------------------------------------------------
+/* ---- Uneven-size batches (Section 2 processes blocks of Q sinograms; Section
+ * 3 tunes the pipeline's block sizes per stage) ------------------------------
  * Many sinograms of different sizes (n_det[i], n_angles[i]) in one graph
- * launch; every other parameter comes from *base (uniform angles only).
- * Instances of equal (n, V) form a class with its own plan and workspace
- * region; classes run concurrently. Sinograms and images live in two packed
- * device buffers at the element offsets sino_off[i] and img_off[i] (host
- * arrays of `count`), each instance float32 [V_i][n_i] and [n_i][n_i].
- * The first bst_batch_backproject with a given workspace captures all launches
- * into a hipGraph; later calls only upload the pointer lists and replay it.
- * Calls on one batch must not overlap in time (they share the pointer lists).
+ * launch; every other parameter comes from *base (uniform angles only, FP32;
+ * otherwise BST_E_UNSUPPORTED, and per-instance validation as for
+ * bst_validate). Instances of equal n form a size class with one plan (built
+ * for the class's largest V) and one workspace region; per stage, one
+ * persistent kernel per class walks a device work list of (instance, tile)
+ * items, each instance with its own V. With the tent angular rule the
+ * classes are instead those of equal (n, V), run by the ordinary kernels.
+ * Classes run concurrently. Sinograms and images live in two packed device
+ * buffers at the element offsets sino_off[i] and img_off[i] (host arrays of
+ * `count`), each instance float32 [V_i][n_i] and [n_i][n_i]. The first
+ * bst_batch_backproject with a given workspace captures all launches into a
+ * hipGraph; later calls only upload the pointer lists and replay it. Calls on
+ * one batch must not overlap in time (they share the pointer lists). Results
+ * equal bst_backproject's for each instance to rounding.
  */
 typedef struct bst_batch_s* bst_batch_t;
 
@@ -308,8 +315,10 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
                             const int32_t* n_angles, bst_batch_t* out);
 bst_status bst_batch_workspace_size(bst_batch_t b, size_t* bytes);
 bst_status bst_batch_classes(bst_batch_t b, int32_t* n_classes);
-/* Time the gather kernel's variants (4, 8, 16 or 32 slices per block) for
- * every class on these inputs, keep the fastest, and drop any captured graph.
+/* Autotuner: for every size class, on these inputs, time each stage's
+ * persistent grid (1, 2, 4 or 8 blocks per compute unit) and the row stage's
+ * tiles per work item (1, 2, 4, 8 or 16 eight-row tiles), keep the fastest,
+ * and drop any captured graph. Results do not depend on the choice.
  * Synchronizes the stream. Outputs are overwritten. */
 bst_status bst_batch_tune(bst_batch_t b, const float* sinos, const int64_t* sino_off, float* imgs,
                           const int64_t* img_off, void* ws, size_t ws_bytes, void* stream);

@@ -16,8 +16,9 @@
 // be contiguous or ordered. The first call with a given workspace captures
 // every class's launches into one hipGraph, forked over a few streams (all at
 // default priority) and joined back; later calls update the pointer lists and
-// replay it. bst_batch_tune times each stage's persistent grid size per class
-// on the caller's data and keeps the fastest.
+// replay it. bst_batch_tune times, per class and on the caller's data, each
+// stage's persistent grid size and the row stage's tile shape (how many row
+// tiles one work item covers), and keeps the fastest.
 //
 // The tent angular rule pre-gathers its patches per angle set, so tent
 // batches keep classes of equal (n, V) run by the ordinary kernels (through
@@ -41,6 +42,7 @@ struct SizeClass {
     bool regular = false;      // equal (n, V), ordinary launches (tent rule)
     bst_plan_t plan = nullptr;
     std::vector<int> members;  // instance indices, in input order
+    std::vector<int> Vs;       // their angle counts
     int list_base = 0;         // offset of this class's pointers in the lists
     size_t ws_off = 0, ws_bytes = 0;
     // workspace layout (offsets inside the class region)
@@ -49,9 +51,21 @@ struct SizeClass {
     int* d_V = nullptr;
     int2* d_items[kStages] = {};
     int n_items[kStages] = {};
-    int row_tiles = 1;
+    int row_tiles = 1;         // row tiles per item of the row stage (tuned)
     int blocks[kStages] = {};  // persistent grid sizes (tuned)
 };
+
+// Work list of a stage: (slice, block) items, slice-major.
+std::vector<int2> stage_items(const SizeClass& c, int stage) {
+    std::vector<int2> list;
+    for (int i = 0; i < (int)c.members.size(); ++i) {
+        const int nb = stage == 0 ? bst::spectrum_blocks_per_slice(*c.plan, c.Vs[i])
+                                  : (stage == 1 ? bst::gather_blocks_per_slice(*c.plan)
+                                                : bst::row_blocks_per_slice(*c.plan, c.row_tiles));
+        for (int k = 0; k < nb; ++k) list.push_back(make_int2(i, k));
+    }
+    return list;
+}
 
 // Layout of a class region: polar [B][Vmax][S] complex64 (one slice per
 // group), DC terms [B][Vmax], grid [B][N][G/2], monopole sums [B][64].
@@ -288,6 +302,7 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
         }
         SizeClass& c = classes[it->second];
         c.members.push_back(i);
+        c.Vs.push_back(n_angles[i]);
         c.Vmax = std::max(c.Vmax, (int)n_angles[i]);
     }
     bst_batch_s* b = new (std::nothrow) bst_batch_s();
@@ -333,20 +348,16 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
         }
         c.ws_bytes = class_layout(c);
         off += c.ws_bytes;
-        // work lists: (slice, block) items of each stage, slice-major
+        // work lists; the row list's region holds the finest tiling (one tile
+        // per item), which the tuner may pick. Start with about four row
+        // blocks per compute unit.
         const int B = (int)c.members.size();
-        const int groups = c.plan->N / 8;  // 8-row tiles per slice
-        c.row_tiles = std::max(1, std::min(16, (int)(((long long)groups * B) / 1024)));
+        const int per_slice = bst::row_blocks_per_slice(*c.plan, 1);
+        c.row_tiles = std::max(1, std::min(bst::row_max_tiles(*c.plan), (per_slice * B) / (4 * b->cus)));
         for (int s = 0; s < kStages; ++s) {
-            std::vector<int2> list;
-            for (int i = 0; i < B; ++i) {
-                const int V = n_angles[c.members[i]];
-                const int nb = s == 0 ? bst::spectrum_blocks_per_slice(*c.plan, V)
-                                      : (s == 1 ? bst::gather_blocks_per_slice(*c.plan)
-                                                : bst::row_blocks_per_slice(*c.plan, c.row_tiles));
-                for (int k = 0; k < nb; ++k) list.push_back(make_int2(i, k));
-            }
+            std::vector<int2> list = stage_items(c, s);
             c.n_items[s] = (int)list.size();
+            if (s == 2) list.resize((size_t)per_slice * B, make_int2(0, 0));
             items.push_back(std::move(list));
         }
         c.blocks[0] = grid_blocks(b, c.n_items[0], 2);
@@ -448,32 +459,49 @@ bst_status bst_batch_tune(bst_batch_t b, const float* sinos, const int64_t* sino
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return fail(e);
+    // the row stage's work list for a tiling (synchronous upload: every
+    // launch that read the previous list has finished)
+    auto set_row_tiles = [&](SizeClass& c, int tiles) {
+        c.row_tiles = tiles;
+        const std::vector<int2> list = stage_items(c, 2);
+        c.n_items[2] = (int)list.size();
+        hipError_t r = hipStreamSynchronize(s);
+        if (r == hipSuccess) r = hipMemcpy(c.d_items[2], list.data(), list.size() * sizeof(int2), hipMemcpyHostToDevice);
+        return r;
+    };
     // per class, stage by stage: the persistent grid (blocks per compute unit)
-    // with which the class's launches run fastest on these inputs
+    // and, for the row stage, the tiles per item with which the class's
+    // launches run fastest on these inputs
     const int per_cu[4] = {1, 2, 4, 8};
     for (auto& c : b->classes) {
         for (int stage = 0; !c.regular && stage < kStages && e == hipSuccess; ++stage) {
             float best = 1e30f;
-            int best_blocks = c.blocks[stage];
-            int tried = -1;
-            for (int k : per_cu) {
-                const int blocks = grid_blocks(b, c.n_items[stage], k);
-                if (blocks == tried) continue;  // capped by the item count
-                tried = blocks;
-                c.blocks[stage] = blocks;
-                e = launch_class(b, c, ws, s);  // warm
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventRecord(t0, s);
-                for (int r = 0; e == hipSuccess && r < 2; ++r) e = launch_class(b, c, ws, s);
-                if (e == hipSuccess) e = hipEventRecord(t1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(t1);
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                if (e != hipSuccess) break;
-                if (ms < best) {
-                    best = ms;
-                    best_blocks = blocks;
+            int best_blocks = c.blocks[stage], best_tiles = c.row_tiles;
+            const int max_tiles = stage == 2 ? bst::row_max_tiles(*c.plan) : 1;
+            for (int tiles = 1; tiles <= max_tiles && e == hipSuccess; tiles *= 2) {
+                if (stage == 2) e = set_row_tiles(c, tiles);
+                int tried = -1;
+                for (int k : per_cu) {
+                    if (e != hipSuccess) break;
+                    const int blocks = grid_blocks(b, c.n_items[stage], k);
+                    if (blocks == tried) continue;  // capped by the item count
+                    tried = blocks;
+                    c.blocks[stage] = blocks;
+                    e = launch_class(b, c, ws, s);  // warm
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventRecord(t0, s);
+                    for (int r = 0; e == hipSuccess && r < 2; ++r) e = launch_class(b, c, ws, s);
+                    if (e == hipSuccess) e = hipEventRecord(t1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(t1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                    if (e == hipSuccess && ms < best) {
+                        best = ms;
+                        best_blocks = blocks;
+                        best_tiles = tiles;
+                    }
                 }
             }
+            if (e == hipSuccess && stage == 2) e = set_row_tiles(c, best_tiles);
             c.blocks[stage] = best_blocks;
         }
         if (e != hipSuccess) break;

@@ -353,6 +353,7 @@ hipError_t launch_row_items(const bst_plan_s& p, const RowArgs& a, int blocks, h
 int spectrum_blocks_per_slice(const bst_plan_s& p, int V);  // one-slice groups
 int gather_blocks_per_slice(const bst_plan_s& p);
 int row_blocks_per_slice(const bst_plan_s& p, int tiles);
+int row_max_tiles(const bst_plan_s& p);  // 8-row tiles (4-row past G = 4096) a row block may walk
 // copy the interleaved polar spectra out as [batch][V][M/2] complex64 (diagnostics)
 hipError_t launch_polar_extract(const bst_plan_s& p, const float2* polar, float2* out, int batch, hipStream_t st);
 hipError_t launch_gather_colifft(const bst_plan_s& p, const GatherArgs& a, hipStream_t st);

@@ -209,6 +209,22 @@ static int row_blocks_t(int N, int tiles) {
     return (groups + tiles - 1) / tiles;
 }
 
+int row_max_tiles(const bst_plan_s& p) {
+    switch (p.logG) {
+        case 4: return RowCfg<4>::MAX_TILES;
+        case 5: return RowCfg<5>::MAX_TILES;
+        case 6: return RowCfg<6>::MAX_TILES;
+        case 7: return RowCfg<7>::MAX_TILES;
+        case 8: return RowCfg<8>::MAX_TILES;
+        case 9: return RowCfg<9>::MAX_TILES;
+        case 10: return RowCfg<10>::MAX_TILES;
+        case 11: return RowCfg<11>::MAX_TILES;
+        case 12: return RowCfg<12>::MAX_TILES;
+        case 13: return RowCfg<13>::MAX_TILES;
+        default: return 1;
+    }
+}
+
 int row_blocks_per_slice(const bst_plan_s& p, int tiles) {
     switch (p.logG) {
         case 4: return row_blocks_t<4>(p.N, tiles);

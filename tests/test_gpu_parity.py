@@ -922,6 +922,23 @@ def test_uneven_batch_of_64_distinct_angle_counts(P):
         assert torch.equal(imgs, first), f"tuned replay {r}"
 
 
+def test_uneven_batch_with_the_largest_transform(P):
+    """4096-bin instances (G = 8192: the row kernel's two-pairs-per-block path,
+    one row group per work item) beside a small one, tuned, against the
+    oracle."""
+    sizes = [(4096, 64), (64, 50), (4096, 33)]
+    batch, sinos, imgs = _uneven(sizes, 4096)
+    ws = batch.workspace()
+    batch.tune(sinos, imgs, ws)
+    imgs.zero_()
+    batch.backproject(sinos, imgs, ws)
+    torch.cuda.synchronize()
+    for i, (n, v) in enumerate(sizes):
+        _say(f"[uneven 4096] instance {i}: n={n} V={v}")
+        ref = obst.backproject(batch.sino_view(sinos, i).double().cpu().numpy(), Geometry(n, v, n))
+        assert_parity(batch.img_view(imgs, i).cpu().numpy(), ref)
+
+
 def test_uneven_batch_tuned(P):
     sizes = [(128, 96), (256, 200), (128, 96), (512, 300)]
     batch, sinos, imgs = _uneven(sizes, 91)

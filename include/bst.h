@@ -291,8 +291,8 @@ bst_status bst_project(bst_plan_t plan, const float* img, float* sino, int32_t b
 bst_status bst_debug_spectrum(bst_plan_t plan, const float* sino, void* spec, float* dc,
                               int32_t batch, void* ws, size_t ws_bytes, void* stream);
 
-/* ---- Uneven-size batches (Section 2 processes blocks of Q sinograms; Section
- * 3 tunes the pipeline's block sizes per stage) ------------------------------
+/* ---- Uneven-size batches (Section 3's pipeline processes blocks of Q
+ * sinograms; Section 4 measures its time against Q) ---------------------------
  * Many sinograms of different sizes (n_det[i], n_angles[i]) in one graph
  * launch; every other parameter comes from *base (uniform angles only, FP32;
  * otherwise BST_E_UNSUPPORTED, and per-instance validation as for

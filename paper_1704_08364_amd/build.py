@@ -108,7 +108,9 @@ def host_sanitizer_env(log_dir: str | None = None) -> dict:
         asan += f":log_path={os.path.join(log_dir, 'asan')}"
         ubsan += f":log_path={os.path.join(log_dir, 'ubsan')}"
     ld = os.environ.get("LD_LIBRARY_PATH", "")
-    return {"BST_LIBRARY": SAN_LIB, "LD_PRELOAD": host_sanitizer_preload(),
+    # the ASan runtime must come first; anything already preloaded stays
+    pre = " ".join(x for x in (host_sanitizer_preload(), os.environ.get("LD_PRELOAD", "")) if x)
+    return {"BST_LIBRARY": SAN_LIB, "LD_PRELOAD": pre,
             "LD_LIBRARY_PATH": ":".join(x for x in (torch_lib, ld) if x),
             "ASAN_OPTIONS": asan, "UBSAN_OPTIONS": ubsan}
 

@@ -1,6 +1,6 @@
 // batch.cpp -- uneven-size batches: many sinograms of different sizes in one
-// graph launch (the paper processes blocks of Q sinograms at once, Section 2,
-// and tunes its pipeline's block sizes and queues per stage, Section 3).
+// graph launch (the paper's pipeline processes blocks of Q sinograms at once,
+// Section 3, and Section 4 measures how the block size Q changes its time).
 //
 // Instances are grouped into size classes of equal n (= N); the angle count V
 // may differ per instance. Each class has one plan (the FFT twiddles, taper,

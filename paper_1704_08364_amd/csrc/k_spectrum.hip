@@ -10,9 +10,10 @@
 // sigma_m beta dt) (K = 1/sigma for plain B, 1 for FBP, 0 at m = M/2; A the
 // apodising window; beta a known rotation-axis offset). With raw counts the
 // load forms y = -log((I - D)/(I0 - D)) first (flat/dark normalisation).
-// The polar spectra of kPolarSlices consecutive slices are stored interleaved
-// (sample m of projection j of the group's slices in 8 kPolarSlices
-// contiguous bytes), because the gather reads all of them at every tap.
+// The polar spectra of a group of Q consecutive slices are stored interleaved
+// (sample m of projection j of the group's slices in 8 Q contiguous bytes),
+// because the gather reads all of them at every tap; groups of two slices in
+// cache-line tiles of neighbouring angles and samples (PolarTiles).
 // Output rows hold m = 0..M/2-1 followed by zero slots, so the gather may read
 // past the last sample without a bound test: two for linear radial
 // interpolation (samples m0, m0+1), four plus a leading conj Yh[1] (the
@@ -118,14 +119,13 @@ constexpr int spec_waves() { return (MONO && COUNTS && LOGP == 0) ? 3 : BST_SPEC
 // slice's result is independent of the other slices). The epilogue separates
 // the two real spectra of every transform and writes, for every sample m of
 // each of the two projections, the group's slices' values side by side
-// (8 kPolarSlices contiguous bytes), so the polar rows come out interleaved
-// as the gather reads them:
-//   polar[((g V + j) S + lead + m) kPolarSlices + s mod kPolarSlices].
+// (8 Q contiguous bytes), so the polar rows come out interleaved as the
+// gather reads them: sample PolarTiles{Q, V, S}.sample(j, lead + m) of group g.
 // Slices of the last group past the batch read zeros.
 // MONO: monopole subtraction, y[i] - m phi[i] (m from the partial sums).
-// Q: slices per polar group (kPolarSlices for ordinary batches, 1 for the
-// persistent launches of uneven batches). Block (bx, g): pair blocks bx of
-// group g.
+// Q: slices per polar group (kPolarSlices for ordinary batches with linear
+// taps, 1 with cubic taps and in the persistent launches of uneven batches).
+// Block (bx, g): pair blocks bx of group g.
 template <int LOGM, int LOGP, bool COUNTS, bool MONO, int Q>
 __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int bx, int g) {
     using C = SpecCfg<LOGM, Q>;

@@ -9,7 +9,8 @@
 // interleaving of ordinary batches pairs equal angle sets, which instances of
 // different V do not have). Per stage and class, one persistent kernel walks
 // a device work list of (slice, tile) items, every item carrying its slice's
-// own V (angle directions j pi / V formed on the fly): spectrum (P1-P4),
+// own V (the gather reads its angle directions j pi / V from a per-slice
+// table built on the host in FP64): spectrum (P1-P4),
 // gather + column inverse FFT (P5-P6) and row C2R (P6-P8), plus a sinogram-sum
 // kernel with monopole subtraction. Kernels read the instances' sinograms and
 // write their images through per-slice pointer lists, so instances need not
@@ -24,6 +25,7 @@
 // batches keep classes of equal (n, V) run by the ordinary kernels (through
 // the same pointer lists), one class per pair.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <new>
@@ -49,6 +51,8 @@ struct SizeClass {
     size_t polar_off = 0, dc_off = 0, grid_off = 0, mass_off = 0;
     // device arrays (inside the batch's table block): V per slice, work lists
     int* d_V = nullptr;
+    int* d_ang_off = nullptr;      // slice i's directions at d_ang + d_ang_off[i]
+    const double2* d_ang = nullptr;
     int2* d_items[kStages] = {};
     int n_items[kStages] = {};
     int row_tiles = 1;         // row tiles per item of the row stage (tuned)
@@ -239,6 +243,8 @@ hipError_t launch_class(const bst_batch_s* b, const SizeClass& c, void* ws, hipS
     ga.rscale = p.rscale;
     ga.dc_rule = p.dc_scale * (float)p.V;  // the plan's per-projection factor times its V
     ga.Vs = c.d_V;
+    ga.ang = c.d_ang;
+    ga.ang_off = c.d_ang_off;
     ga.items = c.d_items[1];
     ga.n_items = c.n_items[1];
     e = bst::launch_gather_items(p, ga, c.blocks[1], st);
@@ -365,12 +371,23 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
         c.blocks[2] = grid_blocks(b, c.n_items[2], 2);
     }
     b->ws_total = off;
-    // one device block: per class its V list, then its three work lists
+    // one device block: per class its V list, the offsets of its slices'
+    // direction tables, the tables ((cos, sin) of j pi / V_i, in FP64 as for
+    // a plan), then its three work lists
+    auto up16 = [](size_t x) { return (x + 15) / 16 * 16; };
     size_t tbytes = 0;
-    std::vector<size_t> v_off(b->classes.size()), i_off(b->classes.size() * kStages);
+    std::vector<size_t> v_off(b->classes.size()), a_off(b->classes.size()), d_off(b->classes.size()),
+        i_off(b->classes.size() * kStages);
     for (size_t k = 0; k < b->classes.size(); ++k) {
+        const SizeClass& c = b->classes[k];
         v_off[k] = tbytes;
-        tbytes += ((b->classes[k].members.size() * sizeof(int) + 15) / 16) * 16;
+        tbytes += up16(c.members.size() * sizeof(int));
+        a_off[k] = tbytes;
+        tbytes += up16(c.members.size() * sizeof(int));
+        d_off[k] = tbytes;
+        size_t dirs = 0;
+        for (int V : c.Vs) dirs += (size_t)V;
+        tbytes += dirs * sizeof(double2);
         for (int s = 0; s < kStages; ++s) {
             i_off[k * kStages + s] = tbytes;
             tbytes += std::max<size_t>(items[k * kStages + s].size(), 1) * sizeof(int2);
@@ -379,9 +396,17 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
     std::vector<unsigned char> host(tbytes, 0);
     for (size_t k = 0; k < b->classes.size(); ++k) {
         const SizeClass& c = b->classes[k];
+        int first = 0;  // direction-table offset of slice i, in entries
         for (size_t i = 0; i < c.members.size(); ++i) {
             const int V = n_angles[c.members[i]];
             std::memcpy(host.data() + v_off[k] + i * sizeof(int), &V, sizeof(int));
+            std::memcpy(host.data() + a_off[k] + i * sizeof(int), &first, sizeof(int));
+            for (int j = 0; j < V; ++j) {
+                const double th = (double)j * M_PI / (double)V;
+                const double2 d = make_double2(std::cos(th), std::sin(th));
+                std::memcpy(host.data() + d_off[k] + (size_t)(first + j) * sizeof(double2), &d, sizeof(double2));
+            }
+            first += V;
         }
         for (int s = 0; s < kStages; ++s) {
             const auto& l = items[k * kStages + s];
@@ -406,6 +431,8 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
     for (size_t k = 0; k < b->classes.size(); ++k) {
         SizeClass& c = b->classes[k];
         c.d_V = reinterpret_cast<int*>(tb + v_off[k]);
+        c.d_ang_off = reinterpret_cast<int*>(tb + a_off[k]);
+        c.d_ang = reinterpret_cast<const double2*>(tb + d_off[k]);
         for (int s = 0; s < kStages; ++s) c.d_items[s] = reinterpret_cast<int2*>(tb + i_off[k * kStages + s]);
     }
     b->d_sino_list = static_cast<const float**>(b->d_lists);

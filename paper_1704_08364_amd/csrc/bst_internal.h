@@ -222,9 +222,12 @@ struct GatherArgs {
     int tent_w;
     // uneven batches: per-slice projection counts (nullptr: V for all; else
     // V is the layout's row count), the origin rule's factor (dc_scale =
-    // dc_rule / V of the slice; angles then come from sincospi, ang unused)
-    // and the work list of a persistent launch ((slice, column block) per item)
+    // dc_rule / V of the slice), the slices' direction tables (slice s's
+    // (cos, sin) of j pi / V_s at ang + ang_off[s]; ang_off nullptr: formed
+    // with sincospi) and the work list of a persistent launch ((slice, column
+    // block) per item)
     const int* Vs;
+    const int* ang_off;
     float dc_rule;
     const int2* items;
     int n_items;

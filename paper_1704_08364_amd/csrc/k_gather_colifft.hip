@@ -135,7 +135,8 @@ constexpr unsigned kOffsetMask = 0x7FFFFFFFu;
 constexpr unsigned kSampleMask = 0x1FFFFFFFu;  // o0 without its flag bits
 
 // Angles of a slice: the plan's table, or (uneven batches, a count per
-// slice) j pi / V formed on the fly; V / pi in FP32.
+// slice) the slice's own table of j pi / V, else j pi / V formed with
+// sincospi; V / pi in FP32.
 struct AngleView {
     int V;
     float vpi_f;
@@ -328,7 +329,8 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
     const int j = threadIdx.x / F;
     const int col = lblock * F + fid;
     const int V = a.Vs ? a.Vs[s_begin] : a.V;  // this chunk's projections
-    const AngleView av{V, a.Vs ? (float)((double)V / M_PI) : a.vpi_f, a.Vs ? nullptr : a.ang};
+    const double2* ang = a.Vs ? (a.ang_off ? a.ang + a.ang_off[s_begin] : nullptr) : a.ang;
+    const AngleView av{V, a.Vs ? (float)((double)V / M_PI) : a.vpi_f, ang};
     const float dc_scale = a.Vs ? a.dc_rule / (float)V : a.dc_scale;
     const bool live = col < G / 2;
     const FftTwiddles<LOGG, +1, E> tw(j, a.tw);

@@ -59,6 +59,26 @@ def algorithmic_bytes(B: int, n: int, V: int, N: int, M: int, G: int) -> dict:
     }
 
 
+def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of a plain
+    torch copy of nbytes, median of reps: the practical ceiling of a streaming
+    kernel, reported beside the 8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2 * nbytes / sorted(ts)[len(ts) // 2]
+
+
 def measured_traffic(kernel: str, config_key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -375,6 +395,7 @@ def main():
         torch.empty_like(src).copy_(src)
         torch.cuda.synchronize()
         del src
+    copy_gbs = copy_bandwidth(dev) / 1e9
     log(f"generating {B} sinograms {V}x{n} on the GPU ...")
     if args.input == "random":
         gen = torch.Generator(device=dev)
@@ -523,7 +544,7 @@ def main():
                 "host_cpus": os.cpu_count()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic, "device_copy_GBps": round(copy_gbs, 1)},
         "kernels": kernels,
         "bruteforce": bf,
         "accuracy": accuracy,

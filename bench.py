@@ -227,7 +227,8 @@ def volume_workload(args):
     torch.cuda.synchronize()
     log(f"  {time.perf_counter() - t0:.1f} s")
     img = torch.empty(S, N, N, dtype=torch.float32, device=dev)
-    plan = P.Plan(n, V, max_batch=Bt)
+    kw = dict(taper="keys", interp="keys") if args.interp == "keys" else {}
+    plan = P.Plan(n, V, max_batch=Bt, pad_radial=args.pad_radial, pad_cart=args.pad_cart, **kw)
     ws = plan.workspace(Bt)
     for b0 in range(0, min(S, Bt * args.warmup), Bt):
         plan.backproject(sino[b0:b0 + Bt], out=img[b0:b0 + Bt], workspace=ws)
@@ -240,13 +241,15 @@ def volume_workload(args):
     out = {"metric": "BST FBP of a full volume", "value": round(S / el, 2), "unit": "slices/s",
            "seconds": round(el, 4), "n_gpus": 1, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{S} slices x {V} angles x {n} bins, 30-ellipsoid phantom, "
-                                  f"Poisson-like noise 1e5 photons, batches of {Bt}", "slices": S}}
+                                  f"Poisson-like noise 1e5 photons, batches of {Bt}", "slices": S,
+                      "interp": args.interp, "pad_radial": args.pad_radial, "pad_cart": args.pad_cart}}
     if args.cpu_slices > 0:
         from oracle import bst as obst
         from oracle.geometry import Geometry
         errs = []
         for k in (S // 3, S // 2):
-            ref = obst.backproject(sino[k].double().cpu().numpy(), Geometry(n, V, N), obst.Params())
+            prm = obst.Params(args.pad_radial, args.pad_cart, **kw)
+            ref = obst.backproject(sino[k].double().cpu().numpy(), Geometry(n, V, N), prm)
             errs.append(float(np.linalg.norm(img[k].double().cpu().numpy() - ref) / np.linalg.norm(ref)))
         out["parity"] = {"slices_checked": 2, "max_rel_l2_vs_fp64_oracle": max(errs)}
     print(json.dumps(out), flush=True)

@@ -47,10 +47,16 @@
 
 namespace bst {
 
-// threads per block of the gather kernel (the columns per block follow from it)
+// Threads per block of the gather kernel (the columns per block follow from
+// it): 1024 for transforms of 4096 points and more (two columns of 4096; two
+// 512-thread blocks of one column each per compute unit measured 14 % slower,
+// their footprints no longer shared), 512 below (two blocks per compute
+// unit, one transforming while the other gathers: 7-21 % faster at G = 1024
+// and 2048 than one 1024-thread block).
 #ifndef BST_GATHER_THREADS
-#define BST_GATHER_THREADS 1024
+#define BST_GATHER_THREADS 0
 #endif
+constexpr int gather_threads(int G) { return BST_GATHER_THREADS ? BST_GATHER_THREADS : (G >= 4096 ? 1024 : 512); }
 
 // waves per SIMD the register allocation must leave room for
 #ifndef BST_GATHER_WAVES
@@ -73,13 +79,13 @@ __device__ __forceinline__ float4 load16(__amdgpu_buffer_rsrc_t r, unsigned off)
     return make_float4(__uint_as_float(q[0]), __uint_as_float(q[1]), __uint_as_float(q[2]), __uint_as_float(q[3]));
 }
 
-template <int LOGG, int QV = kPolarSlices>
+template <int LOGG, int QV = kPolarSlices, int CAPT = 0>
 struct GatherCfg {
     static constexpr int G = 1 << LOGG;
     static constexpr int Q = QV;                         // slices per polar group
     static constexpr int E = Q == 4 ? 16 : 8;            // points (values) per thread
     static constexpr int T = G / E;
-    static constexpr int CAP = Q == 4 ? 512 : BST_GATHER_THREADS;
+    static constexpr int CAP = Q == 4 ? 512 : (CAPT ? CAPT : gather_threads(G));
     static constexpr int WAVES = Q == 4 ? 2 : BST_GATHER_WAVES;  // per SIMD, for the registers
     static constexpr int MAXT = CAP > T ? CAP : T;
     static constexpr int FL = 16384 / G;                 // LDS: two regions of about 70 KB
@@ -317,9 +323,9 @@ __device__ __forceinline__ void radial_row(const float4 (&q)[TAPS * Q / 2], floa
 // One block's work: columns lblock * F .. + F - 1 for the slices
 // [s_begin, s_end) (whole groups of Q). The slices share one angle set: the
 // plan's, or (per-slice counts) that of slice s_begin.
-template <int LOGG, int TAPS, bool NU, bool TENT, int Q>
+template <int LOGG, int TAPS, bool NU, bool TENT, int Q, int CAPT = 0>
 __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int s_begin, int s_end) {
-    using C = GatherCfg<LOGG, Q>;
+    using C = GatherCfg<LOGG, Q, CAPT>;
     constexpr int G = C::G, T = C::T, F = C::F, E = C::E;
     constexpr unsigned kSampleBytes = Q * sizeof(float2);
     constexpr bool TILED = Q == 2 && TAPS == 2;  // the 2 x 4 x 2 tiles of PolarTiles
@@ -525,17 +531,20 @@ __attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG, polar_group(TAPS)>::WAVES, 8)
 // Persistent launch of uneven batches (one slice per group, uniform angles):
 // every block walks the work list (slice, column block) in steps of the grid,
 // the blocks of one XCD taking contiguous items (the neighbouring columns of
-// one slice, which read the same polar lines).
+// one slice, which read the same polar lines). Blocks of 1024 threads at
+// every length: the classes' persistent kernels run side by side, and
+// 512-thread blocks measured slower there.
+constexpr int kItemsThreads = 1024;
 template <int LOGG, int TAPS>
-__global__ void __launch_bounds__((GatherCfg<LOGG, 1>::WG))
-__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG, 1>::WAVES, 8))) k_gather_items(GatherArgs a) {
+__global__ void __launch_bounds__((GatherCfg<LOGG, 1, kItemsThreads>::WG))
+__attribute__((amdgpu_waves_per_eu(GatherCfg<LOGG, 1, kItemsThreads>::WAVES, 8))) k_gather_items(GatherArgs a) {
     const int local = xcd_contiguous(blockIdx.x, gridDim.x);
     for (int base = 0; base < a.n_items; base += gridDim.x) {
         const int it = base + local;
         if (it >= a.n_items) break;
         const int2 w = a.items[it];
         __syncthreads();  // the previous item's LDS reads are done
-        gather_body<LOGG, TAPS, false, false, 1>(a, w.y, w.x, w.x + 1);
+        gather_body<LOGG, TAPS, false, false, 1, kItemsThreads>(a, w.y, w.x, w.x + 1);
     }
 }
 
@@ -713,7 +722,7 @@ hipError_t launch_tent(const bst_plan_s& p, const TentArgs& a, int batch, hipStr
 
 template <int LOGG>
 static hipError_t launch_gather_items_t(const GatherArgs& a, int taps, int blocks, hipStream_t st) {
-    using C = GatherCfg<LOGG, 1>;
+    using C = GatherCfg<LOGG, 1, kItemsThreads>;
     if (taps == 4) hipLaunchKernelGGL((k_gather_items<LOGG, 4>), dim3(blocks), dim3(C::WG), 0, st, a);
     else hipLaunchKernelGGL((k_gather_items<LOGG, 2>), dim3(blocks), dim3(C::WG), 0, st, a);
     return hipGetLastError();
@@ -738,7 +747,7 @@ hipError_t launch_gather_items(const bst_plan_s& p, const GatherArgs& a, int blo
 
 template <int LOGG>
 static int gather_cols_t() {
-    using C = GatherCfg<LOGG, 1>;
+    using C = GatherCfg<LOGG, 1, kItemsThreads>;
     return (C::G / 2 + C::F - 1) / C::F;
 }
 

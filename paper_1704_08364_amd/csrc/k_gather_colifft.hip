@@ -9,16 +9,23 @@
 // angle row, consecutive radii). Columns go to XCDs in contiguous ranges so
 // neighbouring columns share an L2.
 //
-// The polar spectra of kPolarSlices (Q = 2 or 4) consecutive slices are
-// stored interleaved, sample by sample, so one tap of one point reads the Q
-// slices' values of two radial samples as 16 Q contiguous bytes: the lines a
-// wave touches serve Q slices instead of one (simulated over the 2048 x 4096
-// gather points of N = 2048 with two columns per block: 9.9 (Q = 2) or 6.6
-// (Q = 4) instead of 16.4 distinct 128-byte lines per wave and slice). A
-// block therefore gathers Q slices at a time. Their column transforms run
-// one after the other; two of the gathered columns wait in LDS (two
-// transform regions), with Q = 4 the other two in registers (E = 16 points
-// per thread and 512-thread blocks, for the registers).
+// With linear radial taps the polar spectra of Q = 2 consecutive slices are
+// stored interleaved, sample by sample, in cache-line tiles of 2 angles x 4
+// samples (PolarTiles): one tap of one point reads both slices' values of a
+// sample as 16 contiguous bytes, and the four samples of a point's two angle
+// rows mostly share one or two lines (simulated over the 2048 x 4096 gather
+// points of N = 2048 with two columns per block: 7.9 distinct 128-byte lines
+// per wave and slice, against 9.9 for interleaved rows and 16.4 for one
+// slice per row). A block therefore gathers both slices of a group at once;
+// their column transforms run one after the other, each gathered column
+// waiting in its own LDS region. Cubic taps keep one slice per group in plain
+// rows (Q = 1), and uneven batches too (their slices differ in V). Q = 4 (a
+// build option) holds the third and fourth columns in registers (16 points
+// per thread, 512-thread blocks).
+//
+// Blocks have 1024 threads for transforms of 4096 points or more and 512
+// below, where two blocks share a compute unit and one block's transforms
+// overlap the other's polar reads (gather_threads).
 //
 // Each thread keeps the interpolation coordinates of its E points in
 // three registers each and reuses them for every slice of its chunk. They
@@ -413,7 +420,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
                 dcv[k] = block_sum<C::WG>(acc, red) * dc_scale;
             }
         }
-        // gather: slices 0 and 1 of the group wait in the two LDS regions,
+        // gather: slices 0 and 1 of the group wait in the LDS regions,
         // slices 2 and 3 (Q = 4) in registers
         constexpr int NH = Q > 2 ? E : 1;
         float2 hold0[NH], hold1[NH];

@@ -179,47 +179,49 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
     }
 }
 
-// Transposed gather: one thread per polar sample and group of kProjInterleave
-// slices sums the sample's list of Cartesian points (weights and conjugation
-// flags from the plan), in list order. A block takes a tile of
-// kProjTileAngles x kProjTileRadii samples, and the tiles, radius-fastest,
-// are spread XCD-contiguously: the samples of neighbouring angles and radii
-// share stencil points, so a tile and its successors on one XCD find them in
-// that XCD's L2.
+// Transposed gather: each polar sample and group of kProjInterleave slices
+// sums the sample's list of Cartesian points (weights and conjugation flags
+// from the plan), in list order. Eight lanes share a sample, each summing two
+// of the group's slices, so that one 16-byte read per lane covers a list
+// entry's whole 128-byte line (the interleaved slices of one Cartesian point)
+// and every read of a wave is a full line. A block of 256 threads takes a
+// tile of kProjTileAngles x kProjTileRadii samples, 32 at a time, and the
+// tiles, radius-fastest, are spread XCD-contiguously: the samples of
+// neighbouring angles and radii share stencil points, so a tile and its
+// successors on one XCD find them in that XCD's L2.
 constexpr int kProjTileAngles = 16, kProjTileRadii = 16;
-__global__ void __launch_bounds__(kProjTileAngles * kProjTileRadii) k_proj_gather(ProjGatherArgs a) {
+constexpr int kProjLanes = kProjInterleave / 2;  // lanes per sample, two slices each
+constexpr int kProjGatherThreads = 256;
+__global__ void __launch_bounds__(kProjGatherThreads) k_proj_gather(ProjGatherArgs a) {
     const int tiles_m = (a.half_m + kProjTileRadii - 1) / kProjTileRadii;
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int m = (tile % tiles_m) * kProjTileRadii + threadIdx.x % kProjTileRadii;
-    const int j = (tile / tiles_m) * kProjTileAngles + threadIdx.x / kProjTileRadii;
-    if (m >= a.half_m || j * a.half_m >= a.samples) return;
-    const int idx = j * a.half_m + m;
-    const int s0 = blockIdx.y * kProjInterleave;
-    const int ns = min(kProjInterleave, a.batch - s0);
-    float2 acc[kProjInterleave];
-#pragma unroll
-    for (int k = 0; k < kProjInterleave; ++k) acc[k] = make_float2(0.f, 0.f);
-    const int e1 = a.off[idx + 1];
+    const int m_base = (tile % tiles_m) * kProjTileRadii;
+    const int j_base = (tile / tiles_m) * kProjTileAngles;
+    const int p = threadIdx.x % kProjLanes;  // this lane's slices: 2p, 2p + 1 of the group
+    const int sa = blockIdx.y * kProjInterleave + 2 * p, sb = sa + 1;
     const float4* base = reinterpret_cast<const float4*>(a.cart + (size_t)blockIdx.y * a.cart_stride * kProjInterleave);
-    for (int e = a.off[idx]; e < e1; ++e) {
-        const uint2 en = a.ent[e];
-        const size_t pidx = BST_IDX((size_t)(en.x & 0x7FFFFFFFu), (size_t)a.cart_stride, 0);
-        const float w = __uint_as_float(en.y);
-        const float wy = (en.x >> 31) != 0u ? -w : w;  // conjugation folded into the weight
-        float4 q[kProjInterleave / 2];
-#pragma unroll
-        for (int k = 0; k < kProjInterleave / 2; ++k) q[k] = base[pidx * (kProjInterleave / 2) + k];
-#pragma unroll
-        for (int k = 0; k < kProjInterleave / 2; ++k) {
-            acc[2 * k].x = fmaf(w, q[k].x, acc[2 * k].x);
-            acc[2 * k].y = fmaf(wy, q[k].y, acc[2 * k].y);
-            acc[2 * k + 1].x = fmaf(w, q[k].z, acc[2 * k + 1].x);
-            acc[2 * k + 1].y = fmaf(wy, q[k].w, acc[2 * k + 1].y);
+    constexpr int kPerRound = kProjGatherThreads / kProjLanes;
+    for (int r = threadIdx.x / kProjLanes; r < kProjTileAngles * kProjTileRadii; r += kPerRound) {
+        const int m = m_base + r % kProjTileRadii;
+        const int j = j_base + r / kProjTileRadii;
+        if (m >= a.half_m || j * a.half_m >= a.samples) continue;
+        const int idx = j * a.half_m + m;
+        float2 acc0 = make_float2(0.f, 0.f), acc1 = make_float2(0.f, 0.f);
+        const int e1 = a.off[idx + 1];
+        for (int e = a.off[idx]; e < e1; ++e) {
+            const uint2 en = a.ent[e];
+            const size_t pidx = BST_IDX((size_t)(en.x & 0x7FFFFFFFu), (size_t)a.cart_stride, 0);
+            const float w = __uint_as_float(en.y);
+            const float wy = (en.x >> 31) != 0u ? -w : w;  // conjugation folded into the weight
+            const float4 q = base[pidx * kProjLanes + p];
+            acc0.x = fmaf(w, q.x, acc0.x);
+            acc0.y = fmaf(wy, q.y, acc0.y);
+            acc1.x = fmaf(w, q.z, acc1.x);
+            acc1.y = fmaf(wy, q.w, acc1.y);
         }
+        if (sa < a.batch) a.polar[(size_t)sa * a.samples + idx] = acc0;
+        if (sb < a.batch) a.polar[(size_t)sb * a.samples + idx] = acc1;
     }
-#pragma unroll
-    for (int k = 0; k < kProjInterleave; ++k)
-        if (k < ns) a.polar[(size_t)(s0 + k) * a.samples + idx] = acc[k];
 }
 
 template <int LOGM>
@@ -347,7 +349,7 @@ hipError_t launch_proj_gather(const bst_plan_s& p, const ProjGatherArgs& a, hipS
     const int angles = a.samples / a.half_m;
     const int tiles = ((a.half_m + kProjTileRadii - 1) / kProjTileRadii) *
                       ((angles + kProjTileAngles - 1) / kProjTileAngles);
-    hipLaunchKernelGGL(k_proj_gather, dim3(tiles, groups), dim3(kProjTileAngles * kProjTileRadii), 0, st, a);
+    hipLaunchKernelGGL(k_proj_gather, dim3(tiles, groups), dim3(kProjGatherThreads), 0, st, a);
     return hipGetLastError();
 }
 

@@ -307,7 +307,9 @@ bst_status bst_debug_spectrum(bst_plan_t plan, const float* sino, void* spec, fl
  * bst_batch_backproject with a given workspace captures all launches into a
  * hipGraph; later calls only upload the pointer lists and replay it. Calls on
  * one batch must not overlap in time (they share the pointer lists). Results
- * equal bst_backproject's for each instance to rounding.
+ * equal bst_backproject's for each instance to rounding. bst_batch_create
+ * returns BST_E_BATCH for count < 1 or a size class whose instances have more
+ * than 2^31 - 1 angles in total.
  */
 typedef struct bst_batch_s* bst_batch_t;
 

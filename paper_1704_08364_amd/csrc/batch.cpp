@@ -26,6 +26,7 @@
 // the same pointer lists), one class per pair.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -387,6 +388,10 @@ bst_status bst_batch_create(const bst_params* base, int32_t count, const int32_t
         d_off[k] = tbytes;
         size_t dirs = 0;
         for (int V : c.Vs) dirs += (size_t)V;
+        if (dirs > (size_t)INT32_MAX) {  // the slices' table offsets are 32-bit
+            release(b);
+            return BST_E_BATCH;
+        }
         tbytes += dirs * sizeof(double2);
         for (int s = 0; s < kStages; ++s) {
             i_off[k * kStages + s] = tbytes;

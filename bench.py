@@ -149,6 +149,24 @@ def cpu_baseline(sino_cpu, out_gpu_cpu, n, V, N, slices, interp="linear", filter
     return slices / dt, dt, errs, workers
 
 
+def cpu_bruteforce_2048(sino_slice):
+    """s/slice of the FP64 oracle's brute-force backprojection (B_d of Eq. 2)
+    at 2048^2 from 2048 angles, one process, estimated from a band of 32 image
+    rows (1/64 of the slice; the cost is the same for every pixel)."""
+    import numpy as np
+
+    from oracle import bruteforce as obf
+    from oracle.geometry import Geometry
+
+    n = sino_slice.shape[1]
+    V = sino_slice.shape[0]
+    rows = np.repeat(np.arange(n // 2 - 16, n // 2 + 16), n)
+    cols = np.tile(np.arange(n), 32)
+    t0 = time.perf_counter()
+    obf.backproject_pixels(sino_slice, Geometry(n, V, n), rows, cols)
+    return round((time.perf_counter() - t0) * (n * n) / rows.size, 2)
+
+
 def cpu_small_case():
     """s/slice of the FP64 oracle's BST and brute-force backprojection (B_d of
     Eq. 2) at N = 256 (256 angles, one process): the single-slice case the
@@ -535,7 +553,8 @@ def main():
             cpu = {"value": round(rate, 4), "unit": "slices/s", "cores": workers, "kind": "oracle",
                    "sample": f"{s} of the {B} slices ({V}x{n} -> {N}^2), FP64 NumPy BST (the oracle as it "
                              f"stands), one slice per task over {workers} host processes, {dt:.1f} s",
-                   "cpu_model": _cpu_model(), "small_case": cpu_small_case()}
+                   "cpu_model": _cpu_model(), "small_case": cpu_small_case(),
+                   "bruteforce_fp64_s_per_slice": cpu_bruteforce_2048(sino_cpu[0])}
             parity = {"slices_checked": s, "max_rel_l2_vs_fp64_oracle": max(errs)}
             log(f"oracle: {rate:.4f} slices/s on {workers} processes; GPU vs oracle rel-L2 {max(errs):.2e}")
         except Exception as exc:  # a reported baseline, not the product: keep the benchmark line

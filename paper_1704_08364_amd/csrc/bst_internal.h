@@ -98,12 +98,8 @@ struct TentSizes {
     size_t W = 0, rowsV = 0, C = 0;
 };
 // slices whose polar spectra are stored interleaved (sample by sample): the
-// gather reads all of them with every tap (2 or 4)
-#ifndef BST_POLAR_SLICES
-#define BST_POLAR_SLICES 2
-#endif
-constexpr int kPolarSlices = BST_POLAR_SLICES;
-static_assert(kPolarSlices == 2 || kPolarSlices == 4, "2 or 4 interleaved slices");
+// gather reads both with every tap
+constexpr int kPolarSlices = 2;
 // Slices per polar group of an ordinary batch: cubic radial taps read four
 // samples per row, twice the bytes per slice, and run fastest one slice per
 // group (eight 16-byte reads per point otherwise pile up in flight).
@@ -113,8 +109,8 @@ constexpr int polar_group(int taps) { return taps == 4 ? 1 : kPolarSlices; }
 // Q = 2: tiles of 2 angles x 4 slots x 2 slices (128 bytes, one cache line),
 // ceil(V/2) rows of ceil(S/4) tiles. The four samples (j0, m0..m0+1) x (j0+1,
 // m0..m0+1) a linear-tap point reads mostly fall into one or two such lines,
-// where rows of single angles spread them over two to four. Other Q: rows
-// [V][S] of Q-slice samples.
+// where rows of single angles spread them over two to four. Q = 1: rows
+// [V][S] of single samples.
 struct PolarTiles {
     int Q, V, S;
     __host__ __device__ int tiles_per_row() const { return (S + 3) >> 2; }

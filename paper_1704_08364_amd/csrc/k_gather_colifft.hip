@@ -19,9 +19,7 @@
 // slice per row). A block therefore gathers both slices of a group at once;
 // their column transforms run one after the other, each gathered column
 // waiting in its own LDS region. Cubic taps keep one slice per group in plain
-// rows (Q = 1), and uneven batches too (their slices differ in V). Q = 4 (a
-// build option) holds the third and fourth columns in registers (16 points
-// per thread, 512-thread blocks).
+// rows (Q = 1), and uneven batches too (their slices differ in V).
 //
 // Blocks have 1024 threads for transforms of 4096 points or more and 512
 // below, where two blocks share a compute unit and one block's transforms
@@ -90,10 +88,10 @@ template <int LOGG, int QV = kPolarSlices, int CAPT = 0>
 struct GatherCfg {
     static constexpr int G = 1 << LOGG;
     static constexpr int Q = QV;                         // slices per polar group
-    static constexpr int E = Q == 4 ? 16 : 8;            // points (values) per thread
+    static constexpr int E = 8;                          // points (values) per thread
     static constexpr int T = G / E;
-    static constexpr int CAP = Q == 4 ? 512 : (CAPT ? CAPT : gather_threads(G));
-    static constexpr int WAVES = Q == 4 ? 2 : BST_GATHER_WAVES;  // per SIMD, for the registers
+    static constexpr int CAP = CAPT ? CAPT : gather_threads(G);
+    static constexpr int WAVES = BST_GATHER_WAVES;       // per SIMD, for the registers
     static constexpr int MAXT = CAP > T ? CAP : T;
     static constexpr int FL = 16384 / G;                 // LDS: two regions of about 70 KB
     static constexpr int F1 = FL < G / 2 ? FL : G / 2;   // no more columns than exist
@@ -420,10 +418,7 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
                 dcv[k] = block_sum<C::WG>(acc, red) * dc_scale;
             }
         }
-        // gather: slices 0 and 1 of the group wait in the LDS regions,
-        // slices 2 and 3 (Q = 4) in registers
-        constexpr int NH = Q > 2 ? E : 1;
-        float2 hold0[NH], hold1[NH];
+        // gather: each slice of the group waits in its own LDS region
         constexpr int H = (TAPS == 2 && !NU && !TENT) ? BST_GATHER_INFLIGHT : BST_GATHER_INFLIGHT_OTHER;
         static_assert(E % H == 0, "whole groups of points");
 #pragma unroll
@@ -479,10 +474,6 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
                 }
                 R0[lds_pad(jv + e * T)] = val[0];
                 if constexpr (Q > 1) R1[lds_pad(jv + e * T)] = val[1];
-                if constexpr (Q > 2) {
-                    hold0[e] = val[2];
-                    hold1[e] = val[3];
-                }
             }
             asm volatile("" ::: "memory");
         }
@@ -490,25 +481,16 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
 
         // One transform per iteration, the loop kept rolled: unrolled, the
         // transforms share address arithmetic that then stays live across
-        // all of them and spills. Slices 0, 1 come from their LDS region,
-        // slices 2, 3 from registers (moved up one place per turn).
+        // all of them and spills. Each slice comes from its LDS region.
 #pragma unroll 1
         for (int k = 0; k < nq; ++k) {
             int jk = jv;
             asm volatile("" : "+v"(jk));
             float2* Rk = (k & 1) ? R1 : R0;
             float2 v[E];
-            if (k < 2) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) v[e] = Rk[lds_pad(jk + e * T)];
-                __syncthreads();  // every lane has its inputs before the first pass writes
-            } else if constexpr (Q > 2) {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    v[e] = hold0[e];
-                    hold0[e] = hold1[e];
-                }
-            }
+            for (int e = 0; e < E; ++e) v[e] = Rk[lds_pad(jk + e * T)];
+            __syncthreads();  // every lane has its inputs before the first pass writes
             FftTwiddles<LOGG, +1, E> twl = tw;
             twl.pin();
             fft<LOGG, +1, E>(v, Rk, jk, twl);

@@ -8,6 +8,27 @@
 // The Stockham auto-sort indexing (Govindaraju et al., SC'08) keeps every pass
 // in natural order, so no bit reversal is needed.
 //
+// LDS layout: element i of a transform sits at position lds_swz<E>(i), an XOR
+// swizzle (bits [0, B) of i XOR bits [B, 2B), bits [B, 2B) XOR bits [2B, 3B),
+// B = log2 of the main radix). It is a permutation of [0, L) that is linear
+// over the bits, so pos(a + b) = pos(a) ^ pos(b) when a and b share no set
+// bit: a butterfly's R outputs and a thread's E inputs are one per-thread
+// position XOR a compile-time constant. 8-byte LDS accesses on gfx950 are
+// served 32 lanes at a time over 32 eight-byte banks for reads and 16 lanes
+// at a time over 16 banks for writes (measured with SQ_LDS_BANK_CONFLICT);
+// under that model every read and every write of the passes below touches
+// distinct banks for the lengths the kernels use, where a plain i + i/16
+// padding costs two extra cycles on each contiguous read.
+//
+// A transform's region starts at a byte offset `off` of the block's LDS array
+// that is a multiple of 8 L, so the region and the position OR together and
+// the thread's byte offset of an element is one XOR with a constant (the
+// instruction's offset field takes the array's address): one VALU operation
+// per LDS access. The positions of a region are XOR-ed with a mask xm below L
+// that puts transforms sharing a wave on different banks: region_xor for
+// transforms interleaved lane by lane (thread t serves transform t mod F),
+// contiguous_xor for transforms on contiguous ranges of threads.
+//
 // Inter-pass twiddles: one value w = tw[(jj mod NS) * L/(NS R)] per butterfly
 // from a table tw[k] = exp(-2 pi i k / L) computed in FP64 on the host and
 // rounded to FP32; the other powers w^r are products of its squarings (at most
@@ -39,7 +60,49 @@ __device__ __forceinline__ float2 cmulc(float2 a, float c, float s) {
     return make_float2(fmaf(a.x, c, -a.y * sd), fmaf(a.x, sd, a.y * c));
 }
 
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+template <int E>
+__host__ __device__ constexpr int lds_swz(int i) {
+    constexpr int B = E >= 16 ? 4 : 3;
+    constexpr int M = (1 << B) - 1;
+    return i ^ ((i >> B) & M) ^ (((i >> (2 * B)) & M) << B);
+}
+
+// Byte offset of position p of the region at byte `off` with mask xm.
+__device__ __forceinline__ unsigned lds_byte(unsigned off, int p, int xm) {
+    return off | ((unsigned)(p ^ xm) << 3);
+}
+// The byte XOR of element offset c (no bit in common with the thread's part).
+template <int E>
+__host__ __device__ constexpr unsigned swz_bytes(int c) {
+    return (unsigned)lds_swz<E>(c) << 3;
+}
+// The float2 at byte offset b of the block's LDS array.
+__device__ __forceinline__ float2& lds_at(float2* lds, unsigned b) {
+    return *reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + b);
+}
+
+// Mask of transform f of F interleaved lane by lane, linear in the bits of f
+// (per-bit masks from the bank model; bits of f past the fourth reuse none).
+template <int LOGL, int F>
+__device__ __forceinline__ int region_xor(int f) {
+    int m = 0;
+    if constexpr (F == 2) {
+        m = f ? 24 : 0;
+    } else if constexpr (F == 4) {
+        m = ((f & 1) ? 8 : 0) ^ ((f & 2) ? 20 : 0);
+    } else if constexpr (F == 8) {
+        m = ((f & 1) ? 4 : 0) ^ ((f & 2) ? 8 : 0) ^ ((f & 4) ? 18 : 0);
+    } else if constexpr (F >= 16) {
+        m = ((f & 1) ? 16 : 0) ^ ((f & 2) ? 4 : 0) ^ ((f & 4) ? 6 : 0) ^ ((f & 8) ? 8 : 0);
+    }
+    return m & ((1 << LOGL) - 1);  // any mask below L keeps the region
+}
+// Mask of transform u of transforms on contiguous ranges of T threads: those
+// sharing a 32-lane half then sit on disjoint banks.
+template <int LOGL, int T>
+__device__ __forceinline__ int contiguous_xor(int u) {
+    return T >= 32 ? 0 : ((u * T) & 31 & ((1 << LOGL) - 1));
+}
 
 constexpr float kC1 = 0.92387953251128675613f;  // cos(pi/8)
 constexpr float kS1 = 0.38268343236508977173f;  // sin(pi/8)
@@ -111,7 +174,8 @@ __device__ __forceinline__ void dft(float2* v) {
 // writes output r to position (jj / NS) * NS * R + (jj mod NS) + r * NS.
 // anc[k]: the twiddle anchor of butterfly k, already conjugated for DIR > 0
 template <int L, int DIR, int R, int NS, int E>
-__device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j, const float2* anc) {
+__device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, unsigned off, int j, const float2* anc,
+                                              int xm) {
     constexpr int T = L / E;
     constexpr int BPT = E / R;
     constexpr bool LAST = (NS * R == L);
@@ -147,15 +211,16 @@ __device__ __forceinline__ void stockham_pass(float2 (&v)[E], float2* lds, int j
 #pragma unroll
             for (int r = 0; r < R; ++r) v[k + r * BPT] = x[r];
         } else {
-            const int base = (jj / NS) * NS * R + (jj & (NS - 1));
+            const unsigned pb = lds_byte(off, lds_swz<E>((jj / NS) * NS * R + (jj & (NS - 1))), xm);
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = x[r];
+            for (int r = 0; r < R; ++r) lds_at(lds, pb ^ swz_bytes<E>(r * NS)) = x[r];
         }
     }
     if constexpr (!LAST) {
         __syncthreads();
+        const unsigned pj = lds_byte(off, lds_swz<E>(j), xm);
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(j + e * T)];
+        for (int e = 0; e < E; ++e) v[e] = lds_at(lds, pj ^ swz_bytes<E>(e * T));
         __syncthreads();
     }
 }
@@ -208,37 +273,41 @@ struct FftTwiddles {
 };
 
 template <int LOGL, int DIR, int R, int NS, int E, int P>
-__device__ __forceinline__ void radix_passes(float2 (&v)[E], float2* lds, int j, const FftTwiddles<LOGL, DIR, E>& tw) {
+__device__ __forceinline__ void radix_passes(float2 (&v)[E], float2* lds, unsigned off, int j,
+                                             const FftTwiddles<LOGL, DIR, E>& tw, int xm) {
     constexpr int L = 1 << LOGL;
     if constexpr (NS < L) {
-        stockham_pass<L, DIR, R, NS, E>(v, lds, j, tw.w[P]);
-        radix_passes<LOGL, DIR, R, NS * R, E, (NS > 1 ? P + 1 : P)>(v, lds, j, tw);
+        stockham_pass<L, DIR, R, NS, E>(v, lds, off, j, tw.w[P], xm);
+        radix_passes<LOGL, DIR, R, NS * R, E, (NS > 1 ? P + 1 : P)>(v, lds, off, j, tw, xm);
     }
 }
 
 // Full transform of length 2^LOGL by L/E threads holding E (8, 16 or 32)
 // values each; passes are radix min(E, 16) after one smaller first pass when
-// needed. Requires every thread of the block to call it (barriers); `lds` must
-// hold lds_pad(L) float2 for this transform and not be read by anyone else
-// meanwhile. Ends with a barrier if any LDS exchange happened.
+// needed. Requires every thread of the block to call it (barriers); `lds` is
+// the block's LDS array, and the transform's region of L float2 at byte `off`
+// (a multiple of 8 L; positions lds_swz<E>(i) ^ xm) must not be read by
+// anyone else meanwhile. Ends with a barrier if any LDS exchange happened.
 template <int LOGL, int DIR, int E = 16>
-__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const FftTwiddles<LOGL, DIR, E>& tw) {
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, unsigned off, int j,
+                                    const FftTwiddles<LOGL, DIR, E>& tw, int xm) {
     static_assert(E == 8 || E == 16 || E == 32, "8, 16 or 32 values per thread");
     using TW = FftTwiddles<LOGL, DIR, E>;
     constexpr int L = 1 << LOGL;
     if constexpr (TW::REM != 0) {
-        stockham_pass<L, DIR, (1 << TW::REM), 1, E>(v, lds, j, tw.w[0]);
-        radix_passes<LOGL, DIR, TW::R, (1 << TW::REM), E, 0>(v, lds, j, tw);
+        stockham_pass<L, DIR, (1 << TW::REM), 1, E>(v, lds, off, j, tw.w[0], xm);
+        radix_passes<LOGL, DIR, TW::R, (1 << TW::REM), E, 0>(v, lds, off, j, tw, xm);
     } else {
-        radix_passes<LOGL, DIR, TW::R, 1, E, 0>(v, lds, j, tw);
+        radix_passes<LOGL, DIR, TW::R, 1, E, 0>(v, lds, off, j, tw, xm);
     }
 }
 
 // The same, reading the twiddle anchors from the table first.
 template <int LOGL, int DIR, int E = 16>
-__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int j, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, unsigned off, int j, const float2* __restrict__ tw,
+                                    int xm) {
     const FftTwiddles<LOGL, DIR, E> t(j, tw);
-    fft<LOGL, DIR, E>(v, lds, j, t);
+    fft<LOGL, DIR, E>(v, lds, off, j, t, xm);
 }
 
 // Blocks of a 1D grid are dispatched round-robin over the 8 XCDs of an
@@ -252,12 +321,5 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int nblocks) {
     const int x = bid % kXcd, k = bid / kXcd;
     return x * per + (x < rem ? x : rem) + k;
 }
-
-template <int LOGL>
-struct FftShape {
-    static constexpr int L = 1 << LOGL;
-    static constexpr int T = L / 16;                       // threads per transform
-    static constexpr int LDS = L + L / 16;                 // padded float2 per transform
-};
 
 }  // namespace bst

@@ -98,9 +98,9 @@ struct GatherCfg {
     static constexpr int F2 = MAXT / T;
     static constexpr int F = F1 < F2 ? F1 : F2;          // columns per block
     static constexpr int WG = F * T;
-    // transform stride in LDS: padded length plus 8 float2, so that F regions
-    // start 16 banks apart and lanes of different columns do not collide
-    static constexpr int STRIDE = FftShape<LOGG>::LDS + 8;
+    // transform stride in LDS (float2; a power of two, the columns' lanes
+    // interleaved and their positions told apart by region_xor)
+    static constexpr int STRIDE = G;
     static constexpr int REGION = F * STRIDE;            // one slice's F transforms
     static constexpr int NREG = Q < 2 ? Q : 2;           // LDS regions (parked slices)
 };
@@ -398,8 +398,10 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
     const unsigned tile_row_bytes = (unsigned)lay.tiles_per_row() * 128u;
     const unsigned tile_next = tile_row_bytes - 64u;
     const unsigned tile_wrap = 0u - (unsigned)((V - 1) >> 1) * tile_row_bytes - (unsigned)((V - 1) & 1) * 64u;
-    float2* R0 = lds + fid * C::STRIDE;
-    float2* R1 = R0 + (C::NREG - 1) * C::REGION;
+    // column fid's LDS regions: slice 0 of a group at byte off0, slice 1 at off1
+    const unsigned off0 = (unsigned)(fid * C::STRIDE) * 8u;
+    const unsigned off1 = off0 + (unsigned)((C::NREG - 1) * C::REGION) * 8u;
+    const int xm = region_xor<LOGG, F>(fid);
     for (int s0 = s_begin; s0 < s_end; s0 += Q) {
         const int nq = min(Q, s_end - s0);  // slices of this group in the batch
         // Re-derive the lane's row index each group: otherwise every address
@@ -407,6 +409,8 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
         // loop and held in registers, which spills.
         int jv = j;
         asm volatile("" : "+v"(jv));
+        const unsigned pj0 = lds_byte(off0, lds_swz<E>(jv), xm);  // the thread's first point
+        const unsigned pj1 = lds_byte(off1, lds_swz<E>(jv), xm);
         const __amdgpu_buffer_rsrc_t P = polar_rsrc(a.polar + (size_t)(s0 / Q) * lay.group_elems(), group_bytes);
         float dcv[Q];
         if (lblock == 0) {
@@ -472,8 +476,8 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
 #pragma unroll
                     for (int k = 0; k < Q; ++k) val[k] = make_float2(dcv[k], 0.f);
                 }
-                R0[lds_pad(jv + e * T)] = val[0];
-                if constexpr (Q > 1) R1[lds_pad(jv + e * T)] = val[1];
+                lds_at(lds, pj0 ^ swz_bytes<E>(e * T)) = val[0];
+                if constexpr (Q > 1) lds_at(lds, pj1 ^ swz_bytes<E>(e * T)) = val[1];
             }
             asm volatile("" ::: "memory");
         }
@@ -486,14 +490,15 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int lblock, int
         for (int k = 0; k < nq; ++k) {
             int jk = jv;
             asm volatile("" : "+v"(jk));
-            float2* Rk = (k & 1) ? R1 : R0;
+            const unsigned offk = (k & 1) ? off1 : off0;
+            const unsigned pk = lds_byte(offk, lds_swz<E>(jk), xm);
             float2 v[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = Rk[lds_pad(jk + e * T)];
+            for (int e = 0; e < E; ++e) v[e] = lds_at(lds, pk ^ swz_bytes<E>(e * T));
             __syncthreads();  // every lane has its inputs before the first pass writes
             FftTwiddles<LOGG, +1, E> twl = tw;
             twl.pin();
-            fft<LOGG, +1, E>(v, Rk, jk, twl);
+            fft<LOGG, +1, E>(v, lds, offk, jk, twl, xm);
             if (live) {
                 float2* D = a.grid + (size_t)(s0 + k) * a.N * a.GT;
 #pragma unroll

@@ -44,11 +44,11 @@ template <int LOGG>
 __global__ void __launch_bounds__(ProjRowCfg<LOGG>::WG) k_proj_rows(ProjRowArgs a) {
     using C = ProjRowCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
-    constexpr int STRIDE = FftShape<LOGG>::LDS + 8;  // regions 16 banks apart
-    __shared__ float2 lds[C::F * STRIDE];
+    __shared__ float2 lds[C::F * G];  // one region per row pair, the pairs' lanes interleaved
     const int fid = threadIdx.x % C::F;
     const int j = threadIdx.x / C::F;
-    float2* my = lds + fid * STRIDE;
+    const unsigned my_off = (unsigned)(fid * G) * 8u;
+    const int xm = region_xor<LOGG, C::F>(fid);
     const int row0 = blockIdx.x * (2 * C::F) + 2 * fid;
     const int s = blockIdx.y;
     const float* r0 = a.img + ((size_t)s * a.N + row0) * a.N;
@@ -71,9 +71,10 @@ __global__ void __launch_bounds__(ProjRowCfg<LOGG>::WG) k_proj_rows(ProjRowArgs 
         const int q = (j + e * T + half_n) & (G - 1);
         v[e] = q < a.N ? make_float2(x0[e], x1[e]) : make_float2(0.f, 0.f);
     }
-    fft<LOGG, -1>(v, my, j, a.tw);
+    fft<LOGG, -1>(v, lds, my_off, j, a.tw, xm);
+    const unsigned pj = lds_byte(my_off, lds_swz<16>(j), xm);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) my[lds_pad(j + e * T)] = v[e];
+    for (int e = 0; e < 16; ++e) lds_at(lds, pj ^ swz_bytes<16>(e * T)) = v[e];
     __syncthreads();
 
     float4* tile = reinterpret_cast<float4*>(a.grid + ((size_t)s * a.N + (size_t)(row0 >> 3) * 8) * (G / 2));
@@ -81,8 +82,8 @@ __global__ void __launch_bounds__(ProjRowCfg<LOGG>::WG) k_proj_rows(ProjRowArgs 
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int k = j + e * T;  // 0 .. G/2-1
-        const float2 z = my[lds_pad(k)];
-        const float2 zc = my[lds_pad((G - k) & (G - 1))];
+        const float2 z = lds_at(lds, lds_byte(my_off, lds_swz<16>(k), xm));
+        const float2 zc = lds_at(lds, lds_byte(my_off, lds_swz<16>((G - k) & (G - 1)), xm));
         const float c = (k == 0 ? 0.5f : 1.0f) * a.scale;  // dk^2 * c_a / 2
         tile[k * 4 + (sub >> 1)] = make_float4(c * (z.x + zc.x), c * (z.y - zc.y),
                                                c * (z.y + zc.y), -c * (z.x - zc.x));
@@ -102,7 +103,7 @@ struct ProjColCfg {
 // Column transform of one slot of the group (zeros past the batch).
 template <int LOGG>
 __device__ __forceinline__ void proj_col_transform(const ProjColArgs& a, int grp, int col, int slot, int j,
-                                                   float2* my, float2 (&v)[16]) {
+                                                   float2* lds, unsigned off, int xm, float2 (&v)[16]) {
     using C = ProjColCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
     const int s = grp * kProjInterleave + slot;
@@ -122,7 +123,7 @@ __device__ __forceinline__ void proj_col_transform(const ProjColArgs& a, int grp
         const int p = (j + e * T + half_n) & (G - 1);
         if (!(live && p < a.N)) v[e] = make_float2(0.f, 0.f);
     }
-    fft<LOGG, -1>(v, my, j, a.tw);
+    fft<LOGG, -1>(v, lds, off, j, a.tw, xm);
 }
 
 // One block per Cartesian column a and group of kProjInterleave slices: the
@@ -140,13 +141,14 @@ template <int LOGG>
 __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs a) {
     using C = ProjColCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
-    __shared__ float2 lds[C::SL * (FftShape<LOGG>::LDS + 8)];
+    __shared__ float2 lds[C::SL * G];  // one region per slice, the slices' lanes interleaved
     const int unit = xcd_contiguous(blockIdx.x, gridDim.x);
     if (unit >= a.units) return;  // whole block, before any barrier
     const int grp = unit / (G / 2), col = unit % (G / 2);
     const int fid = threadIdx.x % C::SL;
     const int j0 = threadIdx.x / C::SL;
-    float2* my = lds + fid * (FftShape<LOGG>::LDS + 8);
+    const unsigned my_off = (unsigned)(fid * G) * 8u;
+    const int xm = region_xor<LOGG, C::SL>(fid);
     float2* out = a.cart8 + ((size_t)grp * (G / 2) * G + (size_t)col * G) * kProjInterleave;
     if constexpr (C::ROUNDS >= 2) {
         // two rounds per pass: each thread transforms two adjacent slots and
@@ -159,9 +161,9 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
             asm volatile("" : "+v"(j));
             const int slot = r * C::SL + 2 * fid;
             float2 va[16], vb[16];
-            proj_col_transform<LOGG>(a, grp, col, slot, j, my, va);
+            proj_col_transform<LOGG>(a, grp, col, slot, j, lds, my_off, xm, va);
             __syncthreads();
-            proj_col_transform<LOGG>(a, grp, col, slot + 1, j, my, vb);
+            proj_col_transform<LOGG>(a, grp, col, slot + 1, j, lds, my_off, xm, vb);
             float4* o4 = reinterpret_cast<float4*>(out);
 #pragma unroll
             for (int e = 0; e < 16; ++e)
@@ -172,7 +174,7 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
     } else {
         const int slot = fid;
         float2 v[16];
-        proj_col_transform<LOGG>(a, grp, col, slot, j0, my, v);
+        proj_col_transform<LOGG>(a, grp, col, slot, j0, lds, my_off, xm, v);
 #pragma unroll
         for (int e = 0; e < 16; ++e)
             out[BST_IDX((size_t)(j0 + e * T) * kProjInterleave + slot, (size_t)G * kProjInterleave, 1)] = v[e];
@@ -236,10 +238,11 @@ template <int LOGM>
 __global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG) k_proj_polar(ProjPolarArgs a) {
     using C = ProjPolarCfg<LOGM>;
     constexpr int M = C::M, T = C::T;
-    __shared__ float2 lds[C::F * FftShape<LOGM>::LDS];
+    __shared__ float2 lds[C::F * M];
     const int fid = threadIdx.x / T;
     const int j = threadIdx.x - fid * T;
-    float2* my = lds + fid * FftShape<LOGM>::LDS;
+    const unsigned my_off = (unsigned)(fid * M) * 8u;  // this pair's LDS region
+    const int my_xm = contiguous_xor<LOGM, T>(fid);
     const int pair = blockIdx.x * C::F + fid;
     const int s = blockIdx.y;
     const int ja = 2 * pair, jb = 2 * pair + 1;
@@ -280,7 +283,7 @@ __global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG) k_proj_polar(ProjPolar
         if (k == M / 2 || !vb) hb = make_float2(0.f, 0.f);
         v[e] = make_float2(ha.x - hb.y, ha.y + hb.x);
     }
-    fft<LOGM, +1>(v, my, j, a.tw);
+    fft<LOGM, +1>(v, lds, my_off, j, a.tw, my_xm);
 
     const int h = a.n >> 1;
     float* oa = a.sino + ((size_t)s * a.V + ja) * a.n;

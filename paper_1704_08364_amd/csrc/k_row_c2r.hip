@@ -22,11 +22,6 @@ namespace bst {
 #define BST_ROW_TILES 16
 #endif
 
-// extra float2 between the LDS regions of a block's row pairs
-#ifndef BST_ROW_PAD
-#define BST_ROW_PAD 8
-#endif
-
 // row pairs per block for G <= 4096 (one 8-row tile is 4 pairs)
 #ifndef BST_ROW_PAIRS
 #define BST_ROW_PAIRS 4
@@ -49,15 +44,14 @@ template <int LOGG, bool MONO>
 __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int s) {
     using C = RowCfg<LOGG>;
     constexpr int G = C::G, T = C::T;
-    // regions 8 float2 (16 banks) apart, so interleaved lanes of different row
-    // pairs fall on different banks
-    constexpr int STRIDE = FftShape<LOGG>::LDS + BST_ROW_PAD;
-    __shared__ __attribute__((aligned(16))) float2 lds[C::F * STRIDE];
+    // one LDS region of G float2 per row pair, the pairs' lanes interleaved
+    __shared__ __attribute__((aligned(16))) float2 lds[C::F * G];
     // thread t serves row pair t mod F: the lanes of a wave read F neighbouring
     // 16-byte pairs of each k, i.e. contiguous runs of the [G/2][8] tile
     const int fid = threadIdx.x % C::F;
     const int j = threadIdx.x / C::F;
-    float2* my = lds + fid * STRIDE;
+    const unsigned my_off = (unsigned)(fid * G) * 8u;
+    const int xm = region_xor<LOGG, C::F>(fid);
     const int groups = a.N / (2 * C::F);             // row-pair groups (tiles) per slice
     const int g0 = bx * a.tiles;
     float* const img_s = a.img_list ? a.img_list[s] : a.img + (size_t)s * a.N * a.N;
@@ -112,7 +106,7 @@ __device__ __forceinline__ void row_body(const RowArgs& a, int bx, int s) {
 
         FftTwiddles<LOGG, +1, 16> twl = tw;
         twl.pin();
-        fft<LOGG, +1>(v, my, jv, twl);
+        fft<LOGG, +1>(v, lds, my_off, jv, twl, xm);
 
         if (grp < groups) {
             const int row0 = BST_IDX(grp * (2 * C::F) + 2 * fid, a.N - 1, 1);

@@ -132,11 +132,12 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
     constexpr int M = C::M, T = C::T, TP = C::TP;
     constexpr int E0 = 8 >> LOGP;
     constexpr int NQ = 2 * E0;  // data slots per thread
-    __shared__ float2 lds[Q * C::FP * FftShape<LOGM>::LDS];
+    __shared__ float2 lds[Q * C::FP * M];
     const int u = threadIdx.x / T;        // transform: pair u / Q, slice u % Q
     const int j = threadIdx.x - u * T;
     const int pl = u / Q, k = u % Q;
-    float2* my = lds + u * FftShape<LOGM>::LDS;
+    const unsigned my_off = (unsigned)(u * M) * 8u;  // this transform's LDS region
+    const int my_xm = contiguous_xor<LOGM, T>(u);
     const int s = g * Q + k;
     const bool vs = s < batch;
     const int h = a.n >> 1;
@@ -234,10 +235,11 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
         twl.pin();
         int jv = j;
         asm volatile("" : "+v"(jv));
-        fft<LOGM, -1>(v, my, jv, twl);
+        fft<LOGM, -1>(v, lds, my_off, jv, twl, my_xm);
 
+        const unsigned pj = lds_byte(my_off, lds_swz<16>(jv), my_xm);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) my[lds_pad(jv + e * T)] = v[e];
+        for (int e = 0; e < 16; ++e) lds_at(lds, pj ^ swz_bytes<16>(e * T)) = v[e];
         if (jv == 0) {
             if (va) a.dc[(size_t)s * a.V + BST_IDX(ja, a.V, 3)] = a.dt * v[0].x;
             if (vb) a.dc[(size_t)s * a.V + BST_IDX(jb, a.V, 3)] = a.dt * v[0].y;
@@ -247,7 +249,7 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
         // separate the two real spectra of every slice's transform and store
         // rows ja and jb with the group's slices interleaved
         const bool wa = ja < a.V, wb = jb < a.V;
-        const float2* z0 = lds + (Q * pl) * FftShape<LOGM>::LDS;
+
         const PolarTiles lay{Q, a.V, a.S};
         float2* grp = a.polar + (size_t)g * lay.group_elems();
         const int rja = wa ? ja : 0, rjb = wb ? jb : 0;
@@ -274,8 +276,11 @@ __device__ __forceinline__ void spectrum_body(const SpecArgs& a, int batch, int 
             float2 ya[Q], yb[Q];
 #pragma unroll
             for (int d = 0; d < Q; ++d) {
-                const float2* zt = z0 + d * FftShape<LOGM>::LDS;
-                const float2 z = zt[lds_pad(m)], zc = zt[lds_pad(mc)];
+                // slice d's transform of this pair
+                const unsigned zoff = (unsigned)((Q * pl + d) * M) * 8u;
+                const int zxm = contiguous_xor<LOGM, T>(Q * pl + d);
+                const float2 z = lds_at(lds, lds_byte(zoff, lds_swz<16>(m), zxm));
+                const float2 zc = lds_at(lds, lds_byte(zoff, lds_swz<16>(mc), zxm));
                 ya[d] = cmul(make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y - zc.y)), kc[i]);
                 yb[d] = cmul(make_float2(0.5f * (z.y + zc.y), -0.5f * (z.x - zc.x)), kc[i]);
             }

@@ -1,9 +1,10 @@
 // fft_lds.h -- in-register / LDS Stockham FFT used by every BST kernel.
 //
-// A transform of length L = 2^l is held by T = L/E threads (E = 16 or 32);
+// A transform of length L = 2^l is held by T = L/E threads (E = 8, 16 or 32);
 // thread j keeps the E values x[j + e*T], e = 0..E-1, in registers on entry and
-// X[j + e*T] on exit (natural order). Passes are radix 2^(l mod 4) first (if l is not a multiple
-// of 4) and then radix 16. Each pass computes its butterflies in registers;
+// X[j + e*T] on exit (natural order). With B = 3 for E = 8 and B = 4
+// otherwise, passes are radix 2^(l mod B) first (if l is not a multiple of B)
+// and then radix 2^B. Each pass computes its butterflies in registers;
 // between passes the values go through LDS once (write, barrier, read, barrier).
 // The Stockham auto-sort indexing (Govindaraju et al., SC'08) keeps every pass
 // in natural order, so no bit reversal is needed.
@@ -17,7 +18,8 @@
 // served 32 lanes at a time over 32 eight-byte banks for reads and 16 lanes
 // at a time over 16 banks for writes (measured with SQ_LDS_BANK_CONFLICT);
 // under that model every read and every write of the passes below touches
-// distinct banks for the lengths the kernels use, where a plain i + i/16
+// distinct banks at the lengths of 2048-bin slices (L = 2048 and 4096; a few
+// write conflicts remain at some shorter lengths), where a plain i + i/16
 // padding costs two extra cycles on each contiguous read.
 //
 // A transform's region starts at a byte offset `off` of the block's LDS array

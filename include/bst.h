@@ -148,9 +148,10 @@ typedef struct {
                                path (bst_backproject_f64 / bst_project_f64 only)        */
     int32_t gather_slices;  /* slices each block of the step-P5/P6 gather kernel handles
                                (its interpolation coordinates are computed once for
-                               them): 0 = the default (32), else a positive multiple
-                               of 2 up to 1024. Results do not depend on it (tuning
-                               and tests only)                                          */
+                               them): 0 = the default (32; 8 with cubic taps on
+                               Cartesian grids of G <= 2048), else a positive
+                               multiple of 2 up to 1024. Results do not depend on it
+                               (tuning and tests only)                                  */
 } bst_params;
 
 typedef enum {

@@ -10,9 +10,16 @@
 
 #include "bst_internal.h"
 
-// slices per gather block: the interpolation coordinates are computed once per block
+// slices per gather block: the interpolation coordinates are computed once per
+// block, so more slices amortise them; cubic taps on grids up to 2048 (one
+// slice per polar group, two blocks per compute unit) gain more from a grid of
+// more, shorter blocks (N = 2048 at P_c = 1: gather 1.37 ms with 32 slices,
+// 1.30 ms with 8)
 #ifndef BST_GATHER_SLICES
 #define BST_GATHER_SLICES 32
+#endif
+#ifndef BST_GATHER_SLICES_CUBIC_SMALL
+#define BST_GATHER_SLICES_CUBIC_SMALL 8
 #endif
 
 namespace bst {
@@ -334,7 +341,9 @@ bst_status bst_plan(const bst_params* p, bst_plan_t* out) {
     pl->out_scale = (float)(pl->dk * pl->dk);
     pl->device = p->device;
     pl->adjoint = (p->adjoint != 0);
-    pl->gather_slices = p->gather_slices > 0 ? p->gather_slices : BST_GATHER_SLICES;
+    pl->gather_slices = p->gather_slices > 0
+                            ? p->gather_slices
+                            : ((pl->taps == 4 && pl->G <= 2048) ? BST_GATHER_SLICES_CUBIC_SMALL : BST_GATHER_SLICES);
     pl->monopole = (p->monopole_width != 0.0);
     pl->tent = (p->angular == BST_ANGULAR_TENT);
     pl->f64 = (p->dtype == BST_F64);

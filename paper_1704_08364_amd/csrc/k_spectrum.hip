@@ -102,7 +102,9 @@ struct SpecCfg {
     static constexpr int M = 1 << LOGM;
     static constexpr int T = M / 16;                     // threads per transform
     static constexpr int TP = Q * T;                     // per projection pair: one transform per slice
-    static constexpr int FP = TP >= 512 ? 1 : 512 / TP;  // projection pairs per block
+    // projection pairs per block: blocks of at least 256 threads (one-slice
+    // groups at M = 4096: 0.665 ms in 512-thread blocks, 0.641 ms in 256)
+    static constexpr int FP = TP >= 256 ? 1 : 256 / TP;
     static constexpr int WG = FP * TP;
     static constexpr int MV = (M / 2) / TP;              // output samples per thread and pair
 };

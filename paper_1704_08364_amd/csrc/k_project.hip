@@ -194,6 +194,7 @@ __global__ void __launch_bounds__(ProjColCfg<LOGG>::WG) k_proj_cols(ProjColArgs 
 constexpr int kProjTileAngles = 16, kProjTileRadii = 16;
 constexpr int kProjLanes = kProjInterleave / 2;  // lanes per sample, two slices each
 constexpr int kProjGatherThreads = 256;
+constexpr int kProjBurst = 4;  // list entries whose reads are issued together
 __global__ void __launch_bounds__(kProjGatherThreads) k_proj_gather(ProjGatherArgs a) {
     const int tiles_m = (a.half_m + kProjTileRadii - 1) / kProjTileRadii;
     const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
@@ -210,16 +211,30 @@ __global__ void __launch_bounds__(kProjGatherThreads) k_proj_gather(ProjGatherAr
         const int idx = j * a.half_m + m;
         float2 acc0 = make_float2(0.f, 0.f), acc1 = make_float2(0.f, 0.f);
         const int e1 = a.off[idx + 1];
-        for (int e = a.off[idx]; e < e1; ++e) {
-            const uint2 en = a.ent[e];
-            const size_t pidx = BST_IDX((size_t)(en.x & 0x7FFFFFFFu), (size_t)a.cart_stride, 0);
-            const float w = __uint_as_float(en.y);
-            const float wy = (en.x >> 31) != 0u ? -w : w;  // conjugation folded into the weight
-            const float4 q = base[pidx * kProjLanes + p];
-            acc0.x = fmaf(w, q.x, acc0.x);
-            acc0.y = fmaf(wy, q.y, acc0.y);
-            acc1.x = fmaf(w, q.z, acc1.x);
-            acc1.y = fmaf(wy, q.w, acc1.y);
+        // the list kProjBurst entries at a time: all entry reads, then all
+        // their data reads, then the sums in list order (an entry past the
+        // end re-reads the last one and is not added)
+        for (int e = a.off[idx]; e < e1; e += kProjBurst) {
+            uint2 en[kProjBurst];
+#pragma unroll
+            for (int u = 0; u < kProjBurst; ++u) en[u] = a.ent[min(e + u, e1 - 1)];
+            float4 q[kProjBurst];
+#pragma unroll
+            for (int u = 0; u < kProjBurst; ++u) {
+                const size_t pidx = BST_IDX((size_t)(en[u].x & 0x7FFFFFFFu), (size_t)a.cart_stride, 0);
+                q[u] = base[pidx * kProjLanes + p];
+            }
+#pragma unroll
+            for (int u = 0; u < kProjBurst; ++u) {
+                if (e + u < e1) {
+                    const float w = __uint_as_float(en[u].y);
+                    const float wy = (en[u].x >> 31) != 0u ? -w : w;  // conjugation folded into the weight
+                    acc0.x = fmaf(w, q[u].x, acc0.x);
+                    acc0.y = fmaf(wy, q[u].y, acc0.y);
+                    acc1.x = fmaf(w, q[u].z, acc1.x);
+                    acc1.y = fmaf(wy, q[u].w, acc1.y);
+                }
+            }
         }
         if (sa < a.batch) a.polar[(size_t)sa * a.samples + idx] = acc0;
         if (sb < a.batch) a.polar[(size_t)sb * a.samples + idx] = acc1;

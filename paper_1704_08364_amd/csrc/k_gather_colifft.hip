@@ -212,7 +212,17 @@ __device__ __forceinline__ Stencil point_stencil(int col, int bs, const GatherAr
         const double2 cs = av.dir(j0);
         const double cross = (double)y * cs.x - (double)x * cs.y;
         const double dot = (double)x * cs.x + (double)y * cs.y;
-        f = atan2f((float)cross, (float)dot) * av.vpi_f;
+        // the angle from theta_j0 is about pi / V or less: for |tan| < 0.01
+        // atan t = t (1 - t^2 / 3) to far below FP32 rounding (the next
+        // term is t^5 / 5), which spares the per-point atan2 of every slice
+        // in uneven batches
+        const float cr = (float)cross, dt = (float)dot;
+        if (fabsf(cr) < 0.01f * dt) {
+            const float t = cr / dt;
+            f = t * fmaf(-t * t, 1.f / 3.f, 1.f) * av.vpi_f;
+        } else {
+            f = atan2f(cr, dt) * av.vpi_f;
+        }
         if (f < 0.f) {
             if (j0 > 0) { j0 -= 1; f += 1.f; } else { f = 0.f; }
         } else if (f >= 1.f) {

@@ -250,7 +250,8 @@ struct ProjPolarCfg {
 };
 
 template <int LOGM>
-__global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG) k_proj_polar(ProjPolarArgs a) {
+__global__ void __launch_bounds__(ProjPolarCfg<LOGM>::WG)
+__attribute__((amdgpu_waves_per_eu(4, 8))) k_proj_polar(ProjPolarArgs a) {
     using C = ProjPolarCfg<LOGM>;
     constexpr int M = C::M, T = C::T;
     __shared__ float2 lds[C::F * M];
